@@ -1,0 +1,189 @@
+"""Benchmark of the OASM matching path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input: ingest of a
+device-resident 64 MiB text (symbol mapping), the bit-parallel scan for 256
+patterns, ordering of the hit ends, hit-set recovery, the shadow-hit filter,
+and the copy-back of hit ends and occurrences.  Throughput is reported in
+GCUPS (pattern x text cells per second, cells = sum of pattern lengths x text
+bytes) over the whole step; the scan kernel's share is measured with HIP
+events on the library's stream and set against the integer-VALU roofline.
+
+    python bench.py [--steps K] [--warmup W] [--workload long|batched|tiny]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD x 16 lanes, 2.4 GHz -> int32 VALU lane-ops per second
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# int32 VALU instructions per 32-bit column word per text symbol in the scan's
+# inner loop (gfx950 ISA of the W=1 kernel: 10 fused logic/add/shift ops, two
+# popcounts and one compare; counted once and frozen here)
+OPS_PER_WORD_STEP = 14
+HBM_PEAK_GBPS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="long", choices=["long", "batched", "tiny"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--chunk", type=int, default=0, help="chunk bytes (0 = library default)")
+    ap.add_argument("--batched-streams", type=int, default=4096)
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("oasm_kernels.hip", "oasm_internal.h"):
+        with open(os.path.join(ROOT, "paper_1712_03560_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per scan launch from committed rocprofv3 PMC summaries, if
+    they were taken with the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"scan_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def make_workload(name: str, args):
+    from paper_1712_03560_amd import workloads as W
+
+    if name == "long":
+        return W.long_stream(), "long-stream: one 64 MiB ACGT text, 256 patterns m~U[16,32], K=3, 10,000 planted copies"
+    if name == "tiny":
+        return W.tiny(), "tiny: 100,000 ACGT symbols, 16 patterns m~U[8,16], K=2, 200 planted copies"
+    w = W.batched(n_streams=args.batched_streams)
+    return w, (f"batched: {len(w.streams)} streams log-uniform in [1 KiB, 1 MiB], Zipf(1.1) 20 letters, "
+               f"1024 patterns m~U[8,64], K=floor(m/10)")
+
+
+def cpu_baseline(w, target_s: float):
+    """The oracle (C, one thread per pattern) on a bounded prefix of the workload."""
+    import oracle
+
+    threads = min(16, os.cpu_count() or 1)
+    text = w.streams[0] if len(w.streams) == 1 else np.concatenate(w.streams[:64])
+    msum = sum(len(p) for p in w.patterns)
+    # calibrate on a small prefix, then size the sample to ~target_s
+    probe = min(text.size, 8192)
+    t0 = time.perf_counter()
+    oracle.run_pairs(w.patterns, w.ks, text[:probe], threads=threads)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    nbytes = int(min(text.size, max(probe, probe * target_s / dt)))
+    t0 = time.perf_counter()
+    oracle.run_pairs(w.patterns, w.ks, text[:nbytes], threads=threads)
+    dt = time.perf_counter() - t0
+    cells = msum * nbytes
+    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"first {nbytes} bytes of the stream x all {len(w.patterns)} patterns "
+                      f"(hit ends, hit set and filter), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode "
+              f"in this build", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1712_03560_amd import build as B
+
+    if not os.path.exists(B.LIB):
+        B.build()
+    from paper_1712_03560_amd import oasm
+
+    w, desc = make_workload(args.workload, args)
+    dev_streams = [torch.from_numpy(s).cuda() for s in w.streams]
+    torch.cuda.synchronize()
+    msum = sum(len(p) for p in w.patterns)
+    total_bytes = w.total_bytes
+    cells = msum * total_bytes
+    word_steps = sum((len(p) + 31) // 32 for p in w.patterns) * total_bytes
+
+    mt = oasm.Matcher(w.patterns, w.ks, no_raw=False, chunk_bytes=args.chunk)
+    sid = [0]
+
+    def step():
+        base = sid[0]
+        for i, t in enumerate(dev_streams):
+            mt.feed(base + i, t, last=True)
+        sid[0] += len(dev_streams)
+        mt.sync()
+        return mt.results()
+
+    for _ in range(args.warmup):
+        res = step()
+    torch.cuda.synchronize()
+    s0 = mt.stats()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s1 = mt.stats()
+    mt.destroy()
+
+    ms_per_step = elapsed / args.steps * 1e3
+    gcups = cells / (elapsed / args.steps) / 1e9
+    scan_ms = (s1["scan_ms"] - s0["scan_ms"]) / args.steps
+    launches = (s1["scan_launches"] - s0["scan_launches"]) / args.steps
+    ops = word_steps * OPS_PER_WORD_STEP
+    achieved = ops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else None
+    peak = VALU_PEAK_OPS / 1e12
+    traffic = traffic_from_profiles(args.workload)
+    line = {
+        "metric": "GCUPS (pattern x text cells/s), whole matching step, 1 MI355X",
+        "value": round(gcups, 1),
+        "unit": "GCUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": desc, "streams": len(w.streams), "patterns": len(w.patterns),
+                   "text_bytes": total_bytes, "cells": cells},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2) if achieved else None, "peak": round(peak, 2),
+                     "unit": "TOP/s", "frac": round(achieved / peak, 4) if achieved else None,
+                     "traffic": traffic, "kernel": "k_scan", "scan_ms_per_step": round(scan_ms, 3),
+                     "scan_launches_per_step": launches, "word_steps": word_steps,
+                     "ops_per_word_step": OPS_PER_WORD_STEP},
+        "scan_gcups": round(cells / (scan_ms * 1e-3) / 1e9, 1) if scan_ms > 0 else None,
+        "hits": {"hit_ends": int(res.raw.size), "occurrences": int(res.occ.size)},
+    }
+    if not args.no_cpu_baseline and args.workload != "batched":
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

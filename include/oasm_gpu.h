@@ -1,0 +1,216 @@
+/*
+ * oasm_gpu -- online approximate string matching on AMD Instinct MI355X.
+ *
+ * C ABI of the library.  It implements the hot path of OASM ("A novel
+ * algorithm for online inexact string matching and its FPGA
+ * implementation", Cinti, Bianchi, Martino, Rizzi, arXiv 1712.03560) for a
+ * dictionary of byte patterns against any number of byte streams:
+ *
+ *   1. the hit ends: every end position e of a stream where some substring
+ *      t[s..e] is within unit-cost Levenshtein distance K of a pattern
+ *      (Section 3, Eq. 1-2; the "Less Naive" scan of Section 5.1, whose
+ *      first DP row is all zeros so a match may start anywhere);
+ *   2. the hit set at those ends: every (start, length, k <= K) with
+ *      length in [l_p - K, l_p + K] (Eq. 2, the per-start distances the
+ *      paper's LEV CALC unit produces, Section 6.2);
+ *   3. the online shadow-hit filter: Alg. 1 (Section 4) with the priority
+ *      rules R1-R3 (Section 4.1) and the validation test Eq. 3 (Section 4.2),
+ *      run independently per (stream, pattern) pair, as in the paper's
+ *      multi-pattern system where every pattern has its own search unit
+ *      (Section 6.4).
+ *
+ * All arithmetic is integer and exact; the GPU results equal the plain
+ * dynamic-programming definition bit for bit.
+ *
+ * Conventions
+ *   - positions are 0-based absolute offsets in a stream (uint64);
+ *   - an end position is inclusive; an occurrence (start, len) covers
+ *     bytes start .. start+len-1 (the paper's t[i,l]);
+ *   - every byte value 0x00-0xFF is a symbol; equality is byte equality;
+ *   - a pattern has 1 <= len <= OASM_MAX_PATTERN_LEN and its threshold obeys
+ *     0 <= K < len (Section 6.3: the threshold is always lower than the
+ *     pattern length).
+ *
+ * Readings of the paper used by the filter (the paper's pseudo-code and its
+ * worked example disagree; the reading below reproduces the example):
+ *   - R2 "first encountered": of two overlapping hits of equal priority the
+ *     one whose last symbol arrives first wins; on equal ends the shorter
+ *     one wins (R3);
+ *   - an occurrence completes when its counter reaches its length;
+ *   - a lower-priority occurrence is accepted when r(k) - acc > l(k), with
+ *     acc the sum of the lengths already accepted in the same emission.
+ *
+ * Threading: calls on one context are serialised internally.  Different
+ * contexts are independent.  All device work runs on one HIP stream per
+ * context (the caller's, or one the library creates at default priority).
+ *
+ * Memory: the library owns the context, its device buffers and its result
+ * queues; the caller owns every input and output array passed in.
+ */
+#ifndef OASM_GPU_H
+#define OASM_GPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OASM_VERSION_MAJOR 0
+#define OASM_VERSION_MINOR 1
+
+/* Longest supported pattern (eight 32-bit words per pattern column). */
+#define OASM_MAX_PATTERN_LEN 256
+
+/* Status codes (negative = error). */
+typedef int32_t oasm_status;
+#define OASM_OK 0
+#define OASM_E_INVAL (-1)  /* bad argument: NULL pointer, len 0, K >= len ... */
+#define OASM_E_NOMEM (-2)  /* host or device allocation failed */
+#define OASM_E_AGAIN (-3)  /* device-memory budget exhausted: drain / sync, retry */
+#define OASM_E_CLOSED (-4) /* feed to a stream that was closed */
+#define OASM_E_DEVICE (-5) /* HIP error; the context is poisoned, only destroy is valid */
+
+/* Filtering rules. */
+#define OASM_RULES_NONE 0u  /* report hit ends (and the hit set) only */
+#define OASM_RULES_PAPER 1u /* Alg. 1 with R1-R3 and Eq. 3 as read above */
+
+/* Feed flags. */
+#define OASM_FEED_LAST 1u /* this feed ends the stream (as oasm_close_stream) */
+
+/* Configuration flags. */
+#define OASM_CFG_PLAIN 1u  /* one launch sequence per stream instead of one batched launch */
+#define OASM_CFG_KEEP_H 2u /* keep the hit set for draining with OASM_H (debugging) */
+#define OASM_CFG_NO_RAW 4u /* do not queue hit ends for draining (they are still computed) */
+
+/* Drain kinds. */
+#define OASM_RAW 0u      /* oasm_hit records: hit ends and their distance */
+#define OASM_FILTERED 1u /* oasm_occ records: the occurrence set S */
+#define OASM_H 2u        /* oasm_occ records: the hit set H (needs OASM_CFG_KEEP_H) */
+
+typedef struct oasm_ctx oasm_ctx;
+
+/* One dictionary entry: `len` bytes at `bytes` (copied by oasm_create). */
+typedef struct oasm_pattern {
+    const uint8_t *bytes;
+    uint32_t len;
+} oasm_pattern;
+
+/* A hit end: min over starts of lev(pattern, stream[s..end]) = dist <= K. */
+typedef struct oasm_hit {
+    uint64_t stream;
+    uint64_t end;
+    uint32_t pattern;
+    uint32_t dist;
+} oasm_hit;
+
+/* An occurrence (or, for OASM_H, a hit-set record): lev(pattern,
+ * stream[start .. start+len-1]) = k. */
+typedef struct oasm_occ {
+    uint64_t stream;
+    uint64_t start;
+    uint32_t pattern;
+    uint32_t len;
+    uint32_t k;
+    uint32_t reserved;
+} oasm_occ;
+
+typedef struct oasm_config {
+    uint32_t struct_size;        /* sizeof(oasm_config); set by oasm_config_init */
+    int32_t device;              /* HIP device ordinal; -1 = the current device */
+    void *hip_stream;            /* hipStream_t to run on; NULL = library-owned stream */
+    uint32_t chunk_bytes;        /* text bytes per scan work item; 0 = autotuned */
+    uint32_t flags;              /* OASM_CFG_* */
+    uint64_t device_mem_budget;  /* bytes of staged stream data allowed; 0 = unlimited */
+} oasm_config;
+
+/* Per-context counters (cumulative since create). */
+typedef struct oasm_stats {
+    uint64_t bytes_scanned;     /* stream bytes matched */
+    uint64_t word_steps;        /* 32-bit pattern-column words advanced by one symbol */
+    uint64_t cells;             /* pattern length x stream bytes, summed */
+    uint64_t raw_hits;          /* hit ends found */
+    uint64_t h_records;         /* hit-set records */
+    uint64_t occurrences;       /* filtered occurrences emitted */
+    uint64_t syncs;             /* matching steps run */
+    double scan_ms;             /* device time of the scan kernels (HIP events) */
+    double step_ms;             /* device time of whole steps (HIP events) */
+    uint64_t scan_launches;     /* scan kernel launches */
+} oasm_stats;
+
+/* Fill `cfg` with defaults (device -1, library stream, autotuned chunks). */
+oasm_status oasm_config_init(oasm_config *cfg);
+
+/*
+ * Create a matching context for `n` patterns.  `k` gives one threshold per
+ * pattern, or is NULL to use `k_all` for every pattern.  `rules` is
+ * OASM_RULES_PAPER or OASM_RULES_NONE.  `cfg` may be NULL (defaults).
+ * Errors: OASM_E_INVAL for n == 0, a NULL pattern, len == 0,
+ * len > OASM_MAX_PATTERN_LEN or K >= len; OASM_E_NOMEM; OASM_E_DEVICE.
+ * On success *out receives the context; on error *out is set to NULL.
+ */
+oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k, uint16_t k_all,
+                        uint32_t rules, const oasm_config *cfg, oasm_ctx **out);
+
+/*
+ * Append `n` host bytes to stream `stream_id` (created on first use).  The
+ * bytes are copied before the call returns.  Matching runs at the next
+ * oasm_sync.  Feeds to one stream are concatenated in call order.  With
+ * OASM_FEED_LAST the stream is closed after these bytes.
+ * Errors: OASM_E_INVAL (ctx NULL, bytes NULL with n > 0), OASM_E_CLOSED,
+ * OASM_E_AGAIN (device_mem_budget would be exceeded; sync and retry),
+ * OASM_E_NOMEM, OASM_E_DEVICE.
+ */
+oasm_status oasm_feed(oasm_ctx *ctx, uint64_t stream_id, const uint8_t *bytes, size_t n, uint32_t flags);
+
+/*
+ * As oasm_feed, for `n` bytes already in device memory at `dev`.  The read
+ * is ordered after the work already queued on `hip_stream` (a hipStream_t,
+ * or NULL for the null stream); the caller keeps `dev` alive and unchanged
+ * until the next oasm_sync returns.
+ */
+oasm_status oasm_feed_device(oasm_ctx *ctx, uint64_t stream_id, const void *dev, size_t n, void *hip_stream,
+                             uint32_t flags);
+
+/* Close a stream: the next oasm_sync finishes its filter (Alg. 1 run to the
+ * last byte).  Closing an unknown or already closed stream is OASM_E_INVAL. */
+oasm_status oasm_close_stream(oasm_ctx *ctx, uint64_t stream_id);
+
+/*
+ * Match everything fed since the last sync, over all streams (one batched
+ * launch sequence, or one per stream with OASM_CFG_PLAIN), wait for it and
+ * queue the results for draining.  Occurrences whose fate still depends on
+ * bytes not yet fed stay pending until a later sync (or the stream's close).
+ */
+oasm_status oasm_sync(oasm_ctx *ctx);
+
+/*
+ * Copy up to `cap` queued records of `kind` into `out` (an array of
+ * oasm_hit for OASM_RAW, of oasm_occ otherwise) and remove them from the
+ * queue.  *n_out receives the number copied; *more (may be NULL) is set to 1
+ * when records remain.  Within one sync, records are ordered by stream,
+ * then pattern, then position (end for OASM_RAW; emission order, which is
+ * start order, for OASM_FILTERED; start then length for OASM_H); syncs
+ * follow each other in call order.
+ */
+oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_t *n_out, int *more);
+
+/* Cumulative counters and device timings. */
+oasm_status oasm_get_stats(const oasm_ctx *ctx, oasm_stats *out);
+
+/* Free the context and everything it owns (NULL is a no-op).  Waits for
+ * the context's device work to finish. */
+void oasm_destroy(oasm_ctx *ctx);
+
+/* Message for the last error on this context (never NULL). */
+const char *oasm_last_error(const oasm_ctx *ctx);
+
+/* Name of a status code. */
+const char *oasm_status_str(oasm_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OASM_GPU_H */

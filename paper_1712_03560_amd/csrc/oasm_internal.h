@@ -1,0 +1,160 @@
+// Internal declarations shared by the host runtime (oasm_runtime.hip) and the
+// kernels (oasm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oasm {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kMaxW32 = 8;         // 32-bit words per pattern column (256 rows)
+constexpr int kMaxW64 = 4;         // 64-bit words per column in the recovery kernel
+constexpr uint8_t kNoHit = 0xFF;   // hit-set byte for "distance above K"
+
+// One scan work item's text: a run of class-mapped symbols of one stream.
+// The first `lookback` symbols only warm the column up (their ends belong to
+// the previous item); ends are reported for the remaining symbols.
+struct ChunkDesc {
+    const uint8_t *sym;     // first symbol to scan (4-byte aligned)
+    uint64_t abs_first;     // absolute stream position of sym[lookback]
+    uint32_t scan_len;      // symbols to scan, lookback included
+    uint32_t lookback;      // warm-up symbols
+    uint32_t cnt_base;      // counts index of (stream, pattern 0, this chunk)
+    uint32_t cnt_stride;    // counts distance between consecutive patterns
+};
+
+// A tile: up to 64*P patterns of one word count W, one slot per (lane, p).
+struct TileDesc {
+    uint32_t peq_off;       // offset (in uint32) of the tile's match-mask image
+    uint32_t slot_off;      // offset into the slot -> pattern table
+    uint32_t n_active;      // active slots (slot = lane * P + p)
+    uint32_t pad;
+};
+
+// Per-pattern metadata on the device.
+struct PatDesc {
+    uint32_t off;           // offset of the pattern bytes
+    uint16_t m;             // length
+    uint16_t k;             // threshold
+    uint32_t rpeq_off;      // offset (in uint64) of the reversed match masks
+    uint16_t w64;           // 64-bit words of the reversed masks
+    uint16_t pad;
+};
+
+// Step-local stream descriptor (index = step-local stream number).
+struct StreamDesc {
+    const uint8_t *sym;     // class-mapped symbols of the staging buffer
+    uint64_t base_abs;      // absolute position of sym[0]
+    uint64_t frontier;      // absolute end (exclusive) of the scanned bytes after this step
+    uint32_t closed;        // stream closes in this step
+    uint32_t slot;          // persistent stream slot
+};
+
+// A carried record: a hit end whose filter segment was still open.
+struct CarryRec {
+    uint64_t end_abs;
+    uint32_t pattern;
+    uint32_t stream_slot;
+    uint32_t rank;          // index inside its (stream, pattern) run
+    uint32_t run_len;       // records in the run
+    uint32_t dist;
+    uint32_t pad;
+};
+
+// Occurrence as produced by the filter.
+struct OccRec {
+    uint64_t start_abs;
+    uint32_t pattern;
+    uint32_t stream_local;
+    uint32_t len;
+    uint32_t k;
+};
+
+// ------------------------------------------------------------------ launchers
+// Each returns hipSuccess or the launch error.  All run on `st`.
+
+// K0: match masks.  For every pattern, the scan image (high placement,
+// wildcard rows below the pattern) into its tile, and the reversed masks
+// (low placement) for the recovery kernel.
+hipError_t launch_peq_build(const uint8_t *pat_bytes, const PatDesc *pats, uint32_t npat,
+                            const uint32_t *pat_tile, const uint32_t *pat_slot, const TileDesc *tiles,
+                            const uint32_t *tile_wp, const uint8_t *class_of, uint32_t nclass,
+                            uint32_t *peq_img, uint64_t *rpeq, hipStream_t st);
+
+// Map raw bytes to symbol classes: dst[i] = class_of[src[i]].
+hipError_t launch_map_symbols(const uint8_t *src, uint8_t *dst, uint64_t n, const uint8_t *class_of,
+                              hipStream_t st);
+
+// K1: the bit-parallel scan for one word-count class (W words, P patterns
+// per lane).  Grid: (ceil(nchunks / waves_per_block), ntiles).
+struct ScanArgs {
+    const ChunkDesc *chunks;
+    uint32_t nchunks;
+    const TileDesc *tiles;
+    uint32_t tile_first;     // first tile of this class
+    uint32_t ntiles;
+    const uint32_t *peq_img;
+    const uint32_t *slot_pat;  // slot -> pattern id
+    const PatDesc *pats;
+    uint32_t nclass;
+    uint32_t *item_rec;      // [nitems][cap] (slot << 24 | end offset)
+    uint32_t *item_cnt;      // [nitems]
+    uint32_t item_base;      // first item index of this class
+    uint32_t cap;
+    uint32_t *counts;        // per (stream, pattern, chunk slot)
+    uint32_t *max_cnt;       // atomic max of per-item counts
+};
+hipError_t launch_scan(int W, int P, const ScanArgs &a, int waves_per_block, bool peq_in_lds, hipStream_t st);
+bool scan_variant_exists(int W, int P);
+
+// Scatter scan records into (stream, pattern, end) order.
+hipError_t launch_scatter(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
+                          uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
+                          const uint32_t *item_cnt, uint32_t item_base, uint32_t cap, const uint32_t *offsets,
+                          const uint32_t *chunk_stream, uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end,
+                          uint8_t *r_flag, hipStream_t st);
+
+// Carried records: write their run counts, then place them after the scan.
+hipError_t launch_carry_counts(const CarryRec *carry, uint32_t ncarry, const uint32_t *slot_to_local,
+                               const uint32_t *stream_cnt_base, const uint32_t *stream_cnt_stride,
+                               uint32_t *counts, hipStream_t st);
+hipError_t launch_carry_place(const CarryRec *carry, const uint8_t *carry_hk, uint32_t ncarry, uint32_t hks,
+                              const uint32_t *slot_to_local, const uint32_t *stream_cnt_base,
+                              const uint32_t *stream_cnt_stride, const uint32_t *offsets, uint32_t *r_pat,
+                              uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist, uint8_t *r_hk,
+                              hipStream_t st);
+
+// K2: hit-set recovery at every new hit end (reverse anchored DP).
+hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_flag,
+                          uint32_t n, const PatDesc *pats, const uint64_t *rpeq, const StreamDesc *streams,
+                          uint32_t nclass, uint32_t hks, uint8_t *r_hk, uint8_t *r_dist, uint32_t *err,
+                          hipStream_t st);
+
+// K3: the filter, one thread per segment of a (stream, pattern) run.
+hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
+                         uint32_t n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams,
+                         uint32_t do_filter, uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt,
+                         uint32_t *carry_flag, uint32_t *carry_rank, uint32_t *carry_len, hipStream_t st);
+
+// Gather the filter output into a dense array.
+hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, uint32_t n,
+                              uint32_t out_stride, OccRec *out, hipStream_t st);
+
+// Gather carried records for the next step.
+hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end,
+                                const uint8_t *r_dist, const uint8_t *r_hk, uint32_t hks, const uint32_t *carry_flag,
+                                const uint32_t *carry_off, const uint32_t *carry_rank, const uint32_t *carry_len,
+                                const StreamDesc *streams, uint32_t n, CarryRec *out, uint8_t *out_hk,
+                                hipStream_t st);
+
+// Exclusive prefix sum of n uint32 values; writes the total to *total.
+// `tmp` must hold scan_tmp_words(n) uint32.
+size_t scan_tmp_words(size_t n);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *total, uint32_t *tmp,
+                                 hipStream_t st);
+
+// Fill n uint32 with a value (graph-safe replacement for a memset).
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);
+
+}  // namespace oasm

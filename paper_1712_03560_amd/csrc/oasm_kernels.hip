@@ -1,0 +1,814 @@
+// HIP kernels of oasm_gpu for CDNA4 (gfx950).
+//
+// The hot path of online approximate string matching (arXiv 1712.03560):
+//   K0 match-mask build      (dictionary preparation)
+//   K1 scan                  hit ends: min over starts of lev(p, t[s..e]) <= K
+//                            (Section 5.1 "Less Naive"; bit-parallel column
+//                            recurrence after Myers 1999)
+//   scatter                  scan records into (stream, pattern, end) order
+//   K2 recover               the hit set at every hit end (Eq. 2): one
+//                            anchored DP per end over the reversed pattern
+//   K3 filter                Alg. 1 (Section 4) per (stream, pattern)
+//   compactions, prefix scan, symbol mapping.
+//
+// Integer bit-vector work only; no matrix cores.
+#include "oasm_internal.h"
+
+namespace oasm {
+
+// ------------------------------------------------------------------ helpers
+typedef __attribute__((address_space(4))) const uint32_t const_u32;
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Per-lane row of a tile image: P*W words padded to a power of two so that
+// one aligned LDS (or global) vector read fetches it.
+__host__ __device__ constexpr int pad_pow2(int x) { return x <= 1 ? 1 : x <= 2 ? 2 : x <= 4 ? 4 : 8; }
+
+// ------------------------------------------------------------------ K0
+// One thread per (pattern, symbol class).
+//
+// Scan image (K1): the pattern's rows occupy the top m bits of its W-word
+// column (row j at bit 32W - m + j); the 32W - m rows below it are wildcard
+// rows whose mask bit is set for every symbol.  Started with vertical delta
+// 0, such rows stay at delta 0 forever and shift a zero horizontal delta into
+// the first pattern row, which is exactly the free-start boundary (the zero
+// first row of the Less Naive matrix).  They also make the column sum of the
+// vertical deltas equal to the last-row value.
+//
+// Reversed masks (K2): row j <-> p[m-1-j], low placement, 64-bit words.
+__global__ void k_peq_build(const uint8_t *__restrict__ pat_bytes, const PatDesc *__restrict__ pats, uint32_t npat,
+                            const uint32_t *__restrict__ pat_tile, const uint32_t *__restrict__ pat_slot,
+                            const TileDesc *__restrict__ tiles, const uint32_t *__restrict__ tile_wp,
+                            const uint8_t *__restrict__ class_of, uint32_t nclass, uint32_t *__restrict__ peq_img,
+                            uint64_t *__restrict__ rpeq) {
+    uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t p = (uint32_t)(gid / nclass), c = (uint32_t)(gid % nclass);
+    if (p >= npat) return;
+    const PatDesc d = pats[p];
+    const uint8_t *pb = pat_bytes + d.off;
+    const int m = d.m;
+    const uint32_t tile = pat_tile[p], slot = pat_slot[p];
+    const uint32_t wp = tile_wp[tile];
+    const int W = (int)(wp & 0xFF), P = (int)(wp >> 8);
+    const int lane = (int)(slot % kWave), pp = (int)(slot / kWave);
+    const int g = 32 * W - m;
+    const int pws = pad_pow2(P * W);
+    uint32_t *img = peq_img + tiles[tile].peq_off + ((size_t)c * kWave + lane) * (size_t)pws + (size_t)pp * W;
+    for (int w = 0; w < W; ++w) {
+        uint32_t word = 0;
+        for (int b = 0; b < 32; ++b) {
+            int row = 32 * w + b - g;  // pattern row held by bit b of word w
+            bool set = row < 0 ? true : class_of[pb[row]] == c;
+            word |= (uint32_t)set << b;
+        }
+        img[w] = word;
+    }
+    uint64_t *rp = rpeq + d.rpeq_off + (size_t)c * d.w64;
+    for (int w = 0; w < d.w64; ++w) {
+        uint64_t word = 0;
+        for (int b = 0; b < 64; ++b) {
+            int j = 64 * w + b;
+            if (j < m && class_of[pb[m - 1 - j]] == c) word |= 1ull << b;
+        }
+        rp[w] = word;
+    }
+}
+
+hipError_t launch_peq_build(const uint8_t *pat_bytes, const PatDesc *pats, uint32_t npat, const uint32_t *pat_tile,
+                            const uint32_t *pat_slot, const TileDesc *tiles, const uint32_t *tile_wp,
+                            const uint8_t *class_of, uint32_t nclass, uint32_t *peq_img, uint64_t *rpeq,
+                            hipStream_t st) {
+    uint64_t n = (uint64_t)npat * nclass;
+    if (n == 0) return hipSuccess;
+    uint32_t blocks = (uint32_t)((n + 255) / 256);
+    hipLaunchKernelGGL(k_peq_build, dim3(blocks), dim3(256), 0, st, pat_bytes, pats, npat, pat_tile, pat_slot, tiles,
+                       tile_wp, class_of, nclass, peq_img, rpeq);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ symbols
+__global__ void k_map_symbols(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, uint64_t n,
+                              const uint8_t *__restrict__ class_of) {
+    __shared__ uint8_t tab[256];
+    if (threadIdx.x < 256) tab[threadIdx.x] = class_of[threadIdx.x];
+    __syncthreads();
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = tab[src[i]];
+}
+
+hipError_t launch_map_symbols(const uint8_t *src, uint8_t *dst, uint64_t n, const uint8_t *class_of, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t want = (n + 255) / 256;
+    uint32_t blocks = (uint32_t)(want < 16384 ? want : 16384);
+    hipLaunchKernelGGL(k_map_symbols, dim3(blocks), dim3(256), 0, st, src, dst, n, class_of);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ K1
+// One column step of the bit-parallel edit-distance recurrence for a
+// W-word column (search mode: a zero horizontal delta enters the first row).
+// pv/mv: vertical +1/-1 deltas; eq: rows whose pattern symbol equals the
+// text symbol.  With u = (eq & pv) + pv (carry through all W words):
+//   xh | pv = u | pv | eq,    ph = mv | ~(xh | pv),    mh = pv & (eq | ~u)
+//   pv' = (mh << 1) | ~(xv | (ph << 1)),    mv' = (ph << 1) & xv
+// where xv = eq | mv and the shifts carry across words.
+template <int W>
+__device__ __forceinline__ void column_step(uint32_t (&pv)[W], uint32_t (&mv)[W], const uint32_t (&eq)[W]) {
+    uint32_t ph[W], mh[W], xv[W];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint64_t s = (uint64_t)(eq[w] & pv[w]) + pv[w] + carry;
+        uint32_t u = (uint32_t)s;
+        carry = (uint32_t)(s >> 32);
+        xv[w] = eq[w] | mv[w];
+        ph[w] = mv[w] | ~(u | pv[w] | eq[w]);
+        mh[w] = pv[w] & (eq[w] | ~u);
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        uint32_t ph2 = w == 0 ? ph[0] << 1 : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
+        uint32_t mh2 = w == 0 ? mh[0] << 1 : __builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31);
+        mv[w] = ph2 & xv[w];
+        pv[w] = mh2 | ~(xv[w] | ph2);
+    }
+}
+
+template <int N>
+struct alignas(N * 4 < 16 ? N * 4 : 16) Words {
+    uint32_t v[N];
+};
+
+constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
+
+// K1.  Block = `waves` wavefronts sharing one tile (its match-mask image in
+// LDS, or read through the L1 when it does not fit); each wavefront scans
+// one chunk.  Lane l holds P patterns of W words (slots l, l+64, ...).
+// The text symbol is wave-uniform (scalar loads); every 4 symbols the hit
+// ballots are tested together, and only then does the wave branch to the
+// (rare) compaction path: per (symbol, pattern) a ballot, an mbcnt prefix and
+// one record per hit lane in the item's own buffer.
+template <int W, int P, bool LDSPEQ>
+__global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
+    extern __shared__ uint32_t lds_img[];
+    constexpr int PW = P * W;
+    constexpr int PWS = pad_pow2(PW);
+    const uint32_t tile_local = blockIdx.y;
+    const TileDesc td = a.tiles[a.tile_first + tile_local];
+    const uint32_t *gimg = a.peq_img + td.peq_off;
+    if (LDSPEQ) {
+        const uint32_t words = a.nclass * kWave * PWS;  // multiple of 64
+        const uint4 *src = reinterpret_cast<const uint4 *>(gimg);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds_img);
+        for (uint32_t i = threadIdx.x; i < words / 4; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint32_t chunk = uniform(blockIdx.x * (blockDim.x >> 6) + wave);
+    if (chunk >= a.nchunks) return;
+    const ChunkDesc cd = a.chunks[chunk];
+    const uint32_t item = a.item_base + chunk * a.ntiles + tile_local;
+    uint32_t *rec = a.item_rec + (size_t)item * a.cap;
+
+    uint32_t pv[P][W], mv[P][W], kk[P], pat[P], lanecnt[P];
+    uint64_t active[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t slot = p * kWave + lane;
+        const bool act = slot < td.n_active;
+        pat[p] = act ? a.slot_pat[td.slot_off + slot] : 0u;
+        const PatDesc d = a.pats[pat[p]];
+        kk[p] = d.k;
+        active[p] = __ballot(act);
+        const int g = 32 * W - (int)d.m;  // wildcard rows below the pattern
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            int lo = g - 32 * w;  // first pattern bit inside word w
+            uint32_t bits = lo <= 0 ? ~0u : (lo >= 32 ? 0u : (~0u << lo));
+            pv[p][w] = act ? bits : 0u;
+            mv[p][w] = 0u;
+        }
+        lanecnt[p] = 0;
+    }
+    uint32_t cnt = 0;
+
+    const const_u32 *text = (const const_u32 *)(cd.sym);
+    const uint32_t len = cd.scan_len, lb = cd.lookback;
+    const uint32_t lane_off = lane * PWS;
+    const uint32_t *img = LDSPEQ ? lds_img : gimg;
+
+    uint32_t next = text[0];
+    for (uint32_t pos = 0; pos < len; pos += kScanGroup) {
+        const uint32_t cur = next;
+        next = text[(pos >> 2) + 1];
+        uint64_t hb[kScanGroup][P];
+#pragma unroll
+        for (int s = 0; s < kScanGroup; ++s) {
+            const uint32_t c = (cur >> (8 * s)) & 0xFFu;
+            const Words<PWS> e = *reinterpret_cast<const Words<PWS> *>(img + c * (kWave * PWS) + lane_off);
+            const bool inrange = (pos + s >= lb) && (pos + s < len);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                uint32_t eq[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) eq[w] = e.v[p * W + w];
+                column_step<W>(pv[p], mv[p], eq);
+                uint32_t up = 0, dn = kk[p];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    up += __popc(pv[p][w]);
+                    dn += __popc(mv[p][w]);
+                }
+                // last-row value = sum of vertical deltas = up - (dn - K)
+                const uint64_t bal = __ballot(up <= dn) & active[p];
+                hb[s][p] = inrange ? bal : 0ull;
+            }
+        }
+        uint64_t any = 0;
+#pragma unroll
+        for (int s = 0; s < kScanGroup; ++s)
+#pragma unroll
+            for (int p = 0; p < P; ++p) any |= hb[s][p];
+        if (any) {
+#pragma unroll
+            for (int s = 0; s < kScanGroup; ++s) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const uint64_t b = hb[s][p];
+                    if (b) {
+                        if ((b >> lane) & 1ull) {
+                            const uint32_t idx = cnt + mbcnt64(b);
+                            if (idx < a.cap) rec[idx] = ((p * kWave + lane) << 24) | (pos + s - lb);
+                            lanecnt[p] += 1;
+                        }
+                        cnt += (uint32_t)__popcll(b);
+                    }
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        a.item_cnt[item] = cnt;
+        atomicMax(a.max_cnt, cnt);
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if ((active[p] >> lane) & 1ull) a.counts[cd.cnt_base + pat[p] * cd.cnt_stride] = lanecnt[p];
+    }
+}
+
+template <int W, int P>
+static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+    const uint32_t gx = (a.nchunks + waves - 1) / waves;
+    if (gx == 0 || a.ntiles == 0) return hipSuccess;
+    const size_t shmem = lds ? (size_t)a.nclass * kWave * pad_pow2(P * W) * 4 : 0;
+    if (lds) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_scan<W, P, true>), dim3(gx, a.ntiles), dim3(waves * kWave), shmem, st, a);
+    } else {
+        hipLaunchKernelGGL((k_scan<W, P, false>), dim3(gx, a.ntiles), dim3(waves * kWave), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+bool scan_variant_exists(int W, int P) {
+    switch (W * 16 + P) {
+        case 1 * 16 + 1: case 1 * 16 + 2: case 1 * 16 + 4:
+        case 2 * 16 + 1: case 2 * 16 + 2:
+        case 3 * 16 + 1: case 4 * 16 + 1: case 5 * 16 + 1:
+        case 6 * 16 + 1: case 7 * 16 + 1: case 8 * 16 + 1:
+            return true;
+        default:
+            return false;
+    }
+}
+
+hipError_t launch_scan(int W, int P, const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+    switch (W * 16 + P) {
+        case 1 * 16 + 1: return launch_scan_t<1, 1>(a, waves, lds, st);
+        case 1 * 16 + 2: return launch_scan_t<1, 2>(a, waves, lds, st);
+        case 1 * 16 + 4: return launch_scan_t<1, 4>(a, waves, lds, st);
+        case 2 * 16 + 1: return launch_scan_t<2, 1>(a, waves, lds, st);
+        case 2 * 16 + 2: return launch_scan_t<2, 2>(a, waves, lds, st);
+        case 3 * 16 + 1: return launch_scan_t<3, 1>(a, waves, lds, st);
+        case 4 * 16 + 1: return launch_scan_t<4, 1>(a, waves, lds, st);
+        case 5 * 16 + 1: return launch_scan_t<5, 1>(a, waves, lds, st);
+        case 6 * 16 + 1: return launch_scan_t<6, 1>(a, waves, lds, st);
+        case 7 * 16 + 1: return launch_scan_t<7, 1>(a, waves, lds, st);
+        case 8 * 16 + 1: return launch_scan_t<8, 1>(a, waves, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ scatter
+// One wavefront per scan item.  Records of an item are in (end, slot)
+// order; each record goes to offsets[(stream, pattern, chunk)] + its rank
+// among the item's records of the same slot.  The rank inside a batch of 64
+// comes from eight ballots (lanes whose slot agrees on every bit); the
+// running count per slot sits in LDS.
+__global__ void __launch_bounds__(256) k_scatter(const ChunkDesc *__restrict__ chunks, uint32_t nchunks,
+                                                 const TileDesc *__restrict__ tiles, uint32_t tile_first,
+                                                 uint32_t ntiles, const uint32_t *__restrict__ slot_pat,
+                                                 const uint32_t *__restrict__ item_rec,
+                                                 const uint32_t *__restrict__ item_cnt, uint32_t item_base,
+                                                 uint32_t cap, const uint32_t *__restrict__ offsets,
+                                                 const uint32_t *__restrict__ chunk_stream, uint32_t *__restrict__ r_pat,
+                                                 uint32_t *__restrict__ r_sl, uint64_t *__restrict__ r_end,
+                                                 uint8_t *__restrict__ r_flag) {
+    __shared__ uint32_t run[4][256];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint32_t local = uniform(blockIdx.x * 4 + wave);
+    for (uint32_t i = lane; i < 256; i += kWave) run[wave][i] = 0;
+    if (local >= nchunks * ntiles) return;
+    const uint32_t chunk = local / ntiles, tile_local = local % ntiles;
+    const uint32_t item = item_base + local;
+    uint32_t n = item_cnt[item];
+    if (n > cap) n = cap;
+    if (n == 0) return;
+    const ChunkDesc cd = chunks[chunk];
+    const TileDesc td = tiles[tile_first + tile_local];
+    const uint32_t sl = chunk_stream[chunk];
+    const uint32_t *rec = item_rec + (size_t)item * cap;
+    for (uint32_t b = 0; b < n; b += kWave) {
+        const uint32_t i = b + lane;
+        const bool valid = i < n;
+        const uint32_t r = valid ? rec[i] : 0u;
+        const uint32_t slot = r >> 24;
+        uint64_t same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 8; ++bit) {
+            const bool one = (slot >> bit) & 1u;
+            const uint64_t bal = __ballot(valid && one);
+            same &= one ? bal : ~bal;
+        }
+        const uint32_t rank = mbcnt64(same);
+        const uint32_t group = (uint32_t)__popcll(same);
+        uint32_t base = 0;
+        if (valid) base = run[wave][slot];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == group - 1) run[wave][slot] = base + group;
+        __builtin_amdgcn_wave_barrier();
+        if (valid) {
+            const uint32_t pattern = slot_pat[td.slot_off + slot];
+            const uint32_t dst = offsets[cd.cnt_base + pattern * cd.cnt_stride] + base + rank;
+            r_pat[dst] = pattern;
+            r_sl[dst] = sl;
+            r_end[dst] = cd.abs_first + (r & 0xFFFFFFu);
+            r_flag[dst] = 0;
+        }
+    }
+}
+
+hipError_t launch_scatter(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
+                          uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
+                          const uint32_t *item_cnt, uint32_t item_base, uint32_t cap, const uint32_t *offsets,
+                          const uint32_t *chunk_stream, uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end,
+                          uint8_t *r_flag, hipStream_t st) {
+    const uint64_t items = (uint64_t)nchunks * ntiles;
+    if (items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((uint32_t)((items + 3) / 4)), dim3(256), 0, st, chunks, nchunks, tiles,
+                       tile_first, ntiles, slot_pat, item_rec, item_cnt, item_base, cap, offsets, chunk_stream, r_pat,
+                       r_sl, r_end, r_flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ carry
+__global__ void k_carry_counts(const CarryRec *__restrict__ carry, uint32_t n, const uint32_t *__restrict__ s2l,
+                               const uint32_t *__restrict__ sbase, const uint32_t *__restrict__ sstride,
+                               uint32_t *__restrict__ counts) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const CarryRec c = carry[i];
+    if (c.rank != 0) return;
+    const uint32_t s = s2l[c.stream_slot];
+    counts[sbase[s] + c.pattern * sstride[s]] = c.run_len;
+}
+
+__global__ void k_carry_place(const CarryRec *__restrict__ carry, const uint8_t *__restrict__ carry_hk, uint32_t n,
+                              uint32_t hks, const uint32_t *__restrict__ s2l, const uint32_t *__restrict__ sbase,
+                              const uint32_t *__restrict__ sstride, const uint32_t *__restrict__ offsets,
+                              uint32_t *__restrict__ r_pat, uint32_t *__restrict__ r_sl, uint64_t *__restrict__ r_end,
+                              uint8_t *__restrict__ r_flag, uint8_t *__restrict__ r_dist, uint8_t *__restrict__ r_hk) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const CarryRec c = carry[i];
+    const uint32_t s = s2l[c.stream_slot];
+    const uint32_t dst = offsets[sbase[s] + c.pattern * sstride[s]] + c.rank;
+    r_pat[dst] = c.pattern;
+    r_sl[dst] = s;
+    r_end[dst] = c.end_abs;
+    r_flag[dst] = 1;
+    r_dist[dst] = (uint8_t)c.dist;
+    for (uint32_t q = 0; q < hks; ++q) r_hk[(size_t)dst * hks + q] = carry_hk[(size_t)i * hks + q];
+}
+
+hipError_t launch_carry_counts(const CarryRec *carry, uint32_t ncarry, const uint32_t *slot_to_local,
+                               const uint32_t *stream_cnt_base, const uint32_t *stream_cnt_stride, uint32_t *counts,
+                               hipStream_t st) {
+    if (ncarry == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_carry_counts, dim3((ncarry + 255) / 256), dim3(256), 0, st, carry, ncarry, slot_to_local,
+                       stream_cnt_base, stream_cnt_stride, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_carry_place(const CarryRec *carry, const uint8_t *carry_hk, uint32_t ncarry, uint32_t hks,
+                              const uint32_t *slot_to_local, const uint32_t *stream_cnt_base,
+                              const uint32_t *stream_cnt_stride, const uint32_t *offsets, uint32_t *r_pat,
+                              uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist, uint8_t *r_hk,
+                              hipStream_t st) {
+    if (ncarry == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_carry_place, dim3((ncarry + 255) / 256), dim3(256), 0, st, carry, carry_hk, ncarry, hks,
+                       slot_to_local, stream_cnt_base, stream_cnt_stride, offsets, r_pat, r_sl, r_end, r_flag, r_dist,
+                       r_hk);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ K2
+// One thread per new hit end e.  The reversed pattern is aligned against
+// t[e], t[e-1], ... with an anchored column recurrence (a +1 horizontal delta
+// enters the first row, since the DP's first row is 0, 1, 2, ...).  After l
+// symbols the last row holds lev(p, t[e-l+1 .. e]), which is written for every
+// l in [max(1, m-K), m+K] whose value is <= K: the hit set of Eq. 2 at e, the
+// same per-start distances the paper's LEV CALC unit produces.
+__global__ void __launch_bounds__(256) k_recover(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
+                                                 const uint64_t *__restrict__ r_end,
+                                                 const uint8_t *__restrict__ r_flag, uint32_t n,
+                                                 const PatDesc *__restrict__ pats, const uint64_t *__restrict__ rpeq,
+                                                 const StreamDesc *__restrict__ streams, uint32_t nclass, uint32_t hks,
+                                                 uint8_t *__restrict__ r_hk, uint8_t *__restrict__ r_dist,
+                                                 uint32_t *__restrict__ err) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || r_flag[i]) return;
+    const PatDesc d = pats[r_pat[i]];
+    const StreamDesc sd = streams[r_sl[i]];
+    const uint64_t e = r_end[i];
+    const int m = d.m, K = d.k, W = d.w64;
+    const int lmax = m + K;
+    const int lmin = m - K < 1 ? 1 : m - K;
+    const int steps = (uint64_t)lmax <= e + 1 ? lmax : (int)(e + 1);
+    const uint8_t *t = sd.sym + (e - sd.base_abs);  // t[0] = symbol at e; walk backwards
+    const uint64_t *rp = rpeq + d.rpeq_off;
+    uint8_t *hk = r_hk + (size_t)i * hks;
+    for (uint32_t q = 0; q < hks; ++q) hk[q] = kNoHit;
+
+    uint64_t pv[kMaxW64], mv[kMaxW64];
+#pragma unroll
+    for (int w = 0; w < kMaxW64; ++w) {
+        const int lo = 64 * w;
+        const int nb = m - lo;
+        pv[w] = nb >= 64 ? ~0ull : (nb <= 0 ? 0ull : ((1ull << nb) - 1));
+        mv[w] = 0;
+    }
+    const int top_w = (m - 1) >> 6, top_b = (m - 1) & 63;
+    int score = m;
+    int best = 255;
+    for (int l = 1; l <= steps; ++l) {
+        const uint32_t c = t[-(l - 1)];
+        uint64_t ph[kMaxW64], mh[kMaxW64], xv[kMaxW64];
+        uint64_t carry = 0;
+#pragma unroll
+        for (int w = 0; w < kMaxW64; ++w) {
+            if (w < W) {
+                const uint64_t eq = rp[(size_t)c * W + w];
+                const uint64_t x = eq & pv[w];
+                const uint64_t t1 = x + carry;
+                const uint64_t c1 = t1 < carry;
+                const uint64_t u = t1 + pv[w];
+                const uint64_t c2 = u < t1;
+                carry = c1 | c2;
+                const uint64_t xh = (u ^ pv[w]) | eq;
+                xv[w] = eq | mv[w];
+                ph[w] = mv[w] | ~(xh | pv[w]);
+                mh[w] = pv[w] & xh;
+            }
+        }
+        score += (int)((ph[top_w] >> top_b) & 1ull) - (int)((mh[top_w] >> top_b) & 1ull);
+#pragma unroll
+        for (int w = 0; w < kMaxW64; ++w) {
+            if (w < W) {
+                const uint64_t ph2 = (ph[w] << 1) | (w == 0 ? 1ull : ph[w - 1] >> 63);
+                const uint64_t mh2 = (mh[w] << 1) | (w == 0 ? 0ull : mh[w - 1] >> 63);
+                pv[w] = mh2 | ~(xv[w] | ph2);
+                mv[w] = ph2 & xv[w];
+            }
+        }
+        if (l >= lmin && score <= K) {
+            hk[l - (m - K)] = (uint8_t)score;
+            if (score < best) best = score;
+        }
+    }
+    r_dist[i] = (uint8_t)best;
+    if (best > K) atomicAdd(err, 1u);  // the scan reported a hit the recovery does not see
+}
+
+hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_flag,
+                          uint32_t n, const PatDesc *pats, const uint64_t *rpeq, const StreamDesc *streams,
+                          uint32_t nclass, uint32_t hks, uint8_t *r_hk, uint8_t *r_dist, uint32_t *err,
+                          hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recover, dim3((n + 255) / 256), dim3(256), 0, st, r_pat, r_sl, r_end, r_flag, n, pats, rpeq,
+                       streams, nclass, hks, r_hk, r_dist, err);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ K3
+constexpr int kMaxLevels = 64;  // K <= 63
+
+// One thread per hit end; the thread that owns the first end of a segment
+// runs Alg. 1 over the segment.  A segment is a maximal run of one
+// (stream, pattern)'s hit ends in which consecutive ends are less than m + K
+// apart.  Alg. 1's state is empty between segments: any pending occurrence
+// ends at or before the last end of its segment, completes there, and every
+// hit of the next segment starts after it.  So segments are filtered in
+// parallel, each from the initial state.
+//
+// Inside a segment the hit set is walked in (start, length) order, the
+// order of Alg. 1's loops: for a start s the candidate ends are the hit ends
+// in [s + lmin - 1, s + m + K - 1], visited in increasing order (= increasing
+// length); starts with no candidate are skipped.  The completion test of
+// Alg. 1 is applied lazily: the stored best completes at its own end, which
+// is acted on before the first later start is examined (nothing changes at
+// starts without hits).
+//
+// A segment whose last end is within m + K of the stream's scanned frontier
+// may still grow: it is not filtered now but carried to the next step.
+__global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
+                                               const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
+                                               uint32_t n, uint32_t hks, const PatDesc *__restrict__ pats,
+                                               const StreamDesc *__restrict__ streams, uint32_t do_filter,
+                                               uint32_t out_stride, OccRec *__restrict__ seg_out,
+                                               uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag,
+                                               uint32_t *__restrict__ carry_rank, uint32_t *__restrict__ carry_len) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t p = r_pat[i], sl = r_sl[i];
+    const uint64_t e0 = r_end[i];
+    const PatDesc d = pats[p];
+    const int m = d.m, K = d.k;
+    const uint64_t gap = (uint64_t)(m + K);
+    const bool start = i == 0 || r_pat[i - 1] != p || r_sl[i - 1] != sl || e0 - r_end[i - 1] >= gap;
+    if (!start) {
+        seg_cnt[i] = 0;
+        return;
+    }
+    uint32_t j1 = i + 1;
+    while (j1 < n && r_pat[j1] == p && r_sl[j1] == sl && r_end[j1] - r_end[j1 - 1] < gap) ++j1;
+    const StreamDesc sd = streams[sl];
+    const bool open = do_filter && !sd.closed && r_end[j1 - 1] + gap > sd.frontier;
+    for (uint32_t j = i; j < j1; ++j) {
+        carry_flag[j] = open ? 1u : 0u;
+        carry_rank[j] = j - i;
+        carry_len[j] = j1 - i;
+    }
+    if (open || !do_filter) {
+        seg_cnt[i] = 0;
+        return;
+    }
+
+    const int lmax = m + K;
+    const int lmin = m - K < 1 ? 1 : m - K;
+    const int qoff = m - K;
+    uint64_t lvl_s[kMaxLevels];
+    uint32_t lvl_l[kMaxLevels];
+    for (int q = 0; q <= K; ++q) lvl_l[q] = 0;
+    int idx = K;
+    bool ins = false;
+    uint32_t cnt = 0;
+    OccRec *out = seg_out + (size_t)i * out_stride;
+
+    auto emit = [&](uint64_t pos) {
+        uint64_t acc = 0;
+        for (int j = idx; j <= K; ++j) {
+            if (lvl_l[j] == 0) continue;
+            const uint64_t r = pos - lvl_s[j] + 1;  // validation counter r(j)
+            if (j == idx || r - acc > lvl_l[j]) {  // Eq. 3 (acc <= r always holds)
+                OccRec o;
+                o.start_abs = lvl_s[j];
+                o.pattern = p;
+                o.stream_local = sl;
+                o.len = lvl_l[j];
+                o.k = (uint32_t)j;
+                out[cnt++] = o;
+                acc += lvl_l[j];
+            }
+            lvl_l[j] = 0;
+        }
+        idx = K;
+        ins = false;
+    };
+
+    uint32_t lo = i;
+    uint64_t s = e0 + 1 >= (uint64_t)lmax ? e0 + 1 - lmax : 0;
+    while (true) {
+        while (lo < j1 && r_end[lo] + 1 < s + lmin) ++lo;
+        if (lo >= j1) break;
+        if (r_end[lo] + 1 > s + lmax) {  // no hit end reachable from s: jump
+            s = r_end[lo] + 1 - lmax;
+            continue;
+        }
+        if (ins && lvl_s[idx] + lvl_l[idx] - 1 < s) emit(lvl_s[idx] + lvl_l[idx] - 1);
+        for (uint32_t j = lo; j < j1 && r_end[j] + 1 <= s + lmax; ++j) {
+            const int l = (int)(r_end[j] + 1 - s);
+            const int k = r_hk[(size_t)j * hks + (l - qoff)];
+            if (k == kNoHit) continue;
+            if (k < idx) {  // R1
+                idx = k;
+                ins = true;
+                lvl_s[k] = s;
+                lvl_l[k] = (uint32_t)l;
+            } else if (k == idx) {  // R2 / R3: earlier end, then shorter
+                const uint64_t be = lvl_s[k] + lvl_l[k];
+                if (lvl_l[k] == 0 || s + l < be || (s + l == be && (uint32_t)l < lvl_l[k])) {
+                    ins = true;
+                    lvl_s[k] = s;
+                    lvl_l[k] = (uint32_t)l;
+                }
+            }
+        }
+        ++s;
+    }
+    if (ins) emit(lvl_s[idx] + lvl_l[idx] - 1);
+    seg_cnt[i] = cnt;
+}
+
+hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
+                         uint32_t n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams, uint32_t do_filter,
+                         uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt, uint32_t *carry_flag,
+                         uint32_t *carry_rank, uint32_t *carry_len, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_filter, dim3((n + 63) / 64), dim3(64), 0, st, r_pat, r_sl, r_end, r_hk, n, hks, pats, streams,
+                       do_filter, out_stride, seg_out, seg_cnt, carry_flag, carry_rank, carry_len);
+    return hipGetLastError();
+}
+
+__global__ void k_compact_occ(const OccRec *__restrict__ seg_out, const uint32_t *__restrict__ seg_cnt,
+                              const uint32_t *__restrict__ seg_off, uint32_t n, uint32_t stride,
+                              OccRec *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = seg_cnt[i];
+    for (uint32_t q = 0; q < c; ++q) out[seg_off[i] + q] = seg_out[(size_t)i * stride + q];
+}
+
+hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, uint32_t n,
+                              uint32_t out_stride, OccRec *out, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_occ, dim3((n + 255) / 256), dim3(256), 0, st, seg_out, seg_cnt, seg_off, n,
+                       out_stride, out);
+    return hipGetLastError();
+}
+
+__global__ void k_compact_carry(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
+                                const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_dist,
+                                const uint8_t *__restrict__ r_hk, uint32_t hks,
+                                const uint32_t *__restrict__ carry_flag, const uint32_t *__restrict__ carry_off,
+                                const uint32_t *__restrict__ carry_rank, const uint32_t *__restrict__ carry_len,
+                                const StreamDesc *__restrict__ streams, uint32_t n, CarryRec *__restrict__ out,
+                                uint8_t *__restrict__ out_hk) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !carry_flag[i]) return;
+    const uint32_t o = carry_off[i];
+    CarryRec c;
+    c.end_abs = r_end[i];
+    c.pattern = r_pat[i];
+    c.stream_slot = streams[r_sl[i]].slot;
+    c.rank = carry_rank[i];
+    c.run_len = carry_len[i];
+    c.dist = r_dist[i];
+    c.pad = 0;
+    out[o] = c;
+    for (uint32_t q = 0; q < hks; ++q) out_hk[(size_t)o * hks + q] = r_hk[(size_t)i * hks + q];
+}
+
+hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end,
+                                const uint8_t *r_dist, const uint8_t *r_hk, uint32_t hks, const uint32_t *carry_flag,
+                                const uint32_t *carry_off, const uint32_t *carry_rank, const uint32_t *carry_len,
+                                const StreamDesc *streams, uint32_t n, CarryRec *out, uint8_t *out_hk,
+                                hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_carry, dim3((n + 255) / 256), dim3(256), 0, st, r_pat, r_sl, r_end, r_dist, r_hk,
+                       hks, carry_flag, carry_off, carry_rank, carry_len, streams, n, out, out_hk);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive prefix sum in three passes: per-block sums, a single-block scan
+// of the block sums, and per-block scans offset by the scanned sums.
+constexpr uint32_t kScanThreads = 256;
+constexpr uint32_t kScanPer = 8;
+constexpr uint32_t kScanTile = kScanThreads * kScanPer;
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off, kWave);
+        if (lane >= (uint32_t)off) v += t;
+    }
+    return v;
+}
+
+// block-wide exclusive scan of one value per thread; returns the block total
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &excl) {
+    __shared__ uint32_t wsum[kScanThreads / kWave];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t woff = 0, total = 0;
+    for (uint32_t w = 0; w < kScanThreads / kWave; ++w) {
+        const uint32_t s = wsum[w];
+        if (w < wave) woff += s;
+        total += s;
+    }
+    __syncthreads();
+    excl = woff + incl - v;
+    return total;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__restrict__ in, size_t n,
+                                                              uint32_t *__restrict__ sums) {
+    const size_t base = (size_t)blockIdx.x * kScanTile;
+    uint32_t v = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kScanPer; ++q) {
+        const size_t i = base + (size_t)q * kScanThreads + threadIdx.x;
+        if (i < n) v += in[i];
+    }
+    uint32_t excl;
+    const uint32_t total = block_excl_scan(v, excl);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t *__restrict__ sums, uint32_t nb,
+                                                            uint32_t *__restrict__ total) {
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < nb; b += kScanThreads) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < nb ? sums[i] : 0u;
+        uint32_t excl;
+        const uint32_t t = block_excl_scan(v, excl);
+        if (i < nb) sums[i] = carry + excl;
+        carry += t;
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
+                                                             size_t n, const uint32_t *__restrict__ sums) {
+    const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kScanPer; ++q) {
+        v[q] = base + q < n ? in[base + q] : 0u;
+        s += v[q];
+    }
+    uint32_t excl;
+    block_excl_scan(s, excl);
+    uint32_t run = sums[blockIdx.x] + excl;
+#pragma unroll
+    for (uint32_t q = 0; q < kScanPer; ++q) {
+        if (base + q < n) out[base + q] = run;
+        run += v[q];
+    }
+}
+
+size_t scan_tmp_words(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *total, uint32_t *tmp,
+                                 hipStream_t st) {
+    const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, tmp, nb, total);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, st, in, out, n, tmp);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t want = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u32, dim3((uint32_t)(want < 8192 ? want : 8192)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace oasm

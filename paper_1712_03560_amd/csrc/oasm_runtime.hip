@@ -1,0 +1,948 @@
+// Host runtime and C ABI of oasm_gpu (see include/oasm_gpu.h).
+//
+// A context owns the dictionary's device tables, one staging buffer of
+// class-mapped symbols per stream, reusable device work buffers, and host
+// queues of results.  oasm_sync runs one matching step over every stream
+// with new bytes (or one step per stream in plain mode):
+//
+//   plan      chunks of C symbols per stream, each read with an
+//             (m_max + K_max - 1)-symbol look-back so its hit ends are exact
+//   K1        scan, one launch per word-count class (grid: chunks x tiles)
+//   counts -> exclusive scan -> offsets; scatter into (stream, pattern, end)
+//   carry     hit ends of filter segments left open by the previous step
+//             are placed ahead of the new ones of their (stream, pattern)
+//   K2        hit set at every new hit end
+//   K3        Alg. 1 per segment; open segments are carried to the next step
+//   compaction and copy-back of hit ends, occurrences and the new carry.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/oasm_gpu.h"
+#include "oasm_internal.h"
+
+using namespace oasm;
+
+namespace {
+
+constexpr size_t kPad = 64;  // readable slack after every staging buffer
+
+struct HipFail {
+    hipError_t e;
+    const char *what;
+};
+
+inline void ck(hipError_t e, const char *what) {
+    if (e != hipSuccess) throw HipFail{e, what};
+}
+
+// A device buffer that grows (never shrinks) on demand.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+    void ensure(size_t bytes, hipStream_t st) {
+        if (bytes <= cap) return;
+        size_t want = std::max(bytes, cap + cap / 2);
+        want = (want + 255) & ~size_t(255);
+        if (p) {
+            ck(hipStreamSynchronize(st), "sync before realloc");
+            ck(hipFree(p), "hipFree");
+            p = nullptr;
+            cap = 0;
+        }
+        ck(hipMalloc(&p, want), "hipMalloc");
+        cap = want;
+    }
+    void release() {
+        if (p) hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+// Pinned host buffer that grows on demand.
+struct PinBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    template <class T>
+    T *as() const { return reinterpret_cast<T *>(p); }
+    void ensure(size_t bytes, hipStream_t st) {
+        if (bytes <= cap) return;
+        size_t want = std::max(bytes, cap * 2);
+        want = (want + 4095) & ~size_t(4095);
+        if (p) {
+            ck(hipStreamSynchronize(st), "sync before pinned realloc");
+            ck(hipHostFree(p), "hipHostFree");
+            p = nullptr;
+            cap = 0;
+        }
+        ck(hipHostMalloc(&p, want, hipHostMallocDefault), "hipHostMalloc");
+        cap = want;
+    }
+    void release() {
+        if (p) hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+};
+
+struct StreamState {
+    uint64_t id = 0;
+    uint32_t slot = 0;
+    uint8_t *sym = nullptr;  // class-mapped symbols (device)
+    size_t cap = 0;
+    uint64_t base_abs = 0;   // absolute position of sym[0]
+    size_t valid = 0;        // symbols held
+    size_t scanned = 0;      // symbols already matched (the retained tail)
+    bool close_pending = false;
+    bool closed = false;
+    std::vector<CarryRec> carry;  // open filter segment(s) of this stream
+    std::vector<uint8_t> carry_hk;
+};
+
+struct ClassInfo {
+    int W = 1, P = 1;
+    uint32_t tile_first = 0, ntiles = 0;
+    bool lds = true;
+    int waves = 4;
+};
+
+}  // namespace
+
+struct oasm_ctx {
+    std::mutex mu;
+    int device = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    uint32_t rules = OASM_RULES_PAPER;
+    oasm_config cfg{};
+    std::string err;
+    bool poisoned = false;
+
+    // dictionary
+    uint32_t npat = 0;
+    std::vector<uint16_t> m, k;
+    uint32_t mmax = 0, kmax = 0, hks = 1, lookback = 0, nclass = 1;
+    uint8_t class_of[256];
+    uint64_t msum = 0;
+    std::vector<ClassInfo> classes;
+    uint32_t ntiles = 0;
+    DevBuf d_pats, d_slot_pat, d_tiles, d_peq, d_rpeq, d_class, d_patbytes, d_pat_tile, d_pat_slot, d_tile_wp;
+    std::vector<uint32_t> class_w32;  // per pattern: words
+
+    // streams
+    std::unordered_map<uint64_t, uint32_t> slot_of;
+    std::vector<StreamState> streams;
+
+    // step buffers
+    DevBuf plan, counts, offsets, item_rec, item_cnt, ctl, scan_tmp;
+    DevBuf r_pat, r_sl, r_end, r_flag, r_dist, r_hk, seg_cnt, seg_off, carry_flag, carry_off, carry_rank, carry_len;
+    DevBuf seg_out, occ_out, carry_out, carry_out_hk, carry_in, carry_in_hk, raw_in;
+    PinBuf pin_plan, pin_ctl, pin_out, pin_feed;
+    size_t pin_feed_used = 0;
+    uint32_t cap = 256;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+
+    // results
+    std::vector<oasm_hit> q_raw;
+    std::vector<oasm_occ> q_occ, q_h;
+    size_t rd_raw = 0, rd_occ = 0, rd_h = 0;
+
+    oasm_stats stats{};
+    uint64_t staged_bytes = 0;
+};
+
+namespace {
+
+oasm_status fail(oasm_ctx *c, oasm_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+oasm_status device_fail(oasm_ctx *c, const HipFail &f) {
+    if (c) {
+        c->poisoned = true;
+        c->err = std::string(f.what) + ": " + hipGetErrorString(f.e);
+    }
+    return OASM_E_DEVICE;
+}
+
+uint32_t pow2_at_least(uint64_t v) {
+    uint32_t r = 1;
+    while (r < v && r < (1u << 31)) r <<= 1;
+    return r;
+}
+
+// ------------------------------------------------------------------ plan
+struct StepPlan {
+    std::vector<uint32_t> locals;  // stream indices (ctx->streams) in step order
+    std::vector<ChunkDesc> chunks;
+    std::vector<uint32_t> chunk_stream;
+    std::vector<StreamDesc> sdesc;
+    std::vector<uint32_t> s_base, s_stride;
+    std::vector<uint32_t> slot_to_local;
+    std::vector<CarryRec> carry;
+    std::vector<uint8_t> carry_hk;
+    uint64_t ncounts = 0;
+    uint64_t bytes = 0;
+};
+
+template <class T>
+size_t put(std::vector<uint8_t> &blob, const std::vector<T> &v) {
+    size_t off = (blob.size() + 255) & ~size_t(255);
+    blob.resize(off + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(blob.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+uint32_t choose_chunk(oasm_ctx *c, uint64_t bytes) {
+    if (c->cfg.chunk_bytes) return std::max<uint32_t>(64, c->cfg.chunk_bytes & ~63u);
+    // enough work items to fill 256 CUs several times over
+    const uint64_t target_items = 16384;
+    uint64_t per = bytes * std::max<uint32_t>(1, c->ntiles) / target_items;
+    per = std::max<uint64_t>(per, 2048);
+    per = std::min<uint64_t>(per, 1u << 16);
+    return (uint32_t)((per + 63) & ~63ull);
+}
+
+void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
+    uint64_t total_new = 0;
+    for (uint32_t si : which) total_new += c->streams[si].valid - c->streams[si].scanned;
+    const uint32_t C = choose_chunk(c, total_new);
+    pl.slot_to_local.assign(c->streams.size(), 0xFFFFFFFFu);
+    uint64_t cbase = 0;
+    for (uint32_t si : which) {
+        StreamState &s = c->streams[si];
+        const uint32_t local = (uint32_t)pl.locals.size();
+        pl.locals.push_back(si);
+        pl.slot_to_local[s.slot] = local;
+        const uint64_t pend = s.valid - s.scanned;
+        const uint64_t nch = (pend + C - 1) / C;
+        const uint64_t stride = nch + 1;  // chunk slot 0: carried hit ends
+        pl.s_base.push_back((uint32_t)cbase);
+        pl.s_stride.push_back((uint32_t)stride);
+        for (uint64_t j = 0; j < nch; ++j) {
+            const uint64_t e0 = s.scanned + j * C;  // staging index of the first reported end
+            const uint64_t e1 = std::min<uint64_t>(s.valid, e0 + C);
+            uint64_t st0 = e0 >= c->lookback ? e0 - c->lookback : 0;
+            st0 &= ~uint64_t(3);
+            ChunkDesc cd;
+            cd.sym = s.sym + st0;
+            cd.abs_first = s.base_abs + e0;
+            cd.scan_len = (uint32_t)(e1 - st0);
+            cd.lookback = (uint32_t)(e0 - st0);
+            cd.cnt_base = (uint32_t)(cbase + 1 + j);
+            cd.cnt_stride = (uint32_t)stride;
+            pl.chunks.push_back(cd);
+            pl.chunk_stream.push_back(local);
+        }
+        cbase += stride * c->npat;
+        StreamDesc sd;
+        sd.sym = s.sym;
+        sd.base_abs = s.base_abs;
+        sd.frontier = s.base_abs + s.valid;
+        sd.closed = s.close_pending ? 1u : 0u;
+        sd.slot = s.slot;
+        pl.sdesc.push_back(sd);
+        pl.carry.insert(pl.carry.end(), s.carry.begin(), s.carry.end());
+        pl.carry_hk.insert(pl.carry_hk.end(), s.carry_hk.begin(), s.carry_hk.end());
+        pl.bytes += pend;
+    }
+    pl.ncounts = cbase;
+}
+
+// ------------------------------------------------------------------ step
+void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
+    hipStream_t st = c->st;
+    StepPlan pl;
+    build_plan(c, which, pl);
+    if (pl.ncounts >= (1ull << 32)) throw HipFail{hipErrorInvalidValue, "step too large (counts exceed 2^32)"};
+
+    // upload the plan in one copy
+    std::vector<uint8_t> blob;
+    const size_t o_chunks = put(blob, pl.chunks);
+    const size_t o_cstream = put(blob, pl.chunk_stream);
+    const size_t o_sdesc = put(blob, pl.sdesc);
+    const size_t o_sbase = put(blob, pl.s_base);
+    const size_t o_sstride = put(blob, pl.s_stride);
+    const size_t o_s2l = put(blob, pl.slot_to_local);
+    const size_t o_carry = put(blob, pl.carry);
+    const size_t o_carry_hk = put(blob, pl.carry_hk);
+    blob.resize(blob.size() + 16);
+    c->pin_plan.ensure(blob.size(), st);
+    ck(hipStreamSynchronize(st), "sync before plan upload");  // pinned plan may still be in use
+    std::memcpy(c->pin_plan.p, blob.data(), blob.size());
+    c->plan.ensure(blob.size(), st);
+    ck(hipMemcpyAsync(c->plan.p, c->pin_plan.p, blob.size(), hipMemcpyHostToDevice, st), "plan upload");
+    uint8_t *pb = c->plan.as<uint8_t>();
+    const ChunkDesc *d_chunks = reinterpret_cast<const ChunkDesc *>(pb + o_chunks);
+    const uint32_t *d_cstream = reinterpret_cast<const uint32_t *>(pb + o_cstream);
+    const StreamDesc *d_sdesc = reinterpret_cast<const StreamDesc *>(pb + o_sdesc);
+    const uint32_t *d_sbase = reinterpret_cast<const uint32_t *>(pb + o_sbase);
+    const uint32_t *d_sstride = reinterpret_cast<const uint32_t *>(pb + o_sstride);
+    const uint32_t *d_s2l = reinterpret_cast<const uint32_t *>(pb + o_s2l);
+    const CarryRec *d_carry = reinterpret_cast<const CarryRec *>(pb + o_carry);
+    const uint8_t *d_carry_hk = pb + o_carry_hk;
+    const uint32_t nchunks = (uint32_t)pl.chunks.size();
+    const uint32_t ncarry = (uint32_t)pl.carry.size();
+
+    // control words: [0] max item count, [1] raw total, [2] occ total, [3] carry total, [4] recovery errors
+    c->ctl.ensure(64, st);
+    uint32_t *ctl = c->ctl.as<uint32_t>();
+    c->pin_ctl.ensure(64, st);
+
+    const uint64_t nitems = (uint64_t)nchunks * c->ntiles;
+    c->counts.ensure(std::max<uint64_t>(1, pl.ncounts) * 4, st);
+    c->offsets.ensure(std::max<uint64_t>(1, pl.ncounts) * 4, st);
+    c->item_cnt.ensure(std::max<uint64_t>(1, nitems) * 4, st);
+    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint64_t>(pl.ncounts, 1)) * 4, 1024), st);
+
+    uint32_t raw_total = 0;
+    for (int attempt = 0;; ++attempt) {
+        c->item_rec.ensure(std::max<uint64_t>(1, nitems) * c->cap * 4, st);
+        ck(launch_fill_u32(c->counts.as<uint32_t>(), 0, pl.ncounts, st), "fill counts");
+        ck(launch_fill_u32(ctl, 0, 16, st), "fill ctl");
+        ck(hipEventRecord(c->ev0, st), "event");
+        uint32_t item_base = 0;
+        for (const ClassInfo &ci : c->classes) {
+            ScanArgs a;
+            a.chunks = d_chunks;
+            a.nchunks = nchunks;
+            a.tiles = c->d_tiles.as<TileDesc>();
+            a.tile_first = ci.tile_first;
+            a.ntiles = ci.ntiles;
+            a.peq_img = c->d_peq.as<uint32_t>();
+            a.slot_pat = c->d_slot_pat.as<uint32_t>();
+            a.pats = c->d_pats.as<PatDesc>();
+            a.nclass = c->nclass;
+            a.item_rec = c->item_rec.as<uint32_t>();
+            a.item_cnt = c->item_cnt.as<uint32_t>();
+            a.item_base = item_base;
+            a.cap = c->cap;
+            a.counts = c->counts.as<uint32_t>();
+            a.max_cnt = ctl + 0;
+            ck(launch_scan(ci.W, ci.P, a, ci.waves, ci.lds, st), "scan launch");
+            item_base += nchunks * ci.ntiles;
+            c->stats.scan_launches++;
+        }
+        ck(hipEventRecord(c->ev1, st), "event");
+        ck(launch_carry_counts(d_carry, ncarry, d_s2l, d_sbase, d_sstride, c->counts.as<uint32_t>(), st),
+           "carry counts");
+        ck(launch_exclusive_scan(c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(), pl.ncounts, ctl + 1,
+                                 c->scan_tmp.as<uint32_t>(), st),
+           "counts scan");
+        ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
+        ck(hipStreamSynchronize(st), "sync after scan");
+        const uint32_t *h = c->pin_ctl.as<uint32_t>();
+        if (h[0] > c->cap) {  // an item overflowed its record buffer: grow and rescan
+            c->cap = pow2_at_least(h[0]);
+            continue;
+        }
+        raw_total = h[1];
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->stats.scan_ms += ms;
+        break;
+    }
+
+    const uint32_t n = raw_total;
+    const uint32_t hks = c->hks;
+    const uint32_t out_stride = c->kmax + 1;
+    c->r_pat.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->r_sl.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->r_end.ensure(std::max<uint32_t>(n, 1) * 8ull, st);
+    c->r_flag.ensure(std::max<uint32_t>(n, 1), st);
+    c->r_dist.ensure(std::max<uint32_t>(n, 1), st);
+    c->r_hk.ensure(std::max<uint32_t>(n, 1) * (uint64_t)hks, st);
+    c->seg_cnt.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->seg_off.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->carry_flag.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->carry_off.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->carry_rank.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->carry_len.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
+    c->seg_out.ensure(std::max<uint64_t>(n, 1) * out_stride * sizeof(OccRec), st);
+    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint32_t>(n, 1)) * 4, 1024), st);
+
+    uint32_t item_base = 0;
+    for (const ClassInfo &ci : c->classes) {
+        ck(launch_scatter(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
+                          c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(), c->item_cnt.as<uint32_t>(),
+                          item_base, c->cap, c->offsets.as<uint32_t>(), d_cstream, c->r_pat.as<uint32_t>(),
+                          c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(), st),
+           "scatter");
+        item_base += nchunks * ci.ntiles;
+    }
+    ck(launch_carry_place(d_carry, d_carry_hk, ncarry, hks, d_s2l, d_sbase, d_sstride, c->offsets.as<uint32_t>(),
+                          c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                          c->r_flag.as<uint8_t>(), c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), st),
+       "carry place");
+    ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                      c->r_flag.as<uint8_t>(), n, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
+                      c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
+       "recover");
+    const uint32_t do_filter = c->rules == OASM_RULES_PAPER ? 1u : 0u;
+    ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_hk.as<uint8_t>(),
+                     n, hks, c->d_pats.as<PatDesc>(), d_sdesc, do_filter, out_stride, c->seg_out.as<OccRec>(),
+                     c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), c->carry_rank.as<uint32_t>(),
+                     c->carry_len.as<uint32_t>(), st),
+       "filter");
+    ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), n, ctl + 2,
+                             c->scan_tmp.as<uint32_t>(), st),
+       "occ scan");
+    ck(launch_exclusive_scan(c->carry_flag.as<uint32_t>(), c->carry_off.as<uint32_t>(), n, ctl + 3,
+                             c->scan_tmp.as<uint32_t>(), st),
+       "carry scan");
+    ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
+    ck(hipStreamSynchronize(st), "sync after filter");
+    const uint32_t *h = c->pin_ctl.as<uint32_t>();
+    const uint32_t nocc = h[2], ncarry_out = h[3], rec_err = h[4];
+    if (rec_err) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
+
+    c->occ_out.ensure(std::max<uint32_t>(nocc, 1) * sizeof(OccRec), st);
+    c->carry_out.ensure(std::max<uint32_t>(ncarry_out, 1) * sizeof(CarryRec), st);
+    c->carry_out_hk.ensure(std::max<uint32_t>(ncarry_out, 1) * (uint64_t)hks, st);
+    ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), n,
+                          out_stride, c->occ_out.as<OccRec>(), st),
+       "compact occ");
+    ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                            c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
+                            c->carry_off.as<uint32_t>(), c->carry_rank.as<uint32_t>(), c->carry_len.as<uint32_t>(),
+                            d_sdesc, n, c->carry_out.as<CarryRec>(), c->carry_out_hk.as<uint8_t>(), st),
+       "compact carry");
+
+    // copy back: raw (pat, sl, end, flag, dist), hk (when kept), occurrences, carry
+    const bool keep_raw = !(c->cfg.flags & OASM_CFG_NO_RAW);
+    const bool keep_h = (c->cfg.flags & OASM_CFG_KEEP_H) != 0;
+    size_t off = 0;
+    auto slot = [&](size_t bytes) {
+        size_t o = (off + 255) & ~size_t(255);
+        off = o + bytes;
+        return o;
+    };
+    const size_t need_raw = keep_raw || keep_h;
+    const size_t o_pat = slot(need_raw ? n * 4ull : 0), o_sl = slot(need_raw ? n * 4ull : 0);
+    const size_t o_end = slot(need_raw ? n * 8ull : 0), o_flag = slot(need_raw ? n : 0);
+    const size_t o_dist = slot(need_raw ? n : 0), o_hk = slot(keep_h ? (size_t)n * hks : 0);
+    const size_t o_occ = slot((size_t)nocc * sizeof(OccRec));
+    const size_t o_cr = slot((size_t)ncarry_out * sizeof(CarryRec));
+    const size_t o_chk = slot((size_t)ncarry_out * hks);
+    c->pin_out.ensure(off + 256, st);
+    uint8_t *hp = c->pin_out.as<uint8_t>();
+    auto d2h = [&](size_t o, const void *src, size_t bytes) {
+        if (bytes) ck(hipMemcpyAsync(hp + o, src, bytes, hipMemcpyDeviceToHost, st), "result d2h");
+    };
+    if (need_raw) {
+        d2h(o_pat, c->r_pat.p, n * 4ull);
+        d2h(o_sl, c->r_sl.p, n * 4ull);
+        d2h(o_end, c->r_end.p, n * 8ull);
+        d2h(o_flag, c->r_flag.p, n);
+        d2h(o_dist, c->r_dist.p, n);
+    }
+    if (keep_h) d2h(o_hk, c->r_hk.p, (size_t)n * hks);
+    d2h(o_occ, c->occ_out.p, (size_t)nocc * sizeof(OccRec));
+    d2h(o_cr, c->carry_out.p, (size_t)ncarry_out * sizeof(CarryRec));
+    d2h(o_chk, c->carry_out_hk.p, (size_t)ncarry_out * hks);
+    ck(hipEventRecord(c->ev2, st), "event");
+    ck(hipStreamSynchronize(st), "sync after copy-back");
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += ms;
+
+    // host bookkeeping: queue results
+    const uint32_t *hpat = reinterpret_cast<const uint32_t *>(hp + o_pat);
+    const uint32_t *hsl = reinterpret_cast<const uint32_t *>(hp + o_sl);
+    const uint64_t *hend = reinterpret_cast<const uint64_t *>(hp + o_end);
+    const uint8_t *hflag = hp + o_flag;
+    const uint8_t *hdist = hp + o_dist;
+    const uint8_t *hhk = hp + o_hk;
+    uint64_t new_raw = 0;
+    if (need_raw) {
+        for (uint32_t i = 0; i < n; ++i) {
+            if (hflag[i]) continue;  // carried from an earlier step: reported there
+            ++new_raw;
+            const uint64_t sid = c->streams[pl.locals[hsl[i]]].id;
+            if (keep_raw) c->q_raw.push_back(oasm_hit{sid, hend[i], hpat[i], hdist[i]});
+            if (keep_h) {
+                const uint32_t p = hpat[i];
+                const int m = c->m[p], K = c->k[p];
+                for (int l = std::max(1, m - K); l <= m + K; ++l) {
+                    const uint8_t kk = hhk[(size_t)i * hks + (l - (m - K))];
+                    if (kk == kNoHit) continue;
+                    c->q_h.push_back(oasm_occ{sid, hend[i] + 1 - (uint64_t)l, p, (uint32_t)l, kk, 0});
+                }
+            }
+        }
+    } else {
+        new_raw = n - ncarry;
+    }
+    if (keep_h) {  // hit set in (stream, pattern, start, length) order within this step
+        // records were appended per end; restore start order for the step's new part
+    }
+    const OccRec *ho = reinterpret_cast<const OccRec *>(hp + o_occ);
+    for (uint32_t i = 0; i < nocc; ++i) {
+        const uint64_t sid = c->streams[pl.locals[ho[i].stream_local]].id;
+        c->q_occ.push_back(oasm_occ{sid, ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
+    }
+    // new carry, per stream
+    for (uint32_t si : pl.locals) {
+        c->streams[si].carry.clear();
+        c->streams[si].carry_hk.clear();
+    }
+    const CarryRec *hc = reinterpret_cast<const CarryRec *>(hp + o_cr);
+    const uint8_t *hck = hp + o_chk;
+    for (uint32_t i = 0; i < ncarry_out; ++i) {
+        const uint32_t sslot = hc[i].stream_slot;
+        StreamState &s = c->streams[sslot];
+        s.carry.push_back(hc[i]);
+        s.carry_hk.insert(s.carry_hk.end(), hck + (size_t)i * hks, hck + (size_t)(i + 1) * hks);
+    }
+    // stream bookkeeping: keep a look-back tail of each stream's symbols
+    for (uint32_t si : pl.locals) {
+        StreamState &s = c->streams[si];
+        c->stats.bytes_scanned += s.valid - s.scanned;
+        s.scanned = s.valid;
+        if (s.close_pending) {
+            s.close_pending = false;
+            s.closed = true;
+            c->staged_bytes -= s.cap;
+            if (s.sym) ck(hipFree(s.sym), "hipFree staging");
+            s.sym = nullptr;
+            s.cap = 0;
+            s.valid = s.scanned = 0;
+            s.carry.clear();
+            s.carry_hk.clear();
+            continue;
+        }
+        const size_t keep = std::min<size_t>(s.valid, c->lookback + 4);
+        if (keep < s.valid) {
+            const size_t drop = s.valid - keep;
+            // move the tail to the front (through the raw_in scratch when the ranges overlap)
+            if (drop >= keep) {
+                ck(hipMemcpyAsync(s.sym, s.sym + drop, keep, hipMemcpyDeviceToDevice, st), "tail move");
+            } else {
+                c->raw_in.ensure(keep + kPad, st);
+                ck(hipMemcpyAsync(c->raw_in.p, s.sym + drop, keep, hipMemcpyDeviceToDevice, st), "tail move");
+                ck(hipMemcpyAsync(s.sym, c->raw_in.p, keep, hipMemcpyDeviceToDevice, st), "tail move");
+            }
+            s.base_abs += drop;
+            s.valid = s.scanned = keep;
+        }
+    }
+    c->stats.raw_hits += new_raw;
+    c->stats.occurrences += nocc;
+    c->stats.syncs++;
+    c->pin_feed_used = 0;
+}
+
+void sort_h_queue_tail(oasm_ctx *c, size_t from) {
+    std::stable_sort(c->q_h.begin() + (ptrdiff_t)from, c->q_h.end(), [](const oasm_occ &a, const oasm_occ &b) {
+        if (a.stream != b.stream) return a.stream < b.stream;
+        if (a.pattern != b.pattern) return a.pattern < b.pattern;
+        if (a.start != b.start) return a.start < b.start;
+        return a.len < b.len;
+    });
+}
+
+void sync_all(oasm_ctx *c) {
+    std::vector<uint32_t> which;
+    for (uint32_t i = 0; i < c->streams.size(); ++i) {
+        const StreamState &s = c->streams[i];
+        if (s.closed) continue;
+        if (s.valid > s.scanned || s.close_pending) which.push_back(i);
+    }
+    if (which.empty()) return;
+    const size_t h0 = c->q_h.size();
+    if (c->cfg.flags & OASM_CFG_PLAIN) {
+        for (uint32_t si : which) run_step(c, std::vector<uint32_t>{si});
+    } else {
+        run_step(c, which);
+    }
+    if (c->cfg.flags & OASM_CFG_KEEP_H) sort_h_queue_tail(c, h0);
+}
+
+StreamState &get_stream(oasm_ctx *c, uint64_t id, bool create) {
+    auto it = c->slot_of.find(id);
+    if (it != c->slot_of.end()) return c->streams[it->second];
+    if (!create) throw std::out_of_range("stream");
+    const uint32_t slot = (uint32_t)c->streams.size();
+    c->streams.emplace_back();
+    StreamState &s = c->streams.back();
+    s.id = id;
+    s.slot = slot;
+    c->slot_of[id] = slot;
+    return s;
+}
+
+// Make room for `n` more symbols in a stream's staging buffer.
+oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n) {
+    const size_t need = s.valid + n + kPad;
+    if (need <= s.cap) return OASM_OK;
+    size_t want = std::max(need, s.cap + s.cap / 2);
+    want = (want + 255) & ~size_t(255);
+    if (c->cfg.device_mem_budget && c->staged_bytes - s.cap + want > c->cfg.device_mem_budget)
+        return fail(c, OASM_E_AGAIN, "device memory budget for staged stream data exhausted");
+    uint8_t *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, OASM_E_NOMEM, "hipMalloc for stream staging failed");
+    }
+    // every byte of a staging buffer is a valid symbol class: the scan's last
+    // group reads up to 8 symbols past the end before masking their ends out
+    ck(hipMemsetAsync(p, 0, want, c->st), "staging clear");
+    if (s.sym) {
+        if (s.valid) ck(hipMemcpyAsync(p, s.sym, s.valid, hipMemcpyDeviceToDevice, c->st), "staging grow");
+        ck(hipStreamSynchronize(c->st), "staging grow sync");
+        ck(hipFree(s.sym), "hipFree staging");
+    }
+    c->staged_bytes += want - s.cap;
+    s.sym = p;
+    s.cap = want;
+    return OASM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+oasm_status oasm_config_init(oasm_config *cfg) {
+    if (!cfg) return OASM_E_INVAL;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->struct_size = sizeof(oasm_config);
+    cfg->device = -1;
+    return OASM_OK;
+}
+
+const char *oasm_status_str(oasm_status s) {
+    switch (s) {
+        case OASM_OK: return "OASM_OK";
+        case OASM_E_INVAL: return "OASM_E_INVAL";
+        case OASM_E_NOMEM: return "OASM_E_NOMEM";
+        case OASM_E_AGAIN: return "OASM_E_AGAIN";
+        case OASM_E_CLOSED: return "OASM_E_CLOSED";
+        case OASM_E_DEVICE: return "OASM_E_DEVICE";
+        default: return "OASM_E_UNKNOWN";
+    }
+}
+
+static thread_local std::string g_create_error;
+
+oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k, uint16_t k_all, uint32_t rules,
+                        const oasm_config *cfg, oasm_ctx **out) {
+    if (!out) return OASM_E_INVAL;
+    *out = nullptr;
+    if (!dict || n == 0) {
+        g_create_error = "empty dictionary";
+        return OASM_E_INVAL;
+    }
+    if (rules != OASM_RULES_NONE && rules != OASM_RULES_PAPER) {
+        g_create_error = "unknown rules";
+        return OASM_E_INVAL;
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        const uint32_t len = dict[i].len;
+        const uint32_t kk = k ? k[i] : k_all;
+        if (!dict[i].bytes || len == 0 || len > OASM_MAX_PATTERN_LEN || kk >= len || kk > 63) {
+            g_create_error = "pattern " + std::to_string(i) + ": need 1 <= len <= 256, K < len and K <= 63";
+            return OASM_E_INVAL;
+        }
+    }
+    oasm_ctx *c = new (std::nothrow) oasm_ctx();
+    if (!c) return OASM_E_NOMEM;
+    if (cfg) {
+        c->cfg = *cfg;
+    } else {
+        oasm_config_init(&c->cfg);
+    }
+    c->rules = rules;
+    try {
+        if (c->cfg.device >= 0) ck(hipSetDevice(c->cfg.device), "hipSetDevice");
+        ck(hipGetDevice(&c->device), "hipGetDevice");
+        if (c->cfg.hip_stream) {
+            c->st = reinterpret_cast<hipStream_t>(c->cfg.hip_stream);
+        } else {
+            ck(hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking), "hipStreamCreate");
+            c->own_stream = true;
+        }
+        ck(hipEventCreate(&c->ev0), "event");
+        ck(hipEventCreate(&c->ev1), "event");
+        ck(hipEventCreate(&c->ev2), "event");
+        ck(hipEventCreate(&c->ev3), "event");
+        hipStream_t st = c->st;
+
+        // dictionary on the host: lengths, thresholds, symbol classes
+        c->npat = n;
+        c->m.resize(n);
+        c->k.resize(n);
+        bool used[256] = {false};
+        std::vector<uint8_t> bytes;
+        std::vector<PatDesc> pd(n);
+        uint64_t rpeq_words = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            c->m[i] = (uint16_t)dict[i].len;
+            c->k[i] = k ? k[i] : k_all;
+            c->mmax = std::max<uint32_t>(c->mmax, c->m[i]);
+            c->kmax = std::max<uint32_t>(c->kmax, c->k[i]);
+            c->msum += c->m[i];
+            pd[i].off = (uint32_t)bytes.size();
+            pd[i].m = c->m[i];
+            pd[i].k = c->k[i];
+            pd[i].w64 = (uint16_t)((c->m[i] + 63) / 64);
+            bytes.insert(bytes.end(), dict[i].bytes, dict[i].bytes + dict[i].len);
+            for (uint32_t j = 0; j < dict[i].len; ++j) used[dict[i].bytes[j]] = true;
+        }
+        // classes: class 0 collects bytes no pattern uses (when there are any)
+        uint32_t nused = 0;
+        for (int b = 0; b < 256; ++b) nused += used[b];
+        uint32_t next = nused < 256 ? 1 : 0;
+        for (int b = 0; b < 256; ++b) c->class_of[b] = used[b] ? (uint8_t)(next++) : 0;
+        c->nclass = next;
+        for (uint32_t i = 0; i < n; ++i) {
+            pd[i].rpeq_off = (uint32_t)rpeq_words;
+            rpeq_words += (uint64_t)pd[i].w64 * c->nclass;
+        }
+        c->hks = 2 * c->kmax + 1;
+        c->lookback = c->mmax + c->kmax - 1;
+
+        // tiles: group patterns by 32-bit word count, choose patterns per lane
+        std::vector<std::vector<uint32_t>> byw(kMaxW32 + 1);
+        for (uint32_t i = 0; i < n; ++i) byw[(c->m[i] + 31) / 32].push_back(i);
+        std::vector<TileDesc> tiles;
+        std::vector<uint32_t> tile_wp, slot_pat, pat_tile(n), pat_slot(n);
+        uint64_t img_words = 0;
+        for (int W = 1; W <= kMaxW32; ++W) {
+            const auto &ids = byw[W];
+            if (ids.empty()) continue;
+            int P = 1;
+            if (W == 1) P = ids.size() > 128 ? 4 : (ids.size() > 64 ? 2 : 1);
+            if (W == 2) P = ids.size() > 64 ? 2 : 1;
+            ClassInfo ci;
+            ci.W = W;
+            ci.P = P;
+            ci.tile_first = (uint32_t)tiles.size();
+            const uint32_t per = 64u * P;
+            const uint32_t pws = (uint32_t)(P * W <= 1 ? 1 : P * W <= 2 ? 2 : P * W <= 4 ? 4 : 8);
+            const uint64_t img_bytes = (uint64_t)c->nclass * 64 * pws * 4;
+            ci.lds = img_bytes <= 64 * 1024;
+            ci.waves = 4;
+            for (size_t t0 = 0; t0 < ids.size(); t0 += per) {
+                TileDesc td;
+                td.peq_off = (uint32_t)img_words;
+                td.slot_off = (uint32_t)slot_pat.size();
+                td.n_active = (uint32_t)std::min<size_t>(per, ids.size() - t0);
+                td.pad = 0;
+                for (uint32_t s = 0; s < td.n_active; ++s) {
+                    const uint32_t pid = ids[t0 + s];
+                    slot_pat.push_back(pid);
+                    pat_tile[pid] = (uint32_t)tiles.size();
+                    pat_slot[pid] = s;
+                }
+                tiles.push_back(td);
+                tile_wp.push_back((uint32_t)W | ((uint32_t)P << 8));
+                img_words += (uint64_t)c->nclass * 64 * pws;
+            }
+            ci.ntiles = (uint32_t)tiles.size() - ci.tile_first;
+            c->classes.push_back(ci);
+        }
+        c->ntiles = (uint32_t)tiles.size();
+
+        auto upload = [&](DevBuf &d, const void *src, size_t bytes) {
+            d.ensure(std::max<size_t>(bytes, 16), st);
+            if (bytes) ck(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st), "dictionary upload");
+        };
+        upload(c->d_patbytes, bytes.data(), bytes.size());
+        upload(c->d_pats, pd.data(), pd.size() * sizeof(PatDesc));
+        upload(c->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc));
+        upload(c->d_tile_wp, tile_wp.data(), tile_wp.size() * 4);
+        upload(c->d_slot_pat, slot_pat.data(), slot_pat.size() * 4);
+        upload(c->d_pat_tile, pat_tile.data(), pat_tile.size() * 4);
+        upload(c->d_pat_slot, pat_slot.data(), pat_slot.size() * 4);
+        upload(c->d_class, c->class_of, 256);
+        c->d_peq.ensure(std::max<uint64_t>(img_words * 4, 16), st);
+        c->d_rpeq.ensure(std::max<uint64_t>(rpeq_words * 8, 16), st);
+        ck(launch_fill_u32(c->d_peq.as<uint32_t>(), 0, img_words, st), "fill peq");
+        ck(launch_peq_build(c->d_patbytes.as<uint8_t>(), c->d_pats.as<PatDesc>(), n, c->d_pat_tile.as<uint32_t>(),
+                            c->d_pat_slot.as<uint32_t>(), c->d_tiles.as<TileDesc>(), c->d_tile_wp.as<uint32_t>(),
+                            c->d_class.as<uint8_t>(), c->nclass, c->d_peq.as<uint32_t>(), c->d_rpeq.as<uint64_t>(),
+                            st),
+           "peq build");
+        ck(hipStreamSynchronize(st), "create sync");
+    } catch (const HipFail &f) {
+        g_create_error = std::string(f.what) + ": " + hipGetErrorString(f.e);
+        oasm_destroy(c);
+        return OASM_E_DEVICE;
+    } catch (const std::bad_alloc &) {
+        oasm_destroy(c);
+        return OASM_E_NOMEM;
+    }
+    *out = c;
+    return OASM_OK;
+}
+
+static oasm_status feed_common(oasm_ctx *c, uint64_t stream_id, const void *src, size_t n, bool device,
+                               void *user_stream, uint32_t flags) {
+    if (!c) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (n > 0 && !src) return fail(c, OASM_E_INVAL, "NULL bytes with n > 0");
+    if (n > (size_t(1) << 31)) return fail(c, OASM_E_INVAL, "feed larger than 2 GiB");
+    try {
+        if (device) ck(hipSetDevice(c->device), "hipSetDevice");
+        StreamState &s = get_stream(c, stream_id, true);
+        if (s.closed || s.close_pending) return fail(c, OASM_E_CLOSED, "feed to a closed stream");
+        if (n > 0) {
+            oasm_status r = reserve_stream(c, s, n);
+            if (r != OASM_OK) return r;
+            if (device) {
+                hipStream_t us = reinterpret_cast<hipStream_t>(user_stream);
+                if (us != c->st) {
+                    ck(hipEventRecord(c->ev3, us), "feed event");
+                    ck(hipStreamWaitEvent(c->st, c->ev3, 0), "feed wait");
+                }
+                ck(launch_map_symbols(reinterpret_cast<const uint8_t *>(src), s.sym + s.valid, n,
+                                      c->d_class.as<uint8_t>(), c->st),
+                   "map symbols");
+            } else {
+                // copy into pinned memory (the caller may reuse its buffer), then H2D + map
+                if (c->pin_feed_used + n > c->pin_feed.cap) {
+                    ck(hipStreamSynchronize(c->st), "feed sync");
+                    c->pin_feed_used = 0;
+                    c->pin_feed.ensure(n, c->st);
+                }
+                uint8_t *hp = c->pin_feed.as<uint8_t>() + c->pin_feed_used;
+                std::memcpy(hp, src, n);
+                c->pin_feed_used += n;
+                c->raw_in.ensure(n + kPad, c->st);
+                ck(hipMemcpyAsync(c->raw_in.p, hp, n, hipMemcpyHostToDevice, c->st), "feed h2d");
+                ck(launch_map_symbols(c->raw_in.as<uint8_t>(), s.sym + s.valid, n, c->d_class.as<uint8_t>(), c->st),
+                   "map symbols");
+            }
+            s.valid += n;
+            c->stats.cells += (uint64_t)n * c->msum;
+            uint64_t ws = 0;
+            for (const ClassInfo &ci : c->classes) (void)ci;
+            for (uint32_t i = 0; i < c->npat; ++i) ws += (c->m[i] + 31) / 32;
+            c->stats.word_steps += (uint64_t)n * ws;
+        }
+        if (flags & OASM_FEED_LAST) s.close_pending = true;
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
+    } catch (const std::bad_alloc &) {
+        return fail(c, OASM_E_NOMEM, "host allocation failed");
+    }
+    return OASM_OK;
+}
+
+oasm_status oasm_feed(oasm_ctx *c, uint64_t stream_id, const uint8_t *bytes, size_t n, uint32_t flags) {
+    return feed_common(c, stream_id, bytes, n, false, nullptr, flags);
+}
+
+oasm_status oasm_feed_device(oasm_ctx *c, uint64_t stream_id, const void *dev, size_t n, void *hip_stream,
+                             uint32_t flags) {
+    return feed_common(c, stream_id, dev, n, true, hip_stream, flags);
+}
+
+oasm_status oasm_close_stream(oasm_ctx *c, uint64_t stream_id) {
+    if (!c) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    auto it = c->slot_of.find(stream_id);
+    if (it == c->slot_of.end()) return fail(c, OASM_E_INVAL, "unknown stream");
+    StreamState &s = c->streams[it->second];
+    if (s.closed || s.close_pending) return fail(c, OASM_E_INVAL, "stream already closed");
+    s.close_pending = true;
+    return OASM_OK;
+}
+
+oasm_status oasm_sync(oasm_ctx *c) {
+    if (!c) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        sync_all(c);
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
+    } catch (const std::bad_alloc &) {
+        return fail(c, OASM_E_NOMEM, "host allocation failed");
+    }
+    return OASM_OK;
+}
+
+oasm_status oasm_hits(oasm_ctx *c, uint32_t kind, void *out, size_t cap, size_t *n_out, int *more) {
+    if (!c || !n_out || (cap > 0 && !out)) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    *n_out = 0;
+    if (kind == OASM_RAW) {
+        const size_t avail = c->q_raw.size() - c->rd_raw;
+        const size_t take = std::min(avail, cap);
+        if (take) std::memcpy(out, c->q_raw.data() + c->rd_raw, take * sizeof(oasm_hit));
+        c->rd_raw += take;
+        *n_out = take;
+        if (more) *more = avail > take;
+        if (c->rd_raw == c->q_raw.size()) {
+            c->q_raw.clear();
+            c->rd_raw = 0;
+        }
+        return OASM_OK;
+    }
+    if (kind == OASM_FILTERED || kind == OASM_H) {
+        std::vector<oasm_occ> &q = kind == OASM_FILTERED ? c->q_occ : c->q_h;
+        size_t &rd = kind == OASM_FILTERED ? c->rd_occ : c->rd_h;
+        if (kind == OASM_H && !(c->cfg.flags & OASM_CFG_KEEP_H))
+            return fail(c, OASM_E_INVAL, "OASM_H needs OASM_CFG_KEEP_H");
+        const size_t avail = q.size() - rd;
+        const size_t take = std::min(avail, cap);
+        if (take) std::memcpy(out, q.data() + rd, take * sizeof(oasm_occ));
+        rd += take;
+        *n_out = take;
+        if (more) *more = avail > take;
+        if (rd == q.size()) {
+            q.clear();
+            rd = 0;
+        }
+        return OASM_OK;
+    }
+    return fail(c, OASM_E_INVAL, "unknown drain kind");
+}
+
+oasm_status oasm_get_stats(const oasm_ctx *c, oasm_stats *out) {
+    if (!c || !out) return OASM_E_INVAL;
+    *out = c->stats;
+    return OASM_OK;
+}
+
+void oasm_destroy(oasm_ctx *c) {
+    if (!c) return;
+    if (c->st) (void)hipStreamSynchronize(c->st);
+    for (auto &s : c->streams)
+        if (s.sym) (void)hipFree(s.sym);
+    DevBuf *bufs[] = {&c->d_pats, &c->d_slot_pat, &c->d_tiles, &c->d_peq, &c->d_rpeq, &c->d_class, &c->d_patbytes,
+                      &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->counts, &c->offsets,
+                      &c->item_rec, &c->item_cnt, &c->ctl, &c->scan_tmp, &c->r_pat, &c->r_sl, &c->r_end,
+                      &c->r_flag, &c->r_dist, &c->r_hk, &c->seg_cnt, &c->seg_off, &c->carry_flag, &c->carry_off,
+                      &c->carry_rank, &c->carry_len, &c->seg_out, &c->occ_out, &c->carry_out, &c->carry_out_hk,
+                      &c->carry_in, &c->carry_in_hk, &c->raw_in};
+    for (DevBuf *b : bufs) b->release();
+    c->pin_plan.release();
+    c->pin_ctl.release();
+    c->pin_out.release();
+    c->pin_feed.release();
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->ev2) (void)hipEventDestroy(c->ev2);
+    if (c->ev3) (void)hipEventDestroy(c->ev3);
+    if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
+    delete c;
+}
+
+const char *oasm_last_error(const oasm_ctx *c) {
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+}  // extern "C"

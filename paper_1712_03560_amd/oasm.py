@@ -1,0 +1,291 @@
+"""ctypes binding of liboasm_gpu (the C ABI in include/oasm_gpu.h).
+
+Argument marshalling only: every matching step runs in the library's HIP
+kernels.  The functions below carry the C names; :class:`Matcher` wraps a
+context for Python callers, and accepts numpy arrays, bytes, or torch tensors
+(host or device) as stream data.  PyTorch is used only to hand device memory
+and the current HIP stream to the library.
+
+The library must have been built (``paper_1712_03560_amd.build.build()``);
+importing this module without it raises ImportError, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboasm_gpu.so")
+
+OASM_OK = 0
+OASM_E_INVAL = -1
+OASM_E_NOMEM = -2
+OASM_E_AGAIN = -3
+OASM_E_CLOSED = -4
+OASM_E_DEVICE = -5
+
+OASM_RULES_NONE = 0
+OASM_RULES_PAPER = 1
+OASM_FEED_LAST = 1
+OASM_CFG_PLAIN = 1
+OASM_CFG_KEEP_H = 2
+OASM_CFG_NO_RAW = 4
+OASM_RAW = 0
+OASM_FILTERED = 1
+OASM_H = 2
+OASM_MAX_PATTERN_LEN = 256
+
+# every symbol the header declares (checked by the ABI test)
+EXPORTED = [
+    "oasm_config_init",
+    "oasm_create",
+    "oasm_feed",
+    "oasm_feed_device",
+    "oasm_close_stream",
+    "oasm_sync",
+    "oasm_hits",
+    "oasm_get_stats",
+    "oasm_destroy",
+    "oasm_last_error",
+    "oasm_status_str",
+]
+
+
+class oasm_pattern(ctypes.Structure):
+    _fields_ = [("bytes", ctypes.c_void_p), ("len", ctypes.c_uint32)]
+
+
+class oasm_hit(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_uint64), ("end", ctypes.c_uint64), ("pattern", ctypes.c_uint32),
+                ("dist", ctypes.c_uint32)]
+
+
+class oasm_occ(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_uint64), ("start", ctypes.c_uint64), ("pattern", ctypes.c_uint32),
+                ("len", ctypes.c_uint32), ("k", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class oasm_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("device", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
+                ("chunk_bytes", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("device_mem_budget", ctypes.c_uint64)]
+
+
+class oasm_stats(ctypes.Structure):
+    _fields_ = [("bytes_scanned", ctypes.c_uint64), ("word_steps", ctypes.c_uint64), ("cells", ctypes.c_uint64),
+                ("raw_hits", ctypes.c_uint64), ("h_records", ctypes.c_uint64), ("occurrences", ctypes.c_uint64),
+                ("syncs", ctypes.c_uint64), ("scan_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
+                ("scan_launches", ctypes.c_uint64)]
+
+
+HIT_DTYPE = np.dtype([("stream", "<u8"), ("end", "<u8"), ("pattern", "<u4"), ("dist", "<u4")])
+OCC_DTYPE = np.dtype([("stream", "<u8"), ("start", "<u8"), ("pattern", "<u4"), ("len", "<u4"), ("k", "<u4"),
+                      ("reserved", "<u4")])
+assert HIT_DTYPE.itemsize == ctypes.sizeof(oasm_hit) == 24
+assert OCC_DTYPE.itemsize == ctypes.sizeof(oasm_occ) == 32
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1712_03560_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32
+    sz = ctypes.c_size_t
+    lib.oasm_config_init.argtypes = [ctypes.POINTER(oasm_config)]
+    lib.oasm_config_init.restype = i32
+    lib.oasm_create.argtypes = [ctypes.POINTER(oasm_pattern), u32, P, ctypes.c_uint16, u32,
+                                ctypes.POINTER(oasm_config), ctypes.POINTER(P)]
+    lib.oasm_create.restype = i32
+    lib.oasm_feed.argtypes = [P, u64, P, sz, u32]
+    lib.oasm_feed.restype = i32
+    lib.oasm_feed_device.argtypes = [P, u64, P, sz, P, u32]
+    lib.oasm_feed_device.restype = i32
+    lib.oasm_close_stream.argtypes = [P, u64]
+    lib.oasm_close_stream.restype = i32
+    lib.oasm_sync.argtypes = [P]
+    lib.oasm_sync.restype = i32
+    lib.oasm_hits.argtypes = [P, u32, P, sz, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_int)]
+    lib.oasm_hits.restype = i32
+    lib.oasm_get_stats.argtypes = [P, ctypes.POINTER(oasm_stats)]
+    lib.oasm_get_stats.restype = i32
+    lib.oasm_destroy.argtypes = [P]
+    lib.oasm_destroy.restype = None
+    lib.oasm_last_error.argtypes = [P]
+    lib.oasm_last_error.restype = ctypes.c_char_p
+    lib.oasm_status_str.argtypes = [i32]
+    lib.oasm_status_str.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+class OasmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{lib.oasm_status_str(status).decode()}: {msg}")
+        self.status = status
+
+
+# ------------------------------------------------------------- C-named calls
+def oasm_config_init() -> oasm_config:
+    cfg = oasm_config()
+    lib.oasm_config_init(ctypes.byref(cfg))
+    return cfg
+
+
+def oasm_create(patterns, k, rules: int = OASM_RULES_PAPER, cfg: oasm_config | None = None) -> int:
+    """Create a context; ``k`` is an int (all patterns) or a sequence."""
+    pats = [bytes(p) for p in patterns]
+    n = len(pats)
+    bufs = [ctypes.create_string_buffer(p, len(p)) for p in pats]
+    arr = (oasm_pattern * max(n, 1))()
+    for i, b in enumerate(bufs):
+        arr[i].bytes = ctypes.cast(b, ctypes.c_void_p)
+        arr[i].len = len(pats[i])
+    if np.isscalar(k):
+        kptr, kall = None, int(k)
+    else:
+        karr = np.ascontiguousarray(k, dtype=np.uint16)
+        if karr.size != n:
+            raise ValueError("one K per pattern")
+        kptr, kall = karr.ctypes.data_as(ctypes.c_void_p), 0
+    out = ctypes.c_void_p()
+    st = lib.oasm_create(arr, n, kptr, kall, rules, ctypes.byref(cfg) if cfg is not None else None,
+                         ctypes.byref(out))
+    if st != OASM_OK:
+        raise OasmError(st, lib.oasm_last_error(None).decode())
+    return out.value
+
+
+def _check(ctx, st):
+    if st != OASM_OK:
+        raise OasmError(st, lib.oasm_last_error(ctx).decode())
+
+
+def oasm_feed(ctx, stream_id: int, data, flags: int = 0):
+    a = np.ascontiguousarray(np.frombuffer(data, dtype=np.uint8) if isinstance(data, (bytes, bytearray)) else data,
+                             dtype=np.uint8)
+    _check(ctx, lib.oasm_feed(ctx, stream_id, a.ctypes.data_as(ctypes.c_void_p) if a.size else None, a.size, flags))
+
+
+def oasm_feed_device(ctx, stream_id: int, ptr: int, n: int, hip_stream: int | None, flags: int = 0):
+    _check(ctx, lib.oasm_feed_device(ctx, stream_id, ptr, n, hip_stream, flags))
+
+
+def oasm_close_stream(ctx, stream_id: int):
+    _check(ctx, lib.oasm_close_stream(ctx, stream_id))
+
+
+def oasm_sync(ctx):
+    _check(ctx, lib.oasm_sync(ctx))
+
+
+def oasm_hits(ctx, kind: int, batch: int = 1 << 16) -> np.ndarray:
+    """Drain every queued record of ``kind`` into a structured numpy array."""
+    dt = HIT_DTYPE if kind == OASM_RAW else OCC_DTYPE
+    parts = []
+    while True:
+        buf = np.empty(batch, dtype=dt)
+        n = ctypes.c_size_t(0)
+        more = ctypes.c_int(0)
+        _check(ctx, lib.oasm_hits(ctx, kind, buf.ctypes.data_as(ctypes.c_void_p), batch, ctypes.byref(n),
+                                  ctypes.byref(more)))
+        parts.append(buf[: n.value])
+        if not more.value:
+            break
+    return np.concatenate(parts) if len(parts) > 1 else parts[0]
+
+
+def oasm_get_stats(ctx) -> dict:
+    s = oasm_stats()
+    _check(ctx, lib.oasm_get_stats(ctx, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in oasm_stats._fields_}
+
+
+def oasm_destroy(ctx):
+    if ctx:
+        lib.oasm_destroy(ctx)
+
+
+def oasm_last_error(ctx) -> str:
+    return lib.oasm_last_error(ctx).decode()
+
+
+# ------------------------------------------------------------- Python wrapper
+@dataclass
+class Results:
+    raw: np.ndarray  # HIT_DTYPE
+    occ: np.ndarray  # OCC_DTYPE
+    h: np.ndarray | None = None  # OCC_DTYPE
+
+
+class Matcher:
+    """A dictionary of patterns matched against any number of streams."""
+
+    def __init__(self, patterns, k, rules: int = OASM_RULES_PAPER, *, plain: bool = False, keep_h: bool = False,
+                 no_raw: bool = False, chunk_bytes: int = 0, hip_stream: int | None = None, device: int = -1,
+                 mem_budget: int = 0):
+        cfg = oasm_config_init()
+        cfg.device = device
+        cfg.chunk_bytes = chunk_bytes
+        cfg.flags = (OASM_CFG_PLAIN if plain else 0) | (OASM_CFG_KEEP_H if keep_h else 0) | (
+            OASM_CFG_NO_RAW if no_raw else 0)
+        cfg.device_mem_budget = mem_budget
+        cfg.hip_stream = hip_stream
+        self.keep_h = keep_h
+        self._device_refs = []  # device tensors fed since the last sync
+        self.ctx = oasm_create(patterns, k, rules, cfg)
+
+    def feed(self, stream_id: int, data, last: bool = False):
+        """Append bytes to a stream: bytes / numpy (host) or a torch uint8 tensor (host or device)."""
+        flags = OASM_FEED_LAST if last else 0
+        try:
+            import torch  # only for device buffers and streams
+        except ImportError:  # pragma: no cover
+            torch = None
+        if torch is not None and isinstance(data, torch.Tensor):
+            if data.dtype != torch.uint8 or not data.is_contiguous():
+                raise ValueError("stream tensors must be contiguous uint8")
+            if data.is_cuda:
+                hs = torch.cuda.current_stream(data.device).cuda_stream
+                oasm_feed_device(self.ctx, stream_id, data.data_ptr(), data.numel(), hs, flags)
+                self._device_refs.append(data)  # the library reads it until the next sync
+                return
+            data = data.numpy()
+        oasm_feed(self.ctx, stream_id, data, flags)
+
+    def close(self, stream_id: int):
+        oasm_close_stream(self.ctx, stream_id)
+
+    def sync(self):
+        oasm_sync(self.ctx)
+        self._device_refs.clear()
+
+    def results(self) -> Results:
+        raw = oasm_hits(self.ctx, OASM_RAW)
+        occ = oasm_hits(self.ctx, OASM_FILTERED)
+        h = oasm_hits(self.ctx, OASM_H) if self.keep_h else None
+        return Results(raw, occ, h)
+
+    def stats(self) -> dict:
+        return oasm_get_stats(self.ctx)
+
+    def destroy(self):
+        if self.ctx:
+            oasm_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
