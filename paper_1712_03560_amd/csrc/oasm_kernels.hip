@@ -102,48 +102,124 @@ __global__ void k_map_symbols(const uint8_t *__restrict__ src, uint8_t *__restri
     __shared__ uint8_t tab[256];
     if (threadIdx.x < 256) tab[threadIdx.x] = class_of[threadIdx.x];
     __syncthreads();
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = tab[src[i]];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+        // both 16-byte aligned: one uint4 load and store per 16 symbols
+        const uint64_t nv = n / 16;
+        const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+        uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+        for (uint64_t i = tid; i < nv; i += stride) {
+            uint4 v = s4[i];
+            uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t x = w[q];
+                w[q] = (uint32_t)tab[x & 0xFF] | ((uint32_t)tab[(x >> 8) & 0xFF] << 8) |
+                       ((uint32_t)tab[(x >> 16) & 0xFF] << 16) | ((uint32_t)tab[x >> 24] << 24);
+            }
+            d4[i] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+        for (uint64_t i = nv * 16 + tid; i < n; i += stride) dst[i] = tab[src[i]];
+    } else {
+        for (uint64_t i = tid; i < n; i += stride) dst[i] = tab[src[i]];
+    }
 }
 
 hipError_t launch_map_symbols(const uint8_t *src, uint8_t *dst, uint64_t n, const uint8_t *class_of, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    uint64_t want = (n + 255) / 256;
-    uint32_t blocks = (uint32_t)(want < 16384 ? want : 16384);
+    const bool vec = (((uintptr_t)src | (uintptr_t)dst) & 15) == 0;
+    const uint64_t want = vec ? (n / 16 + 255) / 256 : (n + 255) / 256;
+    const uint32_t blocks = (uint32_t)(want < 8192 ? (want ? want : 1) : 8192);
     hipLaunchKernelGGL(k_map_symbols, dim3(blocks), dim3(256), 0, st, src, dst, n, class_of);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ K1
+// Truth-table operands of v_bitop3_b32: the result bit for inputs (a, b, c)
+// is bit (a*4 + b*2 + c) of the immediate.
+constexpr uint32_t TA = 0xF0, TB = 0xCC, TC = 0xAA;
+#define BITOP3(a, b, c, expr) __builtin_amdgcn_bitop3_b32((a), (b), (c), (uint32_t)((expr) & 0xFF))
+
+// (x << 1) | y as one v_lshl_or_b32 (register-only ALU instruction; the
+// compiler would otherwise split it to fuse the OR elsewhere and spend one
+// more instruction per word).
+__device__ __forceinline__ uint32_t shl1_or(uint32_t x, uint32_t y) {
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+
+// popcount(x) + acc as one v_bcnt_u32_b32 (register-only ALU instruction).
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 // One column step of the bit-parallel edit-distance recurrence for a
 // W-word column (search mode: a zero horizontal delta enters the first row).
-// pv/mv: vertical +1/-1 deltas; eq: rows whose pattern symbol equals the
-// text symbol.  With u = (eq & pv) + pv (carry through all W words):
-//   xh | pv = u | pv | eq,    ph = mv | ~(xh | pv),    mh = pv & (eq | ~u)
-//   pv' = (mh << 1) | ~(xv | (ph << 1)),    mv' = (ph << 1) & xv
-// where xv = eq | mv and the shifts carry across words.
+// pv: rows whose vertical delta is +1; cm: the complement of the rows whose
+// vertical delta is -1 (kept complemented because every use of it is inside
+// three-input logic, which absorbs the complement for free, and its
+// popcount then feeds the hit test without a NOT); eq: rows whose pattern
+// symbol equals the text symbol.  With mv = ~cm and u = (eq & pv) + pv
+// (carry through all W words) the horizontal deltas are
+//   ph = mv | ~(u | pv | eq),    mh = pv & (eq | ~u)
+// and, with ph2 / mh2 the deltas shifted one row down (across words),
+//   pv' = mh2 | ~(eq | mv | ph2),    mv' = ph2 & (eq | mv).
+// (Myers 1999 / Hyyro's formulation, rewritten for three-input logic: nine
+// VALU instructions per 32-bit word on gfx950.)
 template <int W>
-__device__ __forceinline__ void column_step(uint32_t (&pv)[W], uint32_t (&mv)[W], const uint32_t (&eq)[W]) {
-    uint32_t ph[W], mh[W], xv[W];
+__device__ __forceinline__ void column_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
+    uint32_t ph[W], mh[W];
     uint32_t carry = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        uint64_t s = (uint64_t)(eq[w] & pv[w]) + pv[w] + carry;
-        uint32_t u = (uint32_t)s;
-        carry = (uint32_t)(s >> 32);
-        xv[w] = eq[w] | mv[w];
-        ph[w] = mv[w] | ~(u | pv[w] | eq[w]);
-        mh[w] = pv[w] & (eq[w] | ~u);
+        const uint32_t x = eq[w] & pv[w];
+        uint32_t u;
+        if (W == 1) {
+            u = x + pv[w];
+        } else {
+            const uint64_t s = (uint64_t)x + pv[w] + carry;
+            u = (uint32_t)s;
+            carry = (uint32_t)(s >> 32);
+        }
+        const uint32_t o = u | pv[w] | eq[w];
+        ph[w] = BITOP3(cm[w], o, 0u, ~(TA & TB));           // ~cm | ~o
+        mh[w] = BITOP3(pv[w], eq[w], u, TA & (TB | ~TC));   // pv & (eq | ~u)
+    }
+    uint32_t npv[W], ncm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t ph2 = w == 0 ? ph[0] << 1 : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
+        const uint32_t t = BITOP3(eq[w], cm[w], ph2, ~(TA | ~TB | TC));  // ~(eq | ~cm | ph2)
+        npv[w] = w == 0 ? shl1_or(mh[0], t) : (__builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31) | t);
+        ncm[w] = BITOP3(ph2, eq[w], cm[w], ~(TA & (TB | ~TC)));        // ~(ph2 & (eq | ~cm))
     }
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-        uint32_t ph2 = w == 0 ? ph[0] << 1 : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
-        uint32_t mh2 = w == 0 ? mh[0] << 1 : __builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31);
-        mv[w] = ph2 & xv[w];
-        pv[w] = mh2 | ~(xv[w] | ph2);
+        pv[w] = npv[w];
+        cm[w] = ncm[w];
     }
 }
 
+// Last-row value D = popcount(pv) - popcount(mv) (the column sum of the
+// vertical deltas; wildcard rows contribute 0) = popcount(pv) + popcount(cm)
+// - 32W.  With bias = -32W - bound - 1 the result's sign bit is set exactly
+// when D <= bound.
+template <int W>
+__device__ __forceinline__ int32_t le_bound(const uint32_t (&pv)[W], const uint32_t (&cm)[W], uint32_t bias) {
+    uint32_t d = bias;
+#pragma unroll
+    for (int w = 0; w < W; ++w) d = bcnt_acc(cm[w], d);
+#pragma unroll
+    for (int w = 0; w < W; ++w) d = bcnt_acc(pv[w], d);
+    return (int32_t)d;
+}
+
+// Per-lane row of a tile image: P*W words padded to a power of two so that
+// one aligned LDS (or global) vector read fetches it.
 template <int N>
 struct alignas(N * 4 < 16 ? N * 4 : 16) Words {
     uint32_t v[N];
@@ -154,10 +230,12 @@ constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
 // K1.  Block = `waves` wavefronts sharing one tile (its match-mask image in
 // LDS, or read through the L1 when it does not fit); each wavefront scans
 // one chunk.  Lane l holds P patterns of W words (slots l, l+64, ...).
-// The text symbol is wave-uniform (scalar loads); every 4 symbols the hit
-// ballots are tested together, and only then does the wave branch to the
-// (rare) compaction path: per (symbol, pattern) a ballot, an mbcnt prefix and
-// one record per hit lane in the item's own buffer.
+// The text symbol is wave-uniform (scalar loads).  Hits are screened once per
+// group of 4 symbols: the last-row value moves by at most 1 per symbol, so
+// if D > K + 2 at the group's second symbol no symbol of the group is a hit.
+// Only when some lane passes the screen is the group replayed from its saved
+// start state with an exact test per symbol, and the hits are compacted with
+// a ballot and an mbcnt prefix into the item's own record buffer.
 template <int W, int P, bool LDSPEQ>
 __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
     extern __shared__ uint32_t lds_img[];
@@ -181,23 +259,26 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
     const uint32_t item = a.item_base + chunk * a.ntiles + tile_local;
     uint32_t *rec = a.item_rec + (size_t)item * a.cap;
 
-    uint32_t pv[P][W], mv[P][W], kk[P], pat[P], lanecnt[P];
-    uint64_t active[P];
+    // Inactive slots hold all-ones +1 deltas (D = 32W) and bounds of 0, so
+    // they never pass the screen or the exact test.  kk / k2 hold the biases
+    // of le_bound for the exact test (D <= K) and the screen (D <= K + 2).
+    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P], lanecnt[P];
+    bool act[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const uint32_t slot = p * kWave + lane;
-        const bool act = slot < td.n_active;
-        pat[p] = act ? a.slot_pat[td.slot_off + slot] : 0u;
+        act[p] = slot < td.n_active;
+        pat[p] = act[p] ? a.slot_pat[td.slot_off + slot] : 0u;
         const PatDesc d = a.pats[pat[p]];
-        kk[p] = d.k;
-        active[p] = __ballot(act);
+        kk[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k : 0u);
+        k2[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k + 2 : 0u);
         const int g = 32 * W - (int)d.m;  // wildcard rows below the pattern
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-            int lo = g - 32 * w;  // first pattern bit inside word w
-            uint32_t bits = lo <= 0 ? ~0u : (lo >= 32 ? 0u : (~0u << lo));
-            pv[p][w] = act ? bits : 0u;
-            mv[p][w] = 0u;
+            const int lo = g - 32 * w;  // first pattern bit inside word w
+            const uint32_t bits = lo <= 0 ? ~0u : (lo >= 32 ? 0u : (~0u << lo));
+            pv[p][w] = act[p] ? bits : ~0u;
+            mv[p][w] = ~0u;  // complemented: no -1 deltas
         }
         lanecnt[p] = 0;
     }
@@ -212,41 +293,39 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
     for (uint32_t pos = 0; pos < len; pos += kScanGroup) {
         const uint32_t cur = next;
         next = text[(pos >> 2) + 1];
-        uint64_t hb[kScanGroup][P];
+        Words<PWS> e[kScanGroup];
 #pragma unroll
         for (int s = 0; s < kScanGroup; ++s) {
             const uint32_t c = (cur >> (8 * s)) & 0xFFu;
-            const Words<PWS> e = *reinterpret_cast<const Words<PWS> *>(img + c * (kWave * PWS) + lane_off);
-            const bool inrange = (pos + s >= lb) && (pos + s < len);
+            e[s] = *reinterpret_cast<const Words<PWS> *>(img + c * (kWave * PWS) + lane_off);
+        }
+        uint32_t pv0[P][W], mv0[P][W];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                pv0[p][w] = pv[p][w];
+                mv0[p][w] = mv[p][w];
+            }
+        int32_t screen = 0;
+#pragma unroll
+        for (int s = 0; s < kScanGroup; ++s) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                uint32_t eq[W];
-#pragma unroll
-                for (int w = 0; w < W; ++w) eq[w] = e.v[p * W + w];
-                column_step<W>(pv[p], mv[p], eq);
-                uint32_t up = 0, dn = kk[p];
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    up += __popc(pv[p][w]);
-                    dn += __popc(mv[p][w]);
-                }
-                // last-row value = sum of vertical deltas = up - (dn - K)
-                const uint64_t bal = __ballot(up <= dn) & active[p];
-                hb[s][p] = inrange ? bal : 0ull;
+                column_step<W>(pv[p], mv[p], &e[s].v[p * W]);
+                if (s == 1) screen |= le_bound<W>(pv[p], mv[p], k2[p]);
             }
         }
-        uint64_t any = 0;
-#pragma unroll
-        for (int s = 0; s < kScanGroup; ++s)
-#pragma unroll
-            for (int p = 0; p < P; ++p) any |= hb[s][p];
-        if (any) {
+        if (__ballot(screen < 0) && pos + (kScanGroup - 1) >= lb) {
+            // replay the group from its start state with an exact test per symbol
 #pragma unroll
             for (int s = 0; s < kScanGroup; ++s) {
+                const bool inrange = (pos + s >= lb) && (pos + s < len);
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    const uint64_t b = hb[s][p];
-                    if (b) {
+                    column_step<W>(pv0[p], mv0[p], &e[s].v[p * W]);
+                    const uint64_t b = __ballot(le_bound<W>(pv0[p], mv0[p], kk[p]) < 0);
+                    if (inrange && b) {
                         if ((b >> lane) & 1ull) {
                             const uint32_t idx = cnt + mbcnt64(b);
                             if (idx < a.cap) rec[idx] = ((p * kWave + lane) << 24) | (pos + s - lb);
@@ -264,7 +343,7 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        if ((active[p] >> lane) & 1ull) a.counts[cd.cnt_base + pat[p] * cd.cnt_stride] = lanecnt[p];
+        if (act[p]) a.counts[cd.cnt_base + pat[p] * cd.cnt_stride] = lanecnt[p];
     }
 }
 

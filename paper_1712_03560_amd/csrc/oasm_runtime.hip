@@ -156,7 +156,12 @@ struct oasm_ctx {
     size_t rd_raw = 0, rd_occ = 0, rd_h = 0;
 
     oasm_stats stats{};
-    uint64_t staged_bytes = 0;
+    uint64_t staged_bytes = 0;  // staging capacity held by open streams
+
+    // Staging buffers of closed streams, kept for reuse.  Every byte of them
+    // was written by this context (cleared at allocation, then mapped
+    // symbols), so they hold valid symbol classes only.
+    std::vector<std::pair<uint8_t *, size_t>> pool;
 };
 
 namespace {
@@ -173,6 +178,9 @@ oasm_status device_fail(oasm_ctx *c, const HipFail &f) {
     }
     return OASM_E_DEVICE;
 }
+
+uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap);
+void release_staging(oasm_ctx *c, uint8_t *p, size_t cap);
 
 uint32_t pow2_at_least(uint64_t v) {
     uint32_t r = 1;
@@ -510,7 +518,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             s.close_pending = false;
             s.closed = true;
             c->staged_bytes -= s.cap;
-            if (s.sym) ck(hipFree(s.sym), "hipFree staging");
+            release_staging(c, s.sym, s.cap);
             s.sym = nullptr;
             s.cap = 0;
             s.valid = s.scanned = 0;
@@ -578,30 +586,60 @@ StreamState &get_stream(oasm_ctx *c, uint64_t id, bool create) {
     return s;
 }
 
+// A staging buffer of at least `need` bytes: the smallest pooled one that
+// fits, else a new allocation cleared to class 0.
+uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap) {
+    size_t best = c->pool.size();
+    for (size_t i = 0; i < c->pool.size(); ++i)
+        if (c->pool[i].second >= need && (best == c->pool.size() || c->pool[i].second < c->pool[best].second))
+            best = i;
+    if (best < c->pool.size()) {
+        uint8_t *p = c->pool[best].first;
+        cap = c->pool[best].second;
+        c->pool.erase(c->pool.begin() + (ptrdiff_t)best);
+        return p;
+    }
+    size_t want = (need + 255) & ~size_t(255);
+    uint8_t *p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        // give the pool back to the device and try once more
+        ck(hipStreamSynchronize(c->st), "sync before pool release");
+        for (auto &b : c->pool) ck(hipFree(b.first), "hipFree pool");
+        c->pool.clear();
+        if (hipMalloc(&p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    // the scan's last group reads up to 8 symbols past the end before masking
+    // their ends out: every byte must be a valid symbol class
+    ck(hipMemsetAsync(p, 0, want, c->st), "staging clear");
+    cap = want;
+    return p;
+}
+
+void release_staging(oasm_ctx *c, uint8_t *p, size_t cap) {
+    if (p) c->pool.emplace_back(p, cap);
+}
+
 // Make room for `n` more symbols in a stream's staging buffer.
 oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n) {
     const size_t need = s.valid + n + kPad;
     if (need <= s.cap) return OASM_OK;
-    size_t want = std::max(need, s.cap + s.cap / 2);
-    want = (want + 255) & ~size_t(255);
+    const size_t want = std::max(need, s.cap + s.cap / 2);
     if (c->cfg.device_mem_budget && c->staged_bytes - s.cap + want > c->cfg.device_mem_budget)
         return fail(c, OASM_E_AGAIN, "device memory budget for staged stream data exhausted");
-    uint8_t *p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(c, OASM_E_NOMEM, "hipMalloc for stream staging failed");
-    }
-    // every byte of a staging buffer is a valid symbol class: the scan's last
-    // group reads up to 8 symbols past the end before masking their ends out
-    ck(hipMemsetAsync(p, 0, want, c->st), "staging clear");
+    size_t cap = 0;
+    uint8_t *p = acquire_staging(c, want, cap);
+    if (!p) return fail(c, OASM_E_NOMEM, "hipMalloc for stream staging failed");
     if (s.sym) {
         if (s.valid) ck(hipMemcpyAsync(p, s.sym, s.valid, hipMemcpyDeviceToDevice, c->st), "staging grow");
-        ck(hipStreamSynchronize(c->st), "staging grow sync");
-        ck(hipFree(s.sym), "hipFree staging");
+        release_staging(c, s.sym, s.cap);
     }
-    c->staged_bytes += want - s.cap;
+    c->staged_bytes += cap - s.cap;
     s.sym = p;
-    s.cap = want;
+    s.cap = cap;
     return OASM_OK;
 }
 
@@ -921,6 +959,7 @@ void oasm_destroy(oasm_ctx *c) {
     if (c->st) (void)hipStreamSynchronize(c->st);
     for (auto &s : c->streams)
         if (s.sym) (void)hipFree(s.sym);
+    for (auto &b : c->pool) (void)hipFree(b.first);
     DevBuf *bufs[] = {&c->d_pats, &c->d_slot_pat, &c->d_tiles, &c->d_peq, &c->d_rpeq, &c->d_class, &c->d_patbytes,
                       &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->counts, &c->offsets,
                       &c->item_rec, &c->item_cnt, &c->ctl, &c->scan_tmp, &c->r_pat, &c->r_sl, &c->r_end,
