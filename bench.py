@@ -196,6 +196,12 @@ def main():
                      "scan_launches_per_step": launches, "word_steps": word_steps,
                      "ops_per_word_step": OPS_PER_WORD_STEP},
         "scan_gcups": round(cells / (scan_ms * 1e-3) / 1e9, 1) if scan_ms > 0 else None,
+        "step_breakdown_ms": {
+            "scan_kernel": round(scan_ms, 3),
+            "device_step": round((s1["step_ms"] - s0["step_ms"]) / args.steps, 3),
+            "sync_wall": round((s1["sync_wall_ms"] - s0["sync_wall_ms"]) / args.steps, 3),
+            "sync_waiting": round((s1["wait_ms"] - s0["wait_ms"]) / args.steps, 3),
+        },
         "hits": {"hit_ends": int(res.raw.size), "occurrences": int(res.occ.size)},
     }
     if not args.no_cpu_baseline and args.workload != "batched":

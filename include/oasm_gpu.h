@@ -137,6 +137,8 @@ typedef struct oasm_stats {
     double scan_ms;             /* device time of the scan kernels (HIP events) */
     double step_ms;             /* device time of whole steps (HIP events) */
     uint64_t scan_launches;     /* scan kernel launches */
+    double sync_wall_ms;        /* host wall time spent inside oasm_sync */
+    double wait_ms;             /* part of it spent waiting for the device */
 } oasm_stats;
 
 /* Fill `cfg` with defaults (device -1, library stream, autotuned chunks). */
@@ -195,6 +197,10 @@ oasm_status oasm_sync(oasm_ctx *ctx);
  * follow each other in call order.
  */
 oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_t *n_out, int *more);
+
+/* Number of records of `kind` queued for draining (OASM_E_INVAL for an
+ * unknown kind, or OASM_H without OASM_CFG_KEEP_H). */
+oasm_status oasm_queued(const oasm_ctx *ctx, uint32_t kind, size_t *n);
 
 /* Cumulative counters and device timings. */
 oasm_status oasm_get_stats(const oasm_ctx *ctx, oasm_stats *out);

@@ -307,22 +307,30 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
                 pv0[p][w] = pv[p][w];
                 mv0[p][w] = mv[p][w];
             }
-        int32_t screen = 0;
+        int32_t screen[P];
 #pragma unroll
         for (int s = 0; s < kScanGroup; ++s) {
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 column_step<W>(pv[p], mv[p], &e[s].v[p * W]);
-                if (s == 1) screen |= le_bound<W>(pv[p], mv[p], k2[p]);
+                if (s == 1) screen[p] = le_bound<W>(pv[p], mv[p], k2[p]);
             }
         }
-        if (__ballot(screen < 0) && pos + (kScanGroup - 1) >= lb) {
-            // replay the group from its start state with an exact test per symbol
+        uint64_t sb[P], any = 0;
 #pragma unroll
-            for (int s = 0; s < kScanGroup; ++s) {
-                const bool inrange = (pos + s >= lb) && (pos + s < len);
+        for (int p = 0; p < P; ++p) {
+            sb[p] = __ballot(screen[p] < 0);
+            any |= sb[p];
+        }
+        if (any && pos + (kScanGroup - 1) >= lb) {
+            // replay the pattern slots that passed the screen from the group's
+            // start state, with an exact test per symbol
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
+            for (int p = 0; p < P; ++p) {
+                if (!sb[p]) continue;
+#pragma unroll
+                for (int s = 0; s < kScanGroup; ++s) {
+                    const bool inrange = (pos + s >= lb) && (pos + s < len);
                     column_step<W>(pv0[p], mv0[p], &e[s].v[p * W]);
                     const uint64_t b = __ballot(le_bound<W>(pv0[p], mv0[p], kk[p]) < 0);
                     if (inrange && b) {

@@ -15,6 +15,7 @@
 //   K3        Alg. 1 per segment; open segments are carried to the next step
 //   compaction and copy-back of hit ends, occurrences and the new carry.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <deque>
@@ -179,8 +180,21 @@ oasm_status device_fail(oasm_ctx *c, const HipFail &f) {
     return OASM_E_DEVICE;
 }
 
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// hipStreamSynchronize, with the blocked time added to the context's stats
+void wait_stream(oasm_ctx *c, const char *what);
+
 uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap);
 void release_staging(oasm_ctx *c, uint8_t *p, size_t cap);
+
+void wait_stream(oasm_ctx *c, const char *what) {
+    const double t0 = now_ms();
+    ck(hipStreamSynchronize(c->st), what);
+    c->stats.wait_ms += now_ms() - t0;
+}
 
 uint32_t pow2_at_least(uint64_t v) {
     uint32_t r = 1;
@@ -347,7 +361,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                                  c->scan_tmp.as<uint32_t>(), st),
            "counts scan");
         ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
-        ck(hipStreamSynchronize(st), "sync after scan");
+        wait_stream(c, "sync after scan");
         const uint32_t *h = c->pin_ctl.as<uint32_t>();
         if (h[0] > c->cap) {  // an item overflowed its record buffer: grow and rescan
             c->cap = pow2_at_least(h[0]);
@@ -407,7 +421,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                              c->scan_tmp.as<uint32_t>(), st),
        "carry scan");
     ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
-    ck(hipStreamSynchronize(st), "sync after filter");
+    wait_stream(c, "sync after filter");
     const uint32_t *h = c->pin_ctl.as<uint32_t>();
     const uint32_t nocc = h[2], ncarry_out = h[3], rec_err = h[4];
     if (rec_err) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
@@ -457,7 +471,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     d2h(o_cr, c->carry_out.p, (size_t)ncarry_out * sizeof(CarryRec));
     d2h(o_chk, c->carry_out_hk.p, (size_t)ncarry_out * hks);
     ck(hipEventRecord(c->ev2, st), "event");
-    ck(hipStreamSynchronize(st), "sync after copy-back");
+    wait_stream(c, "sync after copy-back");
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += ms;
 
@@ -470,10 +484,13 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     const uint8_t *hhk = hp + o_hk;
     uint64_t new_raw = 0;
     if (need_raw) {
+        std::vector<uint64_t> sid_of(pl.locals.size());
+        for (size_t l = 0; l < pl.locals.size(); ++l) sid_of[l] = c->streams[pl.locals[l]].id;
+        if (keep_raw) c->q_raw.reserve(c->q_raw.size() + n);
         for (uint32_t i = 0; i < n; ++i) {
             if (hflag[i]) continue;  // carried from an earlier step: reported there
             ++new_raw;
-            const uint64_t sid = c->streams[pl.locals[hsl[i]]].id;
+            const uint64_t sid = sid_of[hsl[i]];
             if (keep_raw) c->q_raw.push_back(oasm_hit{sid, hend[i], hpat[i], hdist[i]});
             if (keep_h) {
                 const uint32_t p = hpat[i];
@@ -482,16 +499,15 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                     const uint8_t kk = hhk[(size_t)i * hks + (l - (m - K))];
                     if (kk == kNoHit) continue;
                     c->q_h.push_back(oasm_occ{sid, hend[i] + 1 - (uint64_t)l, p, (uint32_t)l, kk, 0});
+                    c->stats.h_records++;
                 }
             }
         }
     } else {
         new_raw = n - ncarry;
     }
-    if (keep_h) {  // hit set in (stream, pattern, start, length) order within this step
-        // records were appended per end; restore start order for the step's new part
-    }
     const OccRec *ho = reinterpret_cast<const OccRec *>(hp + o_occ);
+    c->q_occ.reserve(c->q_occ.size() + nocc);
     for (uint32_t i = 0; i < nocc; ++i) {
         const uint64_t sid = c->streams[pl.locals[ho[i].stream_local]].id;
         c->q_occ.push_back(oasm_occ{sid, ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
@@ -900,13 +916,32 @@ oasm_status oasm_sync(oasm_ctx *c) {
     if (!c) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
     if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    const double t0 = now_ms();
     try {
         ck(hipSetDevice(c->device), "hipSetDevice");
         sync_all(c);
     } catch (const HipFail &f) {
+        c->stats.sync_wall_ms += now_ms() - t0;
         return device_fail(c, f);
     } catch (const std::bad_alloc &) {
         return fail(c, OASM_E_NOMEM, "host allocation failed");
+    }
+    c->stats.sync_wall_ms += now_ms() - t0;
+    return OASM_OK;
+}
+
+oasm_status oasm_queued(const oasm_ctx *c, uint32_t kind, size_t *n) {
+    if (!c || !n) return OASM_E_INVAL;
+    oasm_ctx *m = const_cast<oasm_ctx *>(c);
+    std::lock_guard<std::mutex> g(m->mu);
+    if (kind == OASM_RAW) {
+        *n = c->q_raw.size() - c->rd_raw;
+    } else if (kind == OASM_FILTERED) {
+        *n = c->q_occ.size() - c->rd_occ;
+    } else if (kind == OASM_H && (c->cfg.flags & OASM_CFG_KEEP_H)) {
+        *n = c->q_h.size() - c->rd_h;
+    } else {
+        return OASM_E_INVAL;
     }
     return OASM_OK;
 }

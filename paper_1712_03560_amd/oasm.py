@@ -47,6 +47,7 @@ EXPORTED = [
     "oasm_close_stream",
     "oasm_sync",
     "oasm_hits",
+    "oasm_queued",
     "oasm_get_stats",
     "oasm_destroy",
     "oasm_last_error",
@@ -78,7 +79,7 @@ class oasm_stats(ctypes.Structure):
     _fields_ = [("bytes_scanned", ctypes.c_uint64), ("word_steps", ctypes.c_uint64), ("cells", ctypes.c_uint64),
                 ("raw_hits", ctypes.c_uint64), ("h_records", ctypes.c_uint64), ("occurrences", ctypes.c_uint64),
                 ("syncs", ctypes.c_uint64), ("scan_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
-                ("scan_launches", ctypes.c_uint64)]
+                ("scan_launches", ctypes.c_uint64), ("sync_wall_ms", ctypes.c_double), ("wait_ms", ctypes.c_double)]
 
 
 HIT_DTYPE = np.dtype([("stream", "<u8"), ("end", "<u8"), ("pattern", "<u4"), ("dist", "<u4")])
@@ -109,6 +110,8 @@ def _load():
     lib.oasm_sync.restype = i32
     lib.oasm_hits.argtypes = [P, u32, P, sz, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_int)]
     lib.oasm_hits.restype = i32
+    lib.oasm_queued.argtypes = [P, u32, ctypes.POINTER(sz)]
+    lib.oasm_queued.restype = i32
     lib.oasm_get_stats.argtypes = [P, ctypes.POINTER(oasm_stats)]
     lib.oasm_get_stats.restype = i32
     lib.oasm_destroy.argtypes = [P]
@@ -183,20 +186,22 @@ def oasm_sync(ctx):
     _check(ctx, lib.oasm_sync(ctx))
 
 
-def oasm_hits(ctx, kind: int, batch: int = 1 << 16) -> np.ndarray:
+def oasm_queued(ctx, kind: int) -> int:
+    n = ctypes.c_size_t(0)
+    _check(ctx, lib.oasm_queued(ctx, kind, ctypes.byref(n)))
+    return n.value
+
+
+def oasm_hits(ctx, kind: int) -> np.ndarray:
     """Drain every queued record of ``kind`` into a structured numpy array."""
     dt = HIT_DTYPE if kind == OASM_RAW else OCC_DTYPE
-    parts = []
-    while True:
-        buf = np.empty(batch, dtype=dt)
-        n = ctypes.c_size_t(0)
-        more = ctypes.c_int(0)
-        _check(ctx, lib.oasm_hits(ctx, kind, buf.ctypes.data_as(ctypes.c_void_p), batch, ctypes.byref(n),
-                                  ctypes.byref(more)))
-        parts.append(buf[: n.value])
-        if not more.value:
-            break
-    return np.concatenate(parts) if len(parts) > 1 else parts[0]
+    total = oasm_queued(ctx, kind)
+    buf = np.empty(total, dtype=dt)
+    n = ctypes.c_size_t(0)
+    more = ctypes.c_int(0)
+    _check(ctx, lib.oasm_hits(ctx, kind, buf.ctypes.data_as(ctypes.c_void_p) if total else None, total,
+                              ctypes.byref(n), ctypes.byref(more)))
+    return buf[: n.value]
 
 
 def oasm_get_stats(ctx) -> dict:
