@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
     ap.add_argument("--chunk", type=int, default=0, help="chunk bytes (0 = library default)")
     ap.add_argument("--batched-streams", type=int, default=4096)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (PMC traffic calibration)")
     return ap.parse_args()
@@ -117,6 +118,56 @@ def cpu_baseline(w, target_s: float):
                       f"(hit ends, hit set and filter), {dt:.1f} s"}
 
 
+def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False):
+    """Time `steps` whole-path steps over device-resident streams (after `warmup`)."""
+    dev_streams = [torch.from_numpy(t).cuda() for t in w.streams]
+    torch.cuda.synchronize()
+    mt = oasm.Matcher(w.patterns, w.ks, chunk_bytes=chunk, plain=plain)
+    sid = [0]
+
+    def step():
+        base = sid[0]
+        for i, t in enumerate(dev_streams):
+            mt.feed(base + i, t, last=True)
+        sid[0] += len(dev_streams)
+        mt.sync()
+        return mt.results()
+
+    res = None
+    for _ in range(warmup):
+        res = step()
+    torch.cuda.synchronize()
+    s0 = mt.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s1 = mt.stats()
+    mt.destroy()
+    del dev_streams
+    return {"s0": s0, "s1": s1, "elapsed": elapsed, "res": res}
+
+
+def batched_vs_plain(oasm, torch, args, w=None):
+    """The many-stream workload: one batched launch sequence over all streams
+    versus one launch sequence per stream (the same kernels)."""
+    from paper_1712_03560_amd import workloads as W
+
+    if w is None:
+        w = W.batched(n_streams=args.batched_streams)
+    cells = sum(len(p) for p in w.patterns) * w.total_bytes
+    b = run_steps(oasm, torch, w, 2, 1)
+    p = run_steps(oasm, torch, w, 2, 1, plain=True)
+    tb, tp = b["elapsed"] / 2, p["elapsed"] / 2
+    assert b["res"].occ.size == p["res"].occ.size and b["res"].raw.size == p["res"].raw.size
+    return {"workload": f"{len(w.streams)} streams log-uniform in [1 KiB, 1 MiB] ({w.total_bytes} bytes), Zipf(1.1) "
+                        f"20 letters, {len(w.patterns)} patterns m~U[8,64], K=floor(m/10)",
+            "batched_gcups": round(cells / tb / 1e9, 1), "plain_gcups": round(cells / tp / 1e9, 1),
+            "batched_ms": round(tb * 1e3, 2), "plain_ms": round(tp * 1e3, 2), "speedup": round(tp / tb, 2),
+            "hit_ends": int(b["res"].raw.size), "occurrences": int(b["res"].occ.size)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -137,35 +188,12 @@ def main():
     if args.calibrate_copy:
         copy_calibration()
     w, desc = make_workload(args.workload, args)
-    dev_streams = [torch.from_numpy(s).cuda() for s in w.streams]
-    torch.cuda.synchronize()
+    r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk)
     msum = sum(len(p) for p in w.patterns)
     total_bytes = w.total_bytes
     cells = msum * total_bytes
     word_steps = sum((len(p) + 31) // 32 for p in w.patterns) * total_bytes
-
-    mt = oasm.Matcher(w.patterns, w.ks, no_raw=False, chunk_bytes=args.chunk)
-    sid = [0]
-
-    def step():
-        base = sid[0]
-        for i, t in enumerate(dev_streams):
-            mt.feed(base + i, t, last=True)
-        sid[0] += len(dev_streams)
-        mt.sync()
-        return mt.results()
-
-    for _ in range(args.warmup):
-        res = step()
-    torch.cuda.synchronize()
-    s0 = mt.stats()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    s1 = mt.stats()
-    mt.destroy()
+    s0, s1, elapsed, res = r["s0"], r["s1"], r["elapsed"], r["res"]
 
     ms_per_step = elapsed / args.steps * 1e3
     gcups = cells / (elapsed / args.steps) / 1e9
@@ -204,6 +232,8 @@ def main():
         },
         "hits": {"hit_ends": int(res.raw.size), "occurrences": int(res.occ.size)},
     }
+    if args.workload == "batched" or not args.no_batched:
+        line["batched_vs_plain"] = batched_vs_plain(oasm, torch, args, w if args.workload == "batched" else None)
     if not args.no_cpu_baseline and args.workload != "batched":
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)

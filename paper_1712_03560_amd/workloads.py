@@ -65,10 +65,20 @@ class Letters:
         if self.kind == "uniform":
             return self.alphabet[rng.integers(0, self.alphabet.size, size=n)]
         if self.kind == "weighted":
-            return self.alphabet[rng.choice(self.alphabet.size, size=n, p=self.probs)]
+            # a 2^16-entry table with round(p * 2^16) slots per letter (relative
+            # probability error below 0.1 % for the Zipf(1.1) letters), indexed
+            # by uniform 16-bit draws: much faster than rng.choice for 10^8 draws
+            return self._table()[rng.integers(0, 1 << 16, size=n, dtype=np.uint32)]
         if self.kind == "mixture":
             return mixture_bytes(rng, n, self.mean_run)
         raise ValueError(self.kind)
+
+    def _table(self) -> np.ndarray:
+        if getattr(self, "_tab", None) is None:
+            counts = np.round(self.probs * (1 << 16)).astype(np.int64)
+            counts[np.argmax(counts)] += (1 << 16) - counts.sum()
+            self._tab = np.repeat(self.alphabet, counts)
+        return self._tab
 
     def other_than(self, rng: np.random.Generator, old: int) -> int:
         """A letter different from ``old`` (for substitutions)."""
