@@ -20,8 +20,8 @@ struct ChunkDesc {
     uint64_t abs_first;     // absolute stream position of sym[lookback]
     uint32_t scan_len;      // symbols to scan, lookback included
     uint32_t lookback;      // warm-up symbols
-    uint32_t cnt_base;      // counts index of (stream, pattern 0, this chunk)
-    uint32_t cnt_stride;    // counts distance between consecutive patterns
+    uint32_t stream_local;  // step-local stream number
+    uint32_t pad;
 };
 
 // A tile: up to 64*P patterns of one word count W, one slot per (lane, p).
@@ -56,8 +56,6 @@ struct CarryRec {
     uint64_t end_abs;
     uint32_t pattern;
     uint32_t stream_slot;
-    uint32_t rank;          // index inside its (stream, pattern) run
-    uint32_t run_len;       // records in the run
     uint32_t dist;
     uint32_t pad;
 };
@@ -102,28 +100,28 @@ struct ScanArgs {
     uint32_t *item_cnt;      // [nitems]
     uint32_t item_base;      // first item index of this class
     uint32_t cap;
-    uint32_t *counts;        // per (stream, pattern, chunk slot)
     uint32_t *max_cnt;       // atomic max of per-item counts
 };
 hipError_t launch_scan(int W, int P, const ScanArgs &a, int waves_per_block, bool peq_in_lds, hipStream_t st);
 bool scan_variant_exists(int W, int P);
 
-// Scatter scan records into (stream, pattern, end) order.
-hipError_t launch_scatter(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
-                          uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
-                          const uint32_t *item_cnt, uint32_t item_base, uint32_t cap, const uint32_t *offsets,
-                          const uint32_t *chunk_stream, uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end,
-                          uint8_t *r_flag, hipStream_t st);
-
-// Carried records: write their run counts, then place them after the scan.
-hipError_t launch_carry_counts(const CarryRec *carry, uint32_t ncarry, const uint32_t *slot_to_local,
-                               const uint32_t *stream_cnt_base, const uint32_t *stream_cnt_stride,
-                               uint32_t *counts, hipStream_t st);
-hipError_t launch_carry_place(const CarryRec *carry, const uint8_t *carry_hk, uint32_t ncarry, uint32_t hks,
-                              const uint32_t *slot_to_local, const uint32_t *stream_cnt_base,
-                              const uint32_t *stream_cnt_stride, const uint32_t *offsets, uint32_t *r_pat,
-                              uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist, uint8_t *r_hk,
+// Ordering of the step's hit ends: carried ends first, then the scan items'
+// records (key = stream_local * npat + pattern, val = own index, end), then a
+// stable radix sort on the key, then a gather into the per-record arrays.
+hipError_t launch_place_carry(const CarryRec *carry, uint32_t ncarry, const uint32_t *slot_to_local, uint32_t npat,
+                              uint32_t *key, uint32_t *val, uint64_t *end, hipStream_t st);
+hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
+                              uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
+                              const uint32_t *item_cnt, const uint32_t *item_off, uint32_t item_base, uint32_t cap,
+                              uint32_t base, uint32_t npat, uint32_t *key, uint32_t *val, uint64_t *end,
                               hipStream_t st);
+size_t sort_tmp_words(uint32_t n);
+hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, uint32_t n,
+                             uint32_t key_bits, uint32_t *tmp, hipStream_t st, bool &result_in_second);
+hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, uint32_t n, uint32_t npat, uint32_t ncarry,
+                             const uint64_t *end_in, const CarryRec *carry, const uint8_t *carry_hk, uint32_t hks,
+                             uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist,
+                             uint8_t *r_hk, hipStream_t st);
 
 // K2: hit-set recovery at every new hit end (reverse anchored DP).
 hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_flag,
@@ -135,7 +133,7 @@ hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uin
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
                          uint32_t n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams,
                          uint32_t do_filter, uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt,
-                         uint32_t *carry_flag, uint32_t *carry_rank, uint32_t *carry_len, hipStream_t st);
+                         uint32_t *carry_flag, hipStream_t st);
 
 // Gather the filter output into a dense array.
 hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, uint32_t n,
@@ -144,9 +142,8 @@ hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, co
 // Gather carried records for the next step.
 hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end,
                                 const uint8_t *r_dist, const uint8_t *r_hk, uint32_t hks, const uint32_t *carry_flag,
-                                const uint32_t *carry_off, const uint32_t *carry_rank, const uint32_t *carry_len,
-                                const StreamDesc *streams, uint32_t n, CarryRec *out, uint8_t *out_hk,
-                                hipStream_t st);
+                                const uint32_t *carry_off, const StreamDesc *streams, uint32_t n, CarryRec *out,
+                                uint8_t *out_hk, hipStream_t st);
 
 // Exclusive prefix sum of n uint32 values; writes the total to *total.
 // `tmp` must hold scan_tmp_words(n) uint32.

@@ -12,6 +12,8 @@
 //   compactions, prefix scan, symbol mapping.
 //
 // Integer bit-vector work only; no matrix cores.
+#include <utility>
+
 #include "oasm_internal.h"
 
 namespace oasm {
@@ -262,7 +264,7 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
     // Inactive slots hold all-ones +1 deltas (D = 32W) and bounds of 0, so
     // they never pass the screen or the exact test.  kk / k2 hold the biases
     // of le_bound for the exact test (D <= K) and the screen (D <= K + 2).
-    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P], lanecnt[P];
+    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P];
     bool act[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -280,7 +282,6 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
             pv[p][w] = act[p] ? bits : ~0u;
             mv[p][w] = ~0u;  // complemented: no -1 deltas
         }
-        lanecnt[p] = 0;
     }
     uint32_t cnt = 0;
 
@@ -337,7 +338,6 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
                         if ((b >> lane) & 1ull) {
                             const uint32_t idx = cnt + mbcnt64(b);
                             if (idx < a.cap) rec[idx] = ((p * kWave + lane) << 24) | (pos + s - lb);
-                            lanecnt[p] += 1;
                         }
                         cnt += (uint32_t)__popcll(b);
                     }
@@ -348,10 +348,6 @@ __global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
     if (lane == 0) {
         a.item_cnt[item] = cnt;
         atomicMax(a.max_cnt, cnt);
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        if (act[p]) a.counts[cd.cnt_base + pat[p] * cd.cnt_stride] = lanecnt[p];
     }
 }
 
@@ -400,26 +396,38 @@ hipError_t launch_scan(int W, int P, const ScanArgs &a, int waves, bool lds, hip
     }
 }
 
-// ------------------------------------------------------------------ scatter
-// One wavefront per scan item.  Records of an item are in (end, slot)
-// order; each record goes to offsets[(stream, pattern, chunk)] + its rank
-// among the item's records of the same slot.  The rank inside a batch of 64
-// comes from eight ballots (lanes whose slot agrees on every bit); the
-// running count per slot sits in LDS.
-__global__ void __launch_bounds__(256) k_scatter(const ChunkDesc *__restrict__ chunks, uint32_t nchunks,
-                                                 const TileDesc *__restrict__ tiles, uint32_t tile_first,
-                                                 uint32_t ntiles, const uint32_t *__restrict__ slot_pat,
-                                                 const uint32_t *__restrict__ item_rec,
-                                                 const uint32_t *__restrict__ item_cnt, uint32_t item_base,
-                                                 uint32_t cap, const uint32_t *__restrict__ offsets,
-                                                 const uint32_t *__restrict__ chunk_stream, uint32_t *__restrict__ r_pat,
-                                                 uint32_t *__restrict__ r_sl, uint64_t *__restrict__ r_end,
-                                                 uint8_t *__restrict__ r_flag) {
-    __shared__ uint32_t run[4][256];
+// ------------------------------------------------------------------ ordering
+// The hit ends of a step are put in (stream, pattern, end) order without a
+// dense count table: carried ends first, then every scan item's records in
+// item order (items are chunk-major, so one pair's records appear chunk by
+// chunk, each chunk's in end order), then a stable radix sort on the
+// (stream, pattern) key alone.
+
+// Carried ends (already in order) at the front: key, end, source index.
+__global__ void k_place_carry(const CarryRec *__restrict__ carry, uint32_t n, const uint32_t *__restrict__ s2l,
+                              uint32_t npat, uint32_t *__restrict__ key, uint32_t *__restrict__ val,
+                              uint64_t *__restrict__ end) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const CarryRec c = carry[i];
+    key[i] = s2l[c.stream_slot] * npat + c.pattern;
+    val[i] = i;
+    end[i] = c.end_abs;
+}
+
+// One wavefront per scan item: its records go to base + item_off[item].
+__global__ void __launch_bounds__(256) k_compact_raw(const ChunkDesc *__restrict__ chunks, uint32_t nchunks,
+                                                     const TileDesc *__restrict__ tiles, uint32_t tile_first,
+                                                     uint32_t ntiles, const uint32_t *__restrict__ slot_pat,
+                                                     const uint32_t *__restrict__ item_rec,
+                                                     const uint32_t *__restrict__ item_cnt,
+                                                     const uint32_t *__restrict__ item_off, uint32_t item_base,
+                                                     uint32_t cap, uint32_t base, uint32_t npat,
+                                                     uint32_t *__restrict__ key, uint32_t *__restrict__ val,
+                                                     uint64_t *__restrict__ end) {
     const uint32_t lane = lane_id();
     const uint32_t wave = uniform(threadIdx.x >> 6);
     const uint32_t local = uniform(blockIdx.x * 4 + wave);
-    for (uint32_t i = lane; i < 256; i += kWave) run[wave][i] = 0;
     if (local >= nchunks * ntiles) return;
     const uint32_t chunk = local / ntiles, tile_local = local % ntiles;
     const uint32_t item = item_base + local;
@@ -428,99 +436,161 @@ __global__ void __launch_bounds__(256) k_scatter(const ChunkDesc *__restrict__ c
     if (n == 0) return;
     const ChunkDesc cd = chunks[chunk];
     const TileDesc td = tiles[tile_first + tile_local];
-    const uint32_t sl = chunk_stream[chunk];
     const uint32_t *rec = item_rec + (size_t)item * cap;
-    for (uint32_t b = 0; b < n; b += kWave) {
-        const uint32_t i = b + lane;
+    const uint32_t dst0 = base + item_off[item];
+    const uint32_t kbase = cd.stream_local * npat;
+    for (uint32_t i = lane; i < n; i += kWave) {
+        const uint32_t r = rec[i];
+        const uint32_t d = dst0 + i;
+        key[d] = kbase + slot_pat[td.slot_off + (r >> 24)];
+        val[d] = d;
+        end[d] = cd.abs_first + (r & 0xFFFFFFu);
+    }
+}
+
+hipError_t launch_place_carry(const CarryRec *carry, uint32_t ncarry, const uint32_t *slot_to_local, uint32_t npat,
+                              uint32_t *key, uint32_t *val, uint64_t *end, hipStream_t st) {
+    if (ncarry == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place_carry, dim3((ncarry + 255) / 256), dim3(256), 0, st, carry, ncarry, slot_to_local, npat,
+                       key, val, end);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
+                              uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
+                              const uint32_t *item_cnt, const uint32_t *item_off, uint32_t item_base, uint32_t cap,
+                              uint32_t base, uint32_t npat, uint32_t *key, uint32_t *val, uint64_t *end,
+                              hipStream_t st) {
+    const uint64_t items = (uint64_t)nchunks * ntiles;
+    if (items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_raw, dim3((uint32_t)((items + 3) / 4)), dim3(256), 0, st, chunks, nchunks, tiles,
+                       tile_first, ntiles, slot_pat, item_rec, item_cnt, item_off, item_base, cap, base, npat, key,
+                       val, end);
+    return hipGetLastError();
+}
+
+// Stable LSD radix sort of (key, val) pairs, 8 bits per pass.  Pass =
+// per-block digit histograms (digit-major, so one exclusive scan yields every
+// block's output base per digit) and a stable scatter: each block walks its
+// tile in rounds of 256 elements; inside a wavefront the rank among equal
+// digits comes from eight ballots, across the block's four wavefronts from
+// per-wave digit counts in LDS.
+constexpr uint32_t kSortThreads = 256;
+constexpr uint32_t kSortRounds = 8;
+constexpr uint32_t kSortTile = kSortThreads * kSortRounds;
+
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t *__restrict__ key, uint32_t n,
+                                                            uint32_t shift, uint32_t nblocks,
+                                                            uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t b0 = blockIdx.x * kSortTile;
+    for (uint32_t r = 0; r < kSortRounds; ++r) {
+        const uint32_t i = b0 + r * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(key[i] >> shift) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t *__restrict__ kin,
+                                                               const uint32_t *__restrict__ vin, uint32_t n,
+                                                               uint32_t shift, uint32_t nblocks,
+                                                               const uint32_t *__restrict__ offs,
+                                                               uint32_t *__restrict__ kout,
+                                                               uint32_t *__restrict__ vout) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wc[4][256];
+    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    base[t] = offs[t * nblocks + blockIdx.x];
+    wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
+    __syncthreads();
+    const uint32_t b0 = blockIdx.x * kSortTile;
+    for (uint32_t r = 0; r < kSortRounds; ++r) {
+        const uint32_t i = b0 + r * kSortThreads + t;
         const bool valid = i < n;
-        const uint32_t r = valid ? rec[i] : 0u;
-        const uint32_t slot = r >> 24;
+        const uint32_t k = valid ? kin[i] : 0u;
+        const uint32_t v = valid ? vin[i] : 0u;
+        const uint32_t d = (k >> shift) & 0xFFu;
         uint64_t same = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
-            const bool one = (slot >> bit) & 1u;
+            const bool one = (d >> bit) & 1u;
             const uint64_t bal = __ballot(valid && one);
             same &= one ? bal : ~bal;
         }
         const uint32_t rank = mbcnt64(same);
         const uint32_t group = (uint32_t)__popcll(same);
-        uint32_t base = 0;
-        if (valid) base = run[wave][slot];
-        __builtin_amdgcn_wave_barrier();
-        if (valid && rank == group - 1) run[wave][slot] = base + group;
-        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == group - 1) wc[wave][d] = group;
+        __syncthreads();
         if (valid) {
-            const uint32_t pattern = slot_pat[td.slot_off + slot];
-            const uint32_t dst = offsets[cd.cnt_base + pattern * cd.cnt_stride] + base + rank;
-            r_pat[dst] = pattern;
-            r_sl[dst] = sl;
-            r_end[dst] = cd.abs_first + (r & 0xFFFFFFu);
-            r_flag[dst] = 0;
+            uint32_t o = base[d] + rank;
+            for (uint32_t w = 0; w < wave; ++w) o += wc[w][d];
+            kout[o] = k;
+            vout[o] = v;
         }
+        __syncthreads();
+        base[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
+        __syncthreads();
     }
 }
 
-hipError_t launch_scatter(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
-                          uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
-                          const uint32_t *item_cnt, uint32_t item_base, uint32_t cap, const uint32_t *offsets,
-                          const uint32_t *chunk_stream, uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end,
-                          uint8_t *r_flag, hipStream_t st) {
-    const uint64_t items = (uint64_t)nchunks * ntiles;
-    if (items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scatter, dim3((uint32_t)((items + 3) / 4)), dim3(256), 0, st, chunks, nchunks, tiles,
-                       tile_first, ntiles, slot_pat, item_rec, item_cnt, item_base, cap, offsets, chunk_stream, r_pat,
-                       r_sl, r_end, r_flag);
+size_t sort_tmp_words(uint32_t n) {
+    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+    return (size_t)256 * nb * 2 + scan_tmp_words((size_t)256 * nb) + 16;
+}
+
+hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, uint32_t n,
+                             uint32_t key_bits, uint32_t *tmp, hipStream_t st, bool &result_in_second) {
+    result_in_second = false;
+    if (n <= 1 || key_bits == 0) return hipSuccess;
+    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+    uint32_t *hist = tmp;
+    uint32_t *offs = tmp + (size_t)256 * nb;
+    uint32_t *stmp = offs + (size_t)256 * nb;
+    uint32_t *total = stmp + scan_tmp_words((size_t)256 * nb);
+    uint32_t *ki = key, *vi = val, *ko = key2, *vo = val2;
+    for (uint32_t shift = 0; shift < key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, st, ki, n, shift, nb, hist);
+        hipError_t e = launch_exclusive_scan(hist, offs, (size_t)256 * nb, total, stmp, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortThreads), 0, st, ki, vi, n, shift, nb, offs, ko, vo);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+        result_in_second = !result_in_second;
+    }
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ carry
-__global__ void k_carry_counts(const CarryRec *__restrict__ carry, uint32_t n, const uint32_t *__restrict__ s2l,
-                               const uint32_t *__restrict__ sbase, const uint32_t *__restrict__ sstride,
-                               uint32_t *__restrict__ counts) {
+// Sorted (key, source index) -> the per-record arrays of the step.
+__global__ void k_gather_raw(const uint32_t *__restrict__ skey, const uint32_t *__restrict__ sval, uint32_t n,
+                             uint32_t npat, uint32_t ncarry, const uint64_t *__restrict__ end_in,
+                             const CarryRec *__restrict__ carry, const uint8_t *__restrict__ carry_hk, uint32_t hks,
+                             uint32_t *__restrict__ r_pat, uint32_t *__restrict__ r_sl, uint64_t *__restrict__ r_end,
+                             uint8_t *__restrict__ r_flag, uint8_t *__restrict__ r_dist, uint8_t *__restrict__ r_hk) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const CarryRec c = carry[i];
-    if (c.rank != 0) return;
-    const uint32_t s = s2l[c.stream_slot];
-    counts[sbase[s] + c.pattern * sstride[s]] = c.run_len;
+    const uint32_t k = skey[i], src = sval[i];
+    r_pat[i] = k % npat;
+    r_sl[i] = k / npat;
+    r_end[i] = end_in[src];
+    const bool carried = src < ncarry;
+    r_flag[i] = carried ? 1 : 0;
+    if (carried) {
+        r_dist[i] = (uint8_t)carry[src].dist;
+        for (uint32_t q = 0; q < hks; ++q) r_hk[(size_t)i * hks + q] = carry_hk[(size_t)src * hks + q];
+    }
 }
 
-__global__ void k_carry_place(const CarryRec *__restrict__ carry, const uint8_t *__restrict__ carry_hk, uint32_t n,
-                              uint32_t hks, const uint32_t *__restrict__ s2l, const uint32_t *__restrict__ sbase,
-                              const uint32_t *__restrict__ sstride, const uint32_t *__restrict__ offsets,
-                              uint32_t *__restrict__ r_pat, uint32_t *__restrict__ r_sl, uint64_t *__restrict__ r_end,
-                              uint8_t *__restrict__ r_flag, uint8_t *__restrict__ r_dist, uint8_t *__restrict__ r_hk) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const CarryRec c = carry[i];
-    const uint32_t s = s2l[c.stream_slot];
-    const uint32_t dst = offsets[sbase[s] + c.pattern * sstride[s]] + c.rank;
-    r_pat[dst] = c.pattern;
-    r_sl[dst] = s;
-    r_end[dst] = c.end_abs;
-    r_flag[dst] = 1;
-    r_dist[dst] = (uint8_t)c.dist;
-    for (uint32_t q = 0; q < hks; ++q) r_hk[(size_t)dst * hks + q] = carry_hk[(size_t)i * hks + q];
-}
-
-hipError_t launch_carry_counts(const CarryRec *carry, uint32_t ncarry, const uint32_t *slot_to_local,
-                               const uint32_t *stream_cnt_base, const uint32_t *stream_cnt_stride, uint32_t *counts,
-                               hipStream_t st) {
-    if (ncarry == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_carry_counts, dim3((ncarry + 255) / 256), dim3(256), 0, st, carry, ncarry, slot_to_local,
-                       stream_cnt_base, stream_cnt_stride, counts);
-    return hipGetLastError();
-}
-
-hipError_t launch_carry_place(const CarryRec *carry, const uint8_t *carry_hk, uint32_t ncarry, uint32_t hks,
-                              const uint32_t *slot_to_local, const uint32_t *stream_cnt_base,
-                              const uint32_t *stream_cnt_stride, const uint32_t *offsets, uint32_t *r_pat,
-                              uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist, uint8_t *r_hk,
-                              hipStream_t st) {
-    if (ncarry == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_carry_place, dim3((ncarry + 255) / 256), dim3(256), 0, st, carry, carry_hk, ncarry, hks,
-                       slot_to_local, stream_cnt_base, stream_cnt_stride, offsets, r_pat, r_sl, r_end, r_flag, r_dist,
-                       r_hk);
+hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, uint32_t n, uint32_t npat, uint32_t ncarry,
+                             const uint64_t *end_in, const CarryRec *carry, const uint8_t *carry_hk, uint32_t hks,
+                             uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist,
+                             uint8_t *r_hk, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_raw, dim3((n + 255) / 256), dim3(256), 0, st, skey, sval, n, npat, ncarry, end_in,
+                       carry, carry_hk, hks, r_pat, r_sl, r_end, r_flag, r_dist, r_hk);
     return hipGetLastError();
 }
 
@@ -638,8 +708,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
                                                uint32_t n, uint32_t hks, const PatDesc *__restrict__ pats,
                                                const StreamDesc *__restrict__ streams, uint32_t do_filter,
                                                uint32_t out_stride, OccRec *__restrict__ seg_out,
-                                               uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag,
-                                               uint32_t *__restrict__ carry_rank, uint32_t *__restrict__ carry_len) {
+                                               uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t p = r_pat[i], sl = r_sl[i];
@@ -656,11 +725,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     while (j1 < n && r_pat[j1] == p && r_sl[j1] == sl && r_end[j1] - r_end[j1 - 1] < gap) ++j1;
     const StreamDesc sd = streams[sl];
     const bool open = do_filter && !sd.closed && r_end[j1 - 1] + gap > sd.frontier;
-    for (uint32_t j = i; j < j1; ++j) {
-        carry_flag[j] = open ? 1u : 0u;
-        carry_rank[j] = j - i;
-        carry_len[j] = j1 - i;
-    }
+    for (uint32_t j = i; j < j1; ++j) carry_flag[j] = open ? 1u : 0u;
     if (open || !do_filter) {
         seg_cnt[i] = 0;
         return;
@@ -735,10 +800,10 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
                          uint32_t n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams, uint32_t do_filter,
                          uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt, uint32_t *carry_flag,
-                         uint32_t *carry_rank, uint32_t *carry_len, hipStream_t st) {
+                         hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_filter, dim3((n + 63) / 64), dim3(64), 0, st, r_pat, r_sl, r_end, r_hk, n, hks, pats, streams,
-                       do_filter, out_stride, seg_out, seg_cnt, carry_flag, carry_rank, carry_len);
+                       do_filter, out_stride, seg_out, seg_cnt, carry_flag);
     return hipGetLastError();
 }
 
@@ -763,7 +828,6 @@ __global__ void k_compact_carry(const uint32_t *__restrict__ r_pat, const uint32
                                 const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_dist,
                                 const uint8_t *__restrict__ r_hk, uint32_t hks,
                                 const uint32_t *__restrict__ carry_flag, const uint32_t *__restrict__ carry_off,
-                                const uint32_t *__restrict__ carry_rank, const uint32_t *__restrict__ carry_len,
                                 const StreamDesc *__restrict__ streams, uint32_t n, CarryRec *__restrict__ out,
                                 uint8_t *__restrict__ out_hk) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -773,8 +837,6 @@ __global__ void k_compact_carry(const uint32_t *__restrict__ r_pat, const uint32
     c.end_abs = r_end[i];
     c.pattern = r_pat[i];
     c.stream_slot = streams[r_sl[i]].slot;
-    c.rank = carry_rank[i];
-    c.run_len = carry_len[i];
     c.dist = r_dist[i];
     c.pad = 0;
     out[o] = c;
@@ -783,12 +845,11 @@ __global__ void k_compact_carry(const uint32_t *__restrict__ r_pat, const uint32
 
 hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end,
                                 const uint8_t *r_dist, const uint8_t *r_hk, uint32_t hks, const uint32_t *carry_flag,
-                                const uint32_t *carry_off, const uint32_t *carry_rank, const uint32_t *carry_len,
-                                const StreamDesc *streams, uint32_t n, CarryRec *out, uint8_t *out_hk,
-                                hipStream_t st) {
+                                const uint32_t *carry_off, const StreamDesc *streams, uint32_t n, CarryRec *out,
+                                uint8_t *out_hk, hipStream_t st) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_compact_carry, dim3((n + 255) / 256), dim3(256), 0, st, r_pat, r_sl, r_end, r_dist, r_hk,
-                       hks, carry_flag, carry_off, carry_rank, carry_len, streams, n, out, out_hk);
+                       hks, carry_flag, carry_off, streams, n, out, out_hk);
     return hipGetLastError();
 }
 

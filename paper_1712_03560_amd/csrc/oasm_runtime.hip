@@ -7,10 +7,11 @@
 //
 //   plan      chunks of C symbols per stream, each read with an
 //             (m_max + K_max - 1)-symbol look-back so its hit ends are exact
-//   K1        scan, one launch per word-count class (grid: chunks x tiles)
-//   counts -> exclusive scan -> offsets; scatter into (stream, pattern, end)
-//   carry     hit ends of filter segments left open by the previous step
-//             are placed ahead of the new ones of their (stream, pattern)
+//   K1        scan, one launch per word-count class (grid: chunks x tiles),
+//             hit ends into per-item record buffers
+//   order     hit ends of filter segments left open by the previous step,
+//             then the items' records (chunk-major), then a stable radix sort
+//             on the (stream, pattern) key: (stream, pattern, end) order
 //   K2        hit set at every new hit end
 //   K3        Alg. 1 per segment; open segments are carried to the next step
 //   compaction and copy-back of hit ends, occurrences and the new carry.
@@ -143,9 +144,9 @@ struct oasm_ctx {
     std::vector<StreamState> streams;
 
     // step buffers
-    DevBuf plan, counts, offsets, item_rec, item_cnt, ctl, scan_tmp;
-    DevBuf r_pat, r_sl, r_end, r_flag, r_dist, r_hk, seg_cnt, seg_off, carry_flag, carry_off, carry_rank, carry_len;
-    DevBuf seg_out, occ_out, carry_out, carry_out_hk, carry_in, carry_in_hk, raw_in;
+    DevBuf plan, offsets, item_rec, item_cnt, ctl, scan_tmp, sort_key, sort_val, sort_end, sort_tmp;
+    DevBuf r_pat, r_sl, r_end, r_flag, r_dist, r_hk, seg_cnt, seg_off, carry_flag, carry_off;
+    DevBuf seg_out, occ_out, carry_out, carry_out_hk, raw_in;
     PinBuf pin_plan, pin_ctl, pin_out, pin_feed;
     size_t pin_feed_used = 0;
     uint32_t cap = 256;
@@ -206,13 +207,10 @@ uint32_t pow2_at_least(uint64_t v) {
 struct StepPlan {
     std::vector<uint32_t> locals;  // stream indices (ctx->streams) in step order
     std::vector<ChunkDesc> chunks;
-    std::vector<uint32_t> chunk_stream;
     std::vector<StreamDesc> sdesc;
-    std::vector<uint32_t> s_base, s_stride;
     std::vector<uint32_t> slot_to_local;
     std::vector<CarryRec> carry;
     std::vector<uint8_t> carry_hk;
-    uint64_t ncounts = 0;
     uint64_t bytes = 0;
 };
 
@@ -239,7 +237,6 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
     for (uint32_t si : which) total_new += c->streams[si].valid - c->streams[si].scanned;
     const uint32_t C = choose_chunk(c, total_new);
     pl.slot_to_local.assign(c->streams.size(), 0xFFFFFFFFu);
-    uint64_t cbase = 0;
     for (uint32_t si : which) {
         StreamState &s = c->streams[si];
         const uint32_t local = (uint32_t)pl.locals.size();
@@ -247,9 +244,6 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
         pl.slot_to_local[s.slot] = local;
         const uint64_t pend = s.valid - s.scanned;
         const uint64_t nch = (pend + C - 1) / C;
-        const uint64_t stride = nch + 1;  // chunk slot 0: carried hit ends
-        pl.s_base.push_back((uint32_t)cbase);
-        pl.s_stride.push_back((uint32_t)stride);
         for (uint64_t j = 0; j < nch; ++j) {
             const uint64_t e0 = s.scanned + j * C;  // staging index of the first reported end
             const uint64_t e1 = std::min<uint64_t>(s.valid, e0 + C);
@@ -260,12 +254,10 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
             cd.abs_first = s.base_abs + e0;
             cd.scan_len = (uint32_t)(e1 - st0);
             cd.lookback = (uint32_t)(e0 - st0);
-            cd.cnt_base = (uint32_t)(cbase + 1 + j);
-            cd.cnt_stride = (uint32_t)stride;
+            cd.stream_local = local;
+            cd.pad = 0;
             pl.chunks.push_back(cd);
-            pl.chunk_stream.push_back(local);
         }
-        cbase += stride * c->npat;
         StreamDesc sd;
         sd.sym = s.sym;
         sd.base_abs = s.base_abs;
@@ -277,7 +269,6 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
         pl.carry_hk.insert(pl.carry_hk.end(), s.carry_hk.begin(), s.carry_hk.end());
         pl.bytes += pend;
     }
-    pl.ncounts = cbase;
 }
 
 // ------------------------------------------------------------------ step
@@ -285,51 +276,44 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     hipStream_t st = c->st;
     StepPlan pl;
     build_plan(c, which, pl);
-    if (pl.ncounts >= (1ull << 32)) throw HipFail{hipErrorInvalidValue, "step too large (counts exceed 2^32)"};
+    if ((uint64_t)pl.locals.size() * c->npat >= (1ull << 32))
+        throw HipFail{hipErrorInvalidValue, "step too large (streams x patterns exceed 2^32)"};
 
     // upload the plan in one copy
     std::vector<uint8_t> blob;
     const size_t o_chunks = put(blob, pl.chunks);
-    const size_t o_cstream = put(blob, pl.chunk_stream);
     const size_t o_sdesc = put(blob, pl.sdesc);
-    const size_t o_sbase = put(blob, pl.s_base);
-    const size_t o_sstride = put(blob, pl.s_stride);
     const size_t o_s2l = put(blob, pl.slot_to_local);
     const size_t o_carry = put(blob, pl.carry);
     const size_t o_carry_hk = put(blob, pl.carry_hk);
     blob.resize(blob.size() + 16);
     c->pin_plan.ensure(blob.size(), st);
-    ck(hipStreamSynchronize(st), "sync before plan upload");  // pinned plan may still be in use
+    wait_stream(c, "sync before plan upload");  // the pinned plan of the last step may still be read
     std::memcpy(c->pin_plan.p, blob.data(), blob.size());
     c->plan.ensure(blob.size(), st);
     ck(hipMemcpyAsync(c->plan.p, c->pin_plan.p, blob.size(), hipMemcpyHostToDevice, st), "plan upload");
     uint8_t *pb = c->plan.as<uint8_t>();
     const ChunkDesc *d_chunks = reinterpret_cast<const ChunkDesc *>(pb + o_chunks);
-    const uint32_t *d_cstream = reinterpret_cast<const uint32_t *>(pb + o_cstream);
     const StreamDesc *d_sdesc = reinterpret_cast<const StreamDesc *>(pb + o_sdesc);
-    const uint32_t *d_sbase = reinterpret_cast<const uint32_t *>(pb + o_sbase);
-    const uint32_t *d_sstride = reinterpret_cast<const uint32_t *>(pb + o_sstride);
     const uint32_t *d_s2l = reinterpret_cast<const uint32_t *>(pb + o_s2l);
     const CarryRec *d_carry = reinterpret_cast<const CarryRec *>(pb + o_carry);
     const uint8_t *d_carry_hk = pb + o_carry_hk;
     const uint32_t nchunks = (uint32_t)pl.chunks.size();
     const uint32_t ncarry = (uint32_t)pl.carry.size();
 
-    // control words: [0] max item count, [1] raw total, [2] occ total, [3] carry total, [4] recovery errors
+    // control words: [0] max item count, [1] new hit ends, [2] occurrences, [3] carried, [4] recovery errors
     c->ctl.ensure(64, st);
     uint32_t *ctl = c->ctl.as<uint32_t>();
     c->pin_ctl.ensure(64, st);
 
     const uint64_t nitems = (uint64_t)nchunks * c->ntiles;
-    c->counts.ensure(std::max<uint64_t>(1, pl.ncounts) * 4, st);
-    c->offsets.ensure(std::max<uint64_t>(1, pl.ncounts) * 4, st);
     c->item_cnt.ensure(std::max<uint64_t>(1, nitems) * 4, st);
-    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint64_t>(pl.ncounts, 1)) * 4, 1024), st);
+    c->offsets.ensure(std::max<uint64_t>(1, nitems) * 4, st);
+    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint64_t>(nitems, 1)) * 4, 1024), st);
 
-    uint32_t raw_total = 0;
+    uint32_t n_new = 0;
     for (int attempt = 0;; ++attempt) {
         c->item_rec.ensure(std::max<uint64_t>(1, nitems) * c->cap * 4, st);
-        ck(launch_fill_u32(c->counts.as<uint32_t>(), 0, pl.ncounts, st), "fill counts");
         ck(launch_fill_u32(ctl, 0, 16, st), "fill ctl");
         ck(hipEventRecord(c->ev0, st), "event");
         uint32_t item_base = 0;
@@ -348,18 +332,15 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             a.item_cnt = c->item_cnt.as<uint32_t>();
             a.item_base = item_base;
             a.cap = c->cap;
-            a.counts = c->counts.as<uint32_t>();
             a.max_cnt = ctl + 0;
             ck(launch_scan(ci.W, ci.P, a, ci.waves, ci.lds, st), "scan launch");
             item_base += nchunks * ci.ntiles;
             c->stats.scan_launches++;
         }
         ck(hipEventRecord(c->ev1, st), "event");
-        ck(launch_carry_counts(d_carry, ncarry, d_s2l, d_sbase, d_sstride, c->counts.as<uint32_t>(), st),
-           "carry counts");
-        ck(launch_exclusive_scan(c->counts.as<uint32_t>(), c->offsets.as<uint32_t>(), pl.ncounts, ctl + 1,
+        ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), nitems, ctl + 1,
                                  c->scan_tmp.as<uint32_t>(), st),
-           "counts scan");
+           "item count scan");
         ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
         wait_stream(c, "sync after scan");
         const uint32_t *h = c->pin_ctl.as<uint32_t>();
@@ -367,43 +348,56 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             c->cap = pow2_at_least(h[0]);
             continue;
         }
-        raw_total = h[1];
+        n_new = h[1];
         float ms = 0;
         if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->stats.scan_ms += ms;
         break;
     }
 
-    const uint32_t n = raw_total;
+    const uint32_t n = ncarry + n_new;
     const uint32_t hks = c->hks;
     const uint32_t out_stride = c->kmax + 1;
-    c->r_pat.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->r_sl.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->r_end.ensure(std::max<uint32_t>(n, 1) * 8ull, st);
-    c->r_flag.ensure(std::max<uint32_t>(n, 1), st);
-    c->r_dist.ensure(std::max<uint32_t>(n, 1), st);
-    c->r_hk.ensure(std::max<uint32_t>(n, 1) * (uint64_t)hks, st);
-    c->seg_cnt.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->seg_off.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->carry_flag.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->carry_off.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->carry_rank.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->carry_len.ensure(std::max<uint32_t>(n, 1) * 4ull, st);
-    c->seg_out.ensure(std::max<uint64_t>(n, 1) * out_stride * sizeof(OccRec), st);
-    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint32_t>(n, 1)) * 4, 1024), st);
+    const uint64_t n1 = std::max<uint32_t>(n, 1);
+    c->sort_key.ensure(n1 * 8, st);  // two halves: ping-pong
+    c->sort_val.ensure(n1 * 8, st);
+    c->sort_end.ensure(n1 * 8, st);
+    c->sort_tmp.ensure(sort_tmp_words(n1) * 4, st);
+    c->r_pat.ensure(n1 * 4, st);
+    c->r_sl.ensure(n1 * 4, st);
+    c->r_end.ensure(n1 * 8, st);
+    c->r_flag.ensure(n1, st);
+    c->r_dist.ensure(n1, st);
+    c->r_hk.ensure(n1 * hks, st);
+    c->seg_cnt.ensure(n1 * 4, st);
+    c->seg_off.ensure(n1 * 4, st);
+    c->carry_flag.ensure(n1 * 4, st);
+    c->carry_off.ensure(n1 * 4, st);
+    c->seg_out.ensure(n1 * out_stride * sizeof(OccRec), st);
+    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(n1) * 4, 1024), st);
 
+    uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
+    uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
+    ck(launch_place_carry(d_carry, ncarry, d_s2l, c->npat, key0, val0, c->sort_end.as<uint64_t>(), st),
+       "place carry");
     uint32_t item_base = 0;
     for (const ClassInfo &ci : c->classes) {
-        ck(launch_scatter(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
-                          c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(), c->item_cnt.as<uint32_t>(),
-                          item_base, c->cap, c->offsets.as<uint32_t>(), d_cstream, c->r_pat.as<uint32_t>(),
-                          c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(), st),
-           "scatter");
+        ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
+                              c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(), c->item_cnt.as<uint32_t>(),
+                              c->offsets.as<uint32_t>(), item_base, c->cap, ncarry, c->npat, key0, val0,
+                              c->sort_end.as<uint64_t>(), st),
+           "compact hit ends");
         item_base += nchunks * ci.ntiles;
     }
-    ck(launch_carry_place(d_carry, d_carry_hk, ncarry, hks, d_s2l, d_sbase, d_sstride, c->offsets.as<uint32_t>(),
-                          c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                          c->r_flag.as<uint8_t>(), c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), st),
-       "carry place");
+    uint32_t key_bits = 0;
+    while (key_bits < 32 && ((uint64_t)1 << key_bits) < (uint64_t)pl.locals.size() * c->npat) ++key_bits;
+    bool second = false;
+    ck(launch_radix_sort(key0, val0, key1, val1, n, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
+       "radix sort");
+    ck(launch_gather_raw(second ? key1 : key0, second ? val1 : val0, n, c->npat, ncarry, c->sort_end.as<uint64_t>(),
+                         d_carry, d_carry_hk, hks, c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(),
+                         c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(), c->r_dist.as<uint8_t>(),
+                         c->r_hk.as<uint8_t>(), st),
+       "gather hit ends");
     ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
                       c->r_flag.as<uint8_t>(), n, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
                       c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
@@ -411,8 +405,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     const uint32_t do_filter = c->rules == OASM_RULES_PAPER ? 1u : 0u;
     ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_hk.as<uint8_t>(),
                      n, hks, c->d_pats.as<PatDesc>(), d_sdesc, do_filter, out_stride, c->seg_out.as<OccRec>(),
-                     c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), c->carry_rank.as<uint32_t>(),
-                     c->carry_len.as<uint32_t>(), st),
+                     c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
        "filter");
     ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), n, ctl + 2,
                              c->scan_tmp.as<uint32_t>(), st),
@@ -434,8 +427,8 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
        "compact occ");
     ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
                             c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
-                            c->carry_off.as<uint32_t>(), c->carry_rank.as<uint32_t>(), c->carry_len.as<uint32_t>(),
-                            d_sdesc, n, c->carry_out.as<CarryRec>(), c->carry_out_hk.as<uint8_t>(), st),
+                            c->carry_off.as<uint32_t>(), d_sdesc, n, c->carry_out.as<CarryRec>(),
+                            c->carry_out_hk.as<uint8_t>(), st),
        "compact carry");
 
     // copy back: raw (pat, sl, end, flag, dist), hk (when kept), occurrences, carry
@@ -996,11 +989,11 @@ void oasm_destroy(oasm_ctx *c) {
         if (s.sym) (void)hipFree(s.sym);
     for (auto &b : c->pool) (void)hipFree(b.first);
     DevBuf *bufs[] = {&c->d_pats, &c->d_slot_pat, &c->d_tiles, &c->d_peq, &c->d_rpeq, &c->d_class, &c->d_patbytes,
-                      &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->counts, &c->offsets,
-                      &c->item_rec, &c->item_cnt, &c->ctl, &c->scan_tmp, &c->r_pat, &c->r_sl, &c->r_end,
-                      &c->r_flag, &c->r_dist, &c->r_hk, &c->seg_cnt, &c->seg_off, &c->carry_flag, &c->carry_off,
-                      &c->carry_rank, &c->carry_len, &c->seg_out, &c->occ_out, &c->carry_out, &c->carry_out_hk,
-                      &c->carry_in, &c->carry_in_hk, &c->raw_in};
+                      &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->offsets, &c->item_rec,
+                      &c->item_cnt, &c->ctl, &c->scan_tmp, &c->sort_key, &c->sort_val, &c->sort_end, &c->sort_tmp,
+                      &c->r_pat, &c->r_sl, &c->r_end, &c->r_flag, &c->r_dist, &c->r_hk, &c->seg_cnt, &c->seg_off,
+                      &c->carry_flag, &c->carry_off, &c->seg_out, &c->occ_out, &c->carry_out, &c->carry_out_hk,
+                      &c->raw_in};
     for (DevBuf *b : bufs) b->release();
     c->pin_plan.release();
     c->pin_ctl.release();
