@@ -105,8 +105,7 @@ struct StreamState {
     size_t scanned = 0;      // symbols already matched (the retained tail)
     bool close_pending = false;
     bool closed = false;
-    std::vector<CarryRec> carry;  // open filter segment(s) of this stream
-    std::vector<uint8_t> carry_hk;
+    uint32_t ncarry = 0;     // hit ends of this stream held in the device carry
 };
 
 struct ClassInfo {
@@ -146,7 +145,14 @@ struct oasm_ctx {
     // step buffers
     DevBuf plan, offsets, item_rec, item_cnt, ctl, scan_tmp, sort_key, sort_val, sort_end, sort_tmp;
     DevBuf r_pat, r_sl, r_end, r_flag, r_dist, r_hk, seg_cnt, seg_off, carry_flag, carry_off;
-    DevBuf seg_out, occ_out, carry_out, carry_out_hk, raw_in;
+    DevBuf seg_out, occ_out, raw_in;
+    // Hit ends of filter segments that may still grow, for every stream,
+    // resident on the device between steps (double-buffered: read one,
+    // write the other).  Order: (step-local stream, pattern, end) of the
+    // step that wrote them.
+    DevBuf carry_buf[2], carry_hk_buf[2];
+    int carry_cur = 0;
+    uint32_t ncarry = 0;
     PinBuf pin_plan, pin_ctl, pin_out, pin_feed;
     size_t pin_feed_used = 0;
     uint32_t cap = 256;
@@ -209,8 +215,6 @@ struct StepPlan {
     std::vector<ChunkDesc> chunks;
     std::vector<StreamDesc> sdesc;
     std::vector<uint32_t> slot_to_local;
-    std::vector<CarryRec> carry;
-    std::vector<uint8_t> carry_hk;
     uint64_t bytes = 0;
 };
 
@@ -232,9 +236,17 @@ uint32_t choose_chunk(oasm_ctx *c, uint64_t bytes) {
     return (uint32_t)((per + 63) & ~63ull);
 }
 
-void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
+// `which` lists the streams matched in this step.  Every other stream that
+// holds carried hit ends joins with no new bytes and as not closing, so its
+// open segments pass through the step unchanged.
+void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which_in, StepPlan &pl) {
+    std::vector<uint32_t> which = which_in;
+    std::vector<char> target(c->streams.size(), 0);
+    for (uint32_t si : which_in) target[si] = 1;
+    for (uint32_t si = 0; si < c->streams.size(); ++si)
+        if (!target[si] && c->streams[si].ncarry > 0) which.push_back(si);
     uint64_t total_new = 0;
-    for (uint32_t si : which) total_new += c->streams[si].valid - c->streams[si].scanned;
+    for (uint32_t si : which_in) total_new += c->streams[si].valid - c->streams[si].scanned;
     const uint32_t C = choose_chunk(c, total_new);
     pl.slot_to_local.assign(c->streams.size(), 0xFFFFFFFFu);
     for (uint32_t si : which) {
@@ -242,7 +254,7 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
         const uint32_t local = (uint32_t)pl.locals.size();
         pl.locals.push_back(si);
         pl.slot_to_local[s.slot] = local;
-        const uint64_t pend = s.valid - s.scanned;
+        const uint64_t pend = target[si] ? s.valid - s.scanned : 0;
         const uint64_t nch = (pend + C - 1) / C;
         for (uint64_t j = 0; j < nch; ++j) {
             const uint64_t e0 = s.scanned + j * C;  // staging index of the first reported end
@@ -261,12 +273,10 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which, StepPlan &pl) {
         StreamDesc sd;
         sd.sym = s.sym;
         sd.base_abs = s.base_abs;
-        sd.frontier = s.base_abs + s.valid;
-        sd.closed = s.close_pending ? 1u : 0u;
+        sd.frontier = s.base_abs + (target[si] ? s.valid : s.scanned);
+        sd.closed = target[si] && s.close_pending ? 1u : 0u;
         sd.slot = s.slot;
         pl.sdesc.push_back(sd);
-        pl.carry.insert(pl.carry.end(), s.carry.begin(), s.carry.end());
-        pl.carry_hk.insert(pl.carry_hk.end(), s.carry_hk.begin(), s.carry_hk.end());
         pl.bytes += pend;
     }
 }
@@ -284,8 +294,6 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     const size_t o_chunks = put(blob, pl.chunks);
     const size_t o_sdesc = put(blob, pl.sdesc);
     const size_t o_s2l = put(blob, pl.slot_to_local);
-    const size_t o_carry = put(blob, pl.carry);
-    const size_t o_carry_hk = put(blob, pl.carry_hk);
     blob.resize(blob.size() + 16);
     c->pin_plan.ensure(blob.size(), st);
     wait_stream(c, "sync before plan upload");  // the pinned plan of the last step may still be read
@@ -296,10 +304,13 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     const ChunkDesc *d_chunks = reinterpret_cast<const ChunkDesc *>(pb + o_chunks);
     const StreamDesc *d_sdesc = reinterpret_cast<const StreamDesc *>(pb + o_sdesc);
     const uint32_t *d_s2l = reinterpret_cast<const uint32_t *>(pb + o_s2l);
-    const CarryRec *d_carry = reinterpret_cast<const CarryRec *>(pb + o_carry);
-    const uint8_t *d_carry_hk = pb + o_carry_hk;
     const uint32_t nchunks = (uint32_t)pl.chunks.size();
-    const uint32_t ncarry = (uint32_t)pl.carry.size();
+    const uint32_t ncarry = c->ncarry;
+    const int cin = c->carry_cur, cout = 1 - c->carry_cur;
+    c->carry_buf[cin].ensure(std::max<uint32_t>(ncarry, 1) * sizeof(CarryRec), st);
+    c->carry_hk_buf[cin].ensure(std::max<uint32_t>(ncarry, 1) * (uint64_t)c->hks, st);
+    const CarryRec *d_carry = c->carry_buf[cin].as<CarryRec>();
+    const uint8_t *d_carry_hk = c->carry_hk_buf[cin].as<uint8_t>();
 
     // control words: [0] max item count, [1] new hit ends, [2] occurrences, [3] carried, [4] recovery errors
     c->ctl.ensure(64, st);
@@ -420,15 +431,15 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     if (rec_err) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
 
     c->occ_out.ensure(std::max<uint32_t>(nocc, 1) * sizeof(OccRec), st);
-    c->carry_out.ensure(std::max<uint32_t>(ncarry_out, 1) * sizeof(CarryRec), st);
-    c->carry_out_hk.ensure(std::max<uint32_t>(ncarry_out, 1) * (uint64_t)hks, st);
+    c->carry_buf[cout].ensure(std::max<uint32_t>(ncarry_out, 1) * sizeof(CarryRec), st);
+    c->carry_hk_buf[cout].ensure(std::max<uint32_t>(ncarry_out, 1) * (uint64_t)hks, st);
     ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), n,
                           out_stride, c->occ_out.as<OccRec>(), st),
        "compact occ");
     ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
                             c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
-                            c->carry_off.as<uint32_t>(), d_sdesc, n, c->carry_out.as<CarryRec>(),
-                            c->carry_out_hk.as<uint8_t>(), st),
+                            c->carry_off.as<uint32_t>(), d_sdesc, n, c->carry_buf[cout].as<CarryRec>(),
+                            c->carry_hk_buf[cout].as<uint8_t>(), st),
        "compact carry");
 
     // copy back: raw (pat, sl, end, flag, dist), hk (when kept), occurrences, carry
@@ -446,7 +457,6 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     const size_t o_dist = slot(need_raw ? n : 0), o_hk = slot(keep_h ? (size_t)n * hks : 0);
     const size_t o_occ = slot((size_t)nocc * sizeof(OccRec));
     const size_t o_cr = slot((size_t)ncarry_out * sizeof(CarryRec));
-    const size_t o_chk = slot((size_t)ncarry_out * hks);
     c->pin_out.ensure(off + 256, st);
     uint8_t *hp = c->pin_out.as<uint8_t>();
     auto d2h = [&](size_t o, const void *src, size_t bytes) {
@@ -461,8 +471,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     }
     if (keep_h) d2h(o_hk, c->r_hk.p, (size_t)n * hks);
     d2h(o_occ, c->occ_out.p, (size_t)nocc * sizeof(OccRec));
-    d2h(o_cr, c->carry_out.p, (size_t)ncarry_out * sizeof(CarryRec));
-    d2h(o_chk, c->carry_out_hk.p, (size_t)ncarry_out * hks);
+    d2h(o_cr, c->carry_buf[cout].p, (size_t)ncarry_out * sizeof(CarryRec));
     ck(hipEventRecord(c->ev2, st), "event");
     wait_stream(c, "sync after copy-back");
     float ms = 0;
@@ -505,21 +514,15 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         const uint64_t sid = c->streams[pl.locals[ho[i].stream_local]].id;
         c->q_occ.push_back(oasm_occ{sid, ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
     }
-    // new carry, per stream
-    for (uint32_t si : pl.locals) {
-        c->streams[si].carry.clear();
-        c->streams[si].carry_hk.clear();
-    }
+    // the new carry stays on the device; the host keeps per-stream counts
+    for (uint32_t si : pl.locals) c->streams[si].ncarry = 0;
     const CarryRec *hc = reinterpret_cast<const CarryRec *>(hp + o_cr);
-    const uint8_t *hck = hp + o_chk;
-    for (uint32_t i = 0; i < ncarry_out; ++i) {
-        const uint32_t sslot = hc[i].stream_slot;
-        StreamState &s = c->streams[sslot];
-        s.carry.push_back(hc[i]);
-        s.carry_hk.insert(s.carry_hk.end(), hck + (size_t)i * hks, hck + (size_t)(i + 1) * hks);
-    }
-    // stream bookkeeping: keep a look-back tail of each stream's symbols
-    for (uint32_t si : pl.locals) {
+    for (uint32_t i = 0; i < ncarry_out; ++i) c->streams[hc[i].stream_slot].ncarry++;
+    c->ncarry = ncarry_out;
+    c->carry_cur = cout;
+    // stream bookkeeping (matched streams only): keep a look-back tail of
+    // each stream's symbols
+    for (uint32_t si : which) {
         StreamState &s = c->streams[si];
         c->stats.bytes_scanned += s.valid - s.scanned;
         s.scanned = s.valid;
@@ -531,8 +534,6 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             s.sym = nullptr;
             s.cap = 0;
             s.valid = s.scanned = 0;
-            s.carry.clear();
-            s.carry_hk.clear();
             continue;
         }
         const size_t keep = std::min<size_t>(s.valid, c->lookback + 4);
@@ -992,8 +993,8 @@ void oasm_destroy(oasm_ctx *c) {
                       &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->offsets, &c->item_rec,
                       &c->item_cnt, &c->ctl, &c->scan_tmp, &c->sort_key, &c->sort_val, &c->sort_end, &c->sort_tmp,
                       &c->r_pat, &c->r_sl, &c->r_end, &c->r_flag, &c->r_dist, &c->r_hk, &c->seg_cnt, &c->seg_off,
-                      &c->carry_flag, &c->carry_off, &c->seg_out, &c->occ_out, &c->carry_out, &c->carry_out_hk,
-                      &c->raw_in};
+                      &c->carry_flag, &c->carry_off, &c->seg_out, &c->occ_out, &c->carry_buf[0], &c->carry_buf[1],
+                      &c->carry_hk_buf[0], &c->carry_hk_buf[1], &c->raw_in};
     for (DevBuf *b : bufs) b->release();
     c->pin_plan.release();
     c->pin_ctl.release();
