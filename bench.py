@@ -40,12 +40,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="long", choices=["long", "batched", "tiny"])
+    ap.add_argument("--workload", default="long", choices=["long", "batched", "tiny", "multiword"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the oracle sample")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--chunk", type=int, default=0, help="chunk bytes (0 = library default)")
     ap.add_argument("--batched-streams", type=int, default=4096)
+    ap.add_argument("--multiword-bytes", type=int, default=1 << 26)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
+    ap.add_argument("--serving-sessions", type=int, default=10_000)
+    ap.add_argument("--serving-gbps", type=float, default=20.0)
+    ap.add_argument("--serving-window", type=float, default=0.05, help="arrival window at the offered load, s")
+    ap.add_argument("--serving-window2", type=float, default=2.0, help="arrival window at 0.8x capacity, s")
+    ap.add_argument("--serving-budget", type=int, default=64 << 20, help="unmatched-byte budget")
+    ap.add_argument("--serving-pool", type=int, default=1 << 26)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times (PMC traffic calibration)")
     return ap.parse_args()
@@ -91,6 +99,10 @@ def make_workload(name: str, args):
         return W.long_stream(), "long-stream: one 64 MiB ACGT text, 256 patterns m~U[16,32], K=3, 10,000 planted copies"
     if name == "tiny":
         return W.tiny(), "tiny: 100,000 ACGT symbols, 16 patterns m~U[8,16], K=2, 200 planted copies"
+    if name == "multiword":
+        w = W.multiword(n=args.multiword_bytes)
+        return w, (f"multiword: one {args.multiword_bytes >> 20} MiB stream of mixture bytes (uniform / printable "
+                   f"runs, mean 40), 4096 patterns m~U[16,256], K=floor(m/10), planted copies over 0.1 % of bytes")
     w = W.batched(n_streams=args.batched_streams)
     return w, (f"batched: {len(w.streams)} streams log-uniform in [1 KiB, 1 MiB], Zipf(1.1) 20 letters, "
                f"1024 patterns m~U[8,64], K=floor(m/10)")
@@ -104,7 +116,7 @@ def cpu_baseline(w, target_s: float):
     text = w.streams[0] if len(w.streams) == 1 else np.concatenate(w.streams[:64])
     msum = sum(len(p) for p in w.patterns)
     # calibrate on a small prefix, then size the sample to ~target_s
-    probe = min(text.size, 8192)
+    probe = min(text.size, 1 << 18)
     t0 = time.perf_counter()
     oracle.run_pairs(w.patterns, w.ks, text[:probe], threads=threads)
     dt = max(time.perf_counter() - t0, 1e-3)
@@ -166,6 +178,49 @@ def batched_vs_plain(oasm, torch, args, w=None):
             "batched_gcups": round(cells / tb / 1e9, 1), "plain_gcups": round(cells / tp / 1e9, 1),
             "batched_ms": round(tb * 1e3, 2), "plain_ms": round(tp * 1e3, 2), "speedup": round(tp / tb, 2),
             "hit_ends": int(b["res"].raw.size), "occurrences": int(b["res"].occ.size)}
+
+
+def serving_measure(oasm, torch, args):
+    """Continuous batching of Poisson segment arrivals (10,000 sessions,
+    2048 patterns m~U[16,128], 1..64 KiB segments of mixture bytes): one point
+    at the configured offered load (20 GB/s, far above one GPU's capacity for
+    this dictionary: it measures the sustained rate and the queueing), one at
+    0.8x the sustained rate (latency under a load the GPU can carry)."""
+    from paper_1712_03560_amd import workloads as W
+
+    pats, ks = W.serving_dictionary()
+    pool = W.serving_pool(args.serving_pool)
+    dpool = torch.from_numpy(pool).cuda()
+    msum = sum(len(p) for p in pats)
+    out = {"workload": f"{args.serving_sessions} sessions, {len(pats)} patterns m~U[16,128] K=floor(m/10), "
+                       f"segments U[1,64] KiB of mixture bytes, Poisson arrivals",
+           "mem_budget_bytes": args.serving_budget}
+
+    def point(gbps, duration):
+        sess, off, ln, t = W.serving_arrivals(args.serving_sessions, duration, gbps, pool.size)
+        segs = np.zeros(t.size, dtype=oasm.SEG_DTYPE)
+        segs["stream"], segs["offset"], segs["len"], segs["arrival_s"] = sess, off, ln, t
+        with oasm.Matcher(pats, ks, mem_budget=args.serving_budget, no_raw=True) as mt:
+            # warm the context (kernels, pools) on a small prefix
+            mt.serve(segs[:200].copy(), dpool, want_latency=False)
+            mt.results()
+        with oasm.Matcher(pats, ks, mem_budget=args.serving_budget, no_raw=True) as mt:
+            rep, lat = mt.serve(segs, dpool)
+            res = mt.results()
+        nbytes = int(ln.sum())
+        return {"offered_GBps": gbps, "arrival_window_s": duration, "segments": int(t.size), "bytes": nbytes,
+                "steps": rep["steps"], "deferred": rep["deferred"], "max_batch_bytes": rep["max_batch_bytes"],
+                "wall_s": round(rep["wall_s"], 3), "sustained_GBps": round(nbytes / rep["busy_s"] / 1e9, 4),
+                "gcups": round(msum * nbytes / rep["busy_s"] / 1e9, 1),
+                "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                "occurrences": int(res.occ.size)}
+
+    hi = point(args.serving_gbps, args.serving_window)
+    out["at_offered_load"] = hi
+    lo_rate = 0.8 * hi["sustained_GBps"]
+    out["at_0p8_capacity"] = point(lo_rate, args.serving_window2)
+    return out
 
 
 def main():
@@ -234,6 +289,8 @@ def main():
     }
     if args.workload == "batched" or not args.no_batched:
         line["batched_vs_plain"] = batched_vs_plain(oasm, torch, args, w if args.workload == "batched" else None)
+    if not args.no_serving:
+        line["serving"] = serving_measure(oasm, torch, args)
     if not args.no_cpu_baseline and args.workload != "batched":
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)

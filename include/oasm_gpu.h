@@ -122,8 +122,30 @@ typedef struct oasm_config {
     void *hip_stream;            /* hipStream_t to run on; NULL = library-owned stream */
     uint32_t chunk_bytes;        /* text bytes per scan work item; 0 = autotuned */
     uint32_t flags;              /* OASM_CFG_* */
-    uint64_t device_mem_budget;  /* bytes of staged stream data allowed; 0 = unlimited */
+    uint64_t device_mem_budget;  /* bytes of fed, not yet matched stream data allowed; 0 = unlimited */
 } oasm_config;
+
+/* One segment of a serving run: `len` bytes at `offset` of a device-resident
+ * pool, appended to stream `stream`, arriving `arrival_s` seconds after the
+ * start of the run. */
+typedef struct oasm_segment {
+    uint64_t stream;
+    uint64_t offset;
+    uint32_t len;
+    uint32_t flags;     /* OASM_FEED_LAST: the stream ends with this segment */
+    double arrival_s;
+} oasm_segment;
+
+/* Summary of a serving run. */
+typedef struct oasm_serve_report {
+    uint64_t segments;        /* segments served */
+    uint64_t bytes;           /* bytes served */
+    uint64_t steps;           /* matching steps (batches) run */
+    uint64_t deferred;        /* loop iterations that left ready segments waiting for memory */
+    uint64_t max_batch_bytes; /* largest batch */
+    double wall_s;            /* start of the run to the last completion */
+    double busy_s;            /* time spent in ingest and matching steps */
+} oasm_serve_report;
 
 /* Per-context counters (cumulative since create). */
 typedef struct oasm_stats {
@@ -161,7 +183,8 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
  * oasm_sync.  Feeds to one stream are concatenated in call order.  With
  * OASM_FEED_LAST the stream is closed after these bytes.
  * Errors: OASM_E_INVAL (ctx NULL, bytes NULL with n > 0), OASM_E_CLOSED,
- * OASM_E_AGAIN (device_mem_budget would be exceeded; sync and retry),
+ * OASM_E_AGAIN (the fed-but-unmatched bytes would exceed device_mem_budget;
+ * sync and retry),
  * OASM_E_NOMEM, OASM_E_DEVICE.
  */
 oasm_status oasm_feed(oasm_ctx *ctx, uint64_t stream_id, const uint8_t *bytes, size_t n, uint32_t flags);
@@ -197,6 +220,26 @@ oasm_status oasm_sync(oasm_ctx *ctx);
  * follow each other in call order.
  */
 oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_t *n_out, int *more);
+
+/*
+ * Continuous-batching request loop over `n` segments sorted by arrival_s.
+ * Segments are admitted in arrival order as soon as they have arrived, while
+ * the fed-but-unmatched bytes stay within cfg.device_mem_budget (0 = no
+ * limit; one segment is always admitted when nothing is pending).  Each
+ * iteration copies every admitted segment from `dev_pool` (device memory of
+ * `pool_bytes` bytes, owned by the caller) into its stream with one batched
+ * kernel and runs one matching step over all of them, so segments of many
+ * streams share each launch while later arrivals wait for the next one.  The
+ * loop runs in real time: when nothing is ready it sleeps until the next
+ * arrival.  latency_s (optional, n entries) receives, per segment, the time
+ * from its arrival to the end of the step that matched it (its hit ends are
+ * then drainable and its filter has advanced as far as the bytes allow).
+ * Results are queued as by oasm_sync.  Errors: OASM_E_INVAL (NULL pointers,
+ * unsorted arrivals, a segment outside the pool, a closed stream),
+ * OASM_E_NOMEM, OASM_E_DEVICE.
+ */
+oasm_status oasm_serve(oasm_ctx *ctx, const oasm_segment *segs, size_t n, const void *dev_pool, uint64_t pool_bytes,
+                       double *latency_s, oasm_serve_report *report);
 
 /* Number of records of `kind` queued for draining (OASM_E_INVAL for an
  * unknown kind, or OASM_H without OASM_CFG_KEEP_H). */

@@ -84,6 +84,15 @@ hipError_t launch_peq_build(const uint8_t *pat_bytes, const PatDesc *pats, uint3
 hipError_t launch_map_symbols(const uint8_t *src, uint8_t *dst, uint64_t n, const uint8_t *class_of,
                               hipStream_t st);
 
+// One segment of a batched ingest: len bytes from src mapped into dst.
+struct SegCopy {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint32_t len;
+    uint32_t pad;
+};
+hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *class_of, hipStream_t st);
+
 // K1: the bit-parallel scan for one word-count class (W words, P patterns
 // per lane).  Grid: (ceil(nchunks / waves_per_block), ntiles).
 struct ScanArgs {

@@ -137,6 +137,23 @@ hipError_t launch_map_symbols(const uint8_t *src, uint8_t *dst, uint64_t n, cons
     return hipGetLastError();
 }
 
+// Many segments at once (one block per segment): the serving loop's batched
+// ingest from a device pool into the streams' staging buffers.
+__global__ void __launch_bounds__(256) k_map_segments(const SegCopy *__restrict__ segs,
+                                                      const uint8_t *__restrict__ class_of) {
+    __shared__ uint8_t tab[256];
+    tab[threadIdx.x] = class_of[threadIdx.x];
+    __syncthreads();
+    const SegCopy sc = segs[blockIdx.x];
+    for (uint32_t i = threadIdx.x; i < sc.len; i += blockDim.x) sc.dst[i] = tab[sc.src[i]];
+}
+
+hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *class_of, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_map_segments, dim3(n), dim3(256), 0, st, segs, class_of);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ K1
 // Truth-table operands of v_bitop3_b32: the result bit for inputs (a, b, c)
 // is bit (a*4 + b*2 + c) of the immediate.

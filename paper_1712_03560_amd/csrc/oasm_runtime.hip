@@ -21,6 +21,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <thread>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -132,7 +133,8 @@ struct oasm_ctx {
     std::vector<uint16_t> m, k;
     uint32_t mmax = 0, kmax = 0, hks = 1, lookback = 0, nclass = 1;
     uint8_t class_of[256];
-    uint64_t msum = 0;
+    uint64_t msum = 0;   // sum of pattern lengths (cells per byte)
+    uint64_t wsum = 0;   // sum of 32-bit words (word-steps per byte)
     std::vector<ClassInfo> classes;
     uint32_t ntiles = 0;
     DevBuf d_pats, d_slot_pat, d_tiles, d_peq, d_rpeq, d_class, d_patbytes, d_pat_tile, d_pat_slot, d_tile_wp;
@@ -164,7 +166,10 @@ struct oasm_ctx {
     size_t rd_raw = 0, rd_occ = 0, rd_h = 0;
 
     oasm_stats stats{};
-    uint64_t staged_bytes = 0;  // staging capacity held by open streams
+    uint64_t staged_bytes = 0;   // staging capacity held by open streams
+    uint64_t pending_bytes = 0;  // fed, not yet matched
+    PinBuf pin_seg;
+    DevBuf d_seg;
 
     // Staging buffers of closed streams, kept for reuse.  Every byte of them
     // was written by this context (cleared at allocation, then mapped
@@ -525,6 +530,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     for (uint32_t si : which) {
         StreamState &s = c->streams[si];
         c->stats.bytes_scanned += s.valid - s.scanned;
+        c->pending_bytes -= s.valid - s.scanned;
         s.scanned = s.valid;
         if (s.close_pending) {
             s.close_pending = false;
@@ -638,8 +644,6 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n) {
     const size_t need = s.valid + n + kPad;
     if (need <= s.cap) return OASM_OK;
     const size_t want = std::max(need, s.cap + s.cap / 2);
-    if (c->cfg.device_mem_budget && c->staged_bytes - s.cap + want > c->cfg.device_mem_budget)
-        return fail(c, OASM_E_AGAIN, "device memory budget for staged stream data exhausted");
     size_t cap = 0;
     uint8_t *p = acquire_staging(c, want, cap);
     if (!p) return fail(c, OASM_E_NOMEM, "hipMalloc for stream staging failed");
@@ -737,6 +741,7 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
             c->mmax = std::max<uint32_t>(c->mmax, c->m[i]);
             c->kmax = std::max<uint32_t>(c->kmax, c->k[i]);
             c->msum += c->m[i];
+            c->wsum += (c->m[i] + 31) / 32;
             pd[i].off = (uint32_t)bytes.size();
             pd[i].m = c->m[i];
             pd[i].k = c->k[i];
@@ -843,6 +848,8 @@ static oasm_status feed_common(oasm_ctx *c, uint64_t stream_id, const void *src,
         if (device) ck(hipSetDevice(c->device), "hipSetDevice");
         StreamState &s = get_stream(c, stream_id, true);
         if (s.closed || s.close_pending) return fail(c, OASM_E_CLOSED, "feed to a closed stream");
+        if (n > 0 && c->cfg.device_mem_budget && c->pending_bytes + n > c->cfg.device_mem_budget)
+            return fail(c, OASM_E_AGAIN, "device memory budget for unmatched stream data exhausted");
         if (n > 0) {
             oasm_status r = reserve_stream(c, s, n);
             if (r != OASM_OK) return r;
@@ -871,11 +878,9 @@ static oasm_status feed_common(oasm_ctx *c, uint64_t stream_id, const void *src,
                    "map symbols");
             }
             s.valid += n;
+            c->pending_bytes += n;
             c->stats.cells += (uint64_t)n * c->msum;
-            uint64_t ws = 0;
-            for (const ClassInfo &ci : c->classes) (void)ci;
-            for (uint32_t i = 0; i < c->npat; ++i) ws += (c->m[i] + 31) / 32;
-            c->stats.word_steps += (uint64_t)n * ws;
+            c->stats.word_steps += (uint64_t)n * c->wsum;
         }
         if (flags & OASM_FEED_LAST) s.close_pending = true;
     } catch (const HipFail &f) {
@@ -921,6 +926,101 @@ oasm_status oasm_sync(oasm_ctx *c) {
         return fail(c, OASM_E_NOMEM, "host allocation failed");
     }
     c->stats.sync_wall_ms += now_ms() - t0;
+    return OASM_OK;
+}
+
+oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const void *dev_pool, uint64_t pool_bytes,
+                       double *latency_s, oasm_serve_report *report) {
+    if (!c || (n > 0 && (!segs || !dev_pool))) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    for (size_t i = 0; i < n; ++i) {
+        if (segs[i].offset + segs[i].len > pool_bytes) return fail(c, OASM_E_INVAL, "segment outside the pool");
+        if (i && segs[i].arrival_s < segs[i - 1].arrival_s)
+            return fail(c, OASM_E_INVAL, "segments must be sorted by arrival");
+    }
+    oasm_serve_report rep{};
+    const uint8_t *pool = reinterpret_cast<const uint8_t *>(dev_pool);
+    const double t0 = now_ms();
+    size_t next = 0;
+    std::deque<size_t> ready;
+    std::vector<size_t> batch;
+    std::vector<SegCopy> copies;
+    std::unordered_map<uint32_t, uint64_t> add;  // stream slot -> bytes admitted this iteration
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        while (next < n || !ready.empty()) {
+            const double t = (now_ms() - t0) * 1e-3;
+            while (next < n && segs[next].arrival_s <= t) ready.push_back(next++);
+            if (ready.empty()) {
+                const double dt = segs[next].arrival_s - t;
+                if (dt > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(dt, 0.01)));
+                continue;
+            }
+            // admission: arrival order, within the budget for unmatched bytes
+            batch.clear();
+            add.clear();
+            uint64_t admit = 0;
+            const uint64_t budget = c->cfg.device_mem_budget;
+            while (!ready.empty()) {
+                const oasm_segment &sg = segs[ready.front()];
+                if (budget && c->pending_bytes + admit + sg.len > budget && (admit > 0 || c->pending_bytes > 0)) {
+                    rep.deferred++;
+                    break;
+                }
+                StreamState &s = get_stream(c, sg.stream, true);
+                if (s.closed || s.close_pending) return fail(c, OASM_E_INVAL, "segment for a closed stream");
+                add[s.slot] += sg.len;
+                admit += sg.len;
+                batch.push_back(ready.front());
+                ready.pop_front();
+                if (sg.flags & OASM_FEED_LAST) s.close_pending = true;  // later segments of it are refused above
+            }
+            // one staging reservation per stream, then the copies
+            for (auto &kv : add) {
+                oasm_status r = reserve_stream(c, c->streams[kv.first], kv.second);
+                if (r != OASM_OK) return r;
+            }
+            copies.clear();
+            for (size_t i : batch) {
+                const oasm_segment &sg = segs[i];
+                StreamState &s = c->streams[c->slot_of[sg.stream]];
+                if (sg.len) copies.push_back(SegCopy{pool + sg.offset, s.sym + s.valid, sg.len, 0});
+                s.valid += sg.len;
+                c->pending_bytes += sg.len;
+                c->stats.cells += (uint64_t)sg.len * c->msum;
+                c->stats.word_steps += (uint64_t)sg.len * c->wsum;
+            }
+            const double tb = now_ms();
+            if (!copies.empty()) {
+                c->pin_seg.ensure(copies.size() * sizeof(SegCopy), c->st);
+                c->d_seg.ensure(copies.size() * sizeof(SegCopy), c->st);
+                std::memcpy(c->pin_seg.p, copies.data(), copies.size() * sizeof(SegCopy));
+                ck(hipMemcpyAsync(c->d_seg.p, c->pin_seg.p, copies.size() * sizeof(SegCopy), hipMemcpyHostToDevice,
+                                  c->st),
+                   "segment table upload");
+                ck(launch_map_segments(c->d_seg.as<SegCopy>(), (uint32_t)copies.size(), c->d_class.as<uint8_t>(),
+                                       c->st),
+                   "map segments");
+            }
+            sync_all(c);
+            const double te = now_ms();
+            rep.busy_s += (te - tb) * 1e-3;
+            rep.steps++;
+            rep.max_batch_bytes = std::max<uint64_t>(rep.max_batch_bytes, admit);
+            rep.segments += batch.size();
+            rep.bytes += admit;
+            const double done = (te - t0) * 1e-3;
+            if (latency_s)
+                for (size_t i : batch) latency_s[i] = done - segs[i].arrival_s;
+        }
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
+    } catch (const std::bad_alloc &) {
+        return fail(c, OASM_E_NOMEM, "host allocation failed");
+    }
+    rep.wall_s = (now_ms() - t0) * 1e-3;
+    if (report) *report = rep;
     return OASM_OK;
 }
 
@@ -1000,6 +1100,8 @@ void oasm_destroy(oasm_ctx *c) {
     c->pin_ctl.release();
     c->pin_out.release();
     c->pin_feed.release();
+    c->pin_seg.release();
+    c->d_seg.release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev2) (void)hipEventDestroy(c->ev2);

@@ -48,6 +48,7 @@ EXPORTED = [
     "oasm_sync",
     "oasm_hits",
     "oasm_queued",
+    "oasm_serve",
     "oasm_get_stats",
     "oasm_destroy",
     "oasm_last_error",
@@ -82,6 +83,13 @@ class oasm_stats(ctypes.Structure):
                 ("scan_launches", ctypes.c_uint64), ("sync_wall_ms", ctypes.c_double), ("wait_ms", ctypes.c_double)]
 
 
+class oasm_serve_report(ctypes.Structure):
+    _fields_ = [("segments", ctypes.c_uint64), ("bytes", ctypes.c_uint64), ("steps", ctypes.c_uint64),
+                ("deferred", ctypes.c_uint64), ("max_batch_bytes", ctypes.c_uint64), ("wall_s", ctypes.c_double),
+                ("busy_s", ctypes.c_double)]
+
+
+SEG_DTYPE = np.dtype([("stream", "<u8"), ("offset", "<u8"), ("len", "<u4"), ("flags", "<u4"), ("arrival_s", "<f8")])
 HIT_DTYPE = np.dtype([("stream", "<u8"), ("end", "<u8"), ("pattern", "<u4"), ("dist", "<u4")])
 OCC_DTYPE = np.dtype([("stream", "<u8"), ("start", "<u8"), ("pattern", "<u4"), ("len", "<u4"), ("k", "<u4"),
                       ("reserved", "<u4")])
@@ -110,6 +118,8 @@ def _load():
     lib.oasm_sync.restype = i32
     lib.oasm_hits.argtypes = [P, u32, P, sz, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_int)]
     lib.oasm_hits.restype = i32
+    lib.oasm_serve.argtypes = [P, P, sz, P, u64, P, ctypes.POINTER(oasm_serve_report)]
+    lib.oasm_serve.restype = i32
     lib.oasm_queued.argtypes = [P, u32, ctypes.POINTER(sz)]
     lib.oasm_queued.restype = i32
     lib.oasm_get_stats.argtypes = [P, ctypes.POINTER(oasm_stats)]
@@ -204,6 +214,18 @@ def oasm_hits(ctx, kind: int) -> np.ndarray:
     return buf[: n.value]
 
 
+def oasm_serve(ctx, segs: np.ndarray, pool_ptr: int, pool_bytes: int, want_latency: bool = True):
+    """Run the continuous-batching loop over a SEG_DTYPE array; returns (report dict, latencies or None)."""
+    segs = np.ascontiguousarray(segs, dtype=SEG_DTYPE)
+    lat = np.zeros(segs.size, dtype=np.float64) if want_latency else None
+    rep = oasm_serve_report()
+    _check(ctx, lib.oasm_serve(ctx, segs.ctypes.data_as(ctypes.c_void_p) if segs.size else None, segs.size,
+                               pool_ptr, pool_bytes,
+                               lat.ctypes.data_as(ctypes.c_void_p) if lat is not None and lat.size else None,
+                               ctypes.byref(rep)))
+    return {name: getattr(rep, name) for name, _ in oasm_serve_report._fields_}, lat
+
+
 def oasm_get_stats(ctx) -> dict:
     s = oasm_stats()
     _check(ctx, lib.oasm_get_stats(ctx, ctypes.byref(s)))
@@ -274,6 +296,15 @@ class Matcher:
         occ = oasm_hits(self.ctx, OASM_FILTERED)
         h = oasm_hits(self.ctx, OASM_H) if self.keep_h else None
         return Results(raw, occ, h)
+
+    def serve(self, segs: np.ndarray, pool, want_latency: bool = True):
+        """Continuous batching over segments of a device-resident pool (a CUDA uint8 tensor)."""
+        import torch  # only for the device pool
+
+        if not isinstance(pool, torch.Tensor) or not pool.is_cuda or pool.dtype != torch.uint8:
+            raise ValueError("the pool must be a CUDA uint8 tensor")
+        torch.cuda.current_stream(pool.device).synchronize()
+        return oasm_serve(self.ctx, segs, pool.data_ptr(), pool.numel(), want_latency)
 
     def stats(self) -> dict:
         return oasm_get_stats(self.ctx)

@@ -21,8 +21,8 @@ a small alphabet, Section 7) scaled up to dictionary/stream sizes:
                    K = floor(m/10); planted copies covering about 0.1 % of
                    the bytes.
 * ``serving``   -- 2048 patterns of 16..128 bytes (mixture process),
-                   K = floor(m/10), and sessions that send 1..64 KiB segments
-                   with Poisson arrivals.
+                   K = floor(m/10), and 10,000 sessions that send 1..64 KiB
+                   segments of a mixture-byte pool with Poisson arrivals.
 
 Every generator is a pure function of its arguments and seed (numpy PCG64).
 """
@@ -242,42 +242,35 @@ def multiword(n: int = 1 << 30, n_patterns: int = 4096, plant_fraction: float = 
     return Workload("multiword", [text], pats, ks, pl)
 
 
-@dataclass
-class Segment:
-    session: int
-    arrival_s: float  # seconds since the start of the run
-    data: np.ndarray  # uint8
-
-
-def serving(n_sessions: int = 10_000, n_patterns: int = 2048, duration_s: float = 10.0,
-            offered_gbps: float = 20.0, pool_bytes: int = 1 << 30, seg_lo: int = 1024, seg_hi: int = 65536,
-            seed_sub: int = 0):
-    """Dictionary plus a Poisson segment trace.
-
-    Each session sends segments of U{seg_lo..seg_hi} bytes with exponential
-    inter-arrival times so that the aggregate offered load is
-    ``offered_gbps`` GB/s.  Segment bytes are slices of one pre-generated pool
-    (mixture process) at random offsets.  Returns (patterns, ks, pool,
-    arrivals) where arrivals is a time-ordered list of
-    (time_s, session, pool_offset, length)."""
+def serving_dictionary(n_patterns: int = 2048, seed_sub: int = 0):
+    """2048 patterns of 16..128 bytes from the mixture process, K = floor(m/10)."""
     rng = rng_for(5, seed_sub)
     pats = make_patterns(rng, n_patterns, 16, 128, LETTERS_MIX)
-    ks = k_tenth(pats)
-    pool = LETTERS_MIX.draw(rng, pool_bytes)
+    return pats, k_tenth(pats)
+
+
+def serving_pool(pool_bytes: int = 1 << 28, seed_sub: int = 0) -> np.ndarray:
+    """The byte pool segments are cut from (mixture process)."""
+    return LETTERS_MIX.draw(rng_for(5, 100 + seed_sub), pool_bytes)
+
+
+def serving_arrivals(n_sessions: int = 10_000, duration_s: float = 1.0, offered_gbps: float = 20.0,
+                     pool_bytes: int = 1 << 28, seg_lo: int = 1024, seg_hi: int = 65536, seed_sub: int = 0):
+    """Poisson segment arrivals: every session sends segments of U{seg_lo..seg_hi}
+    bytes as a Poisson process whose rate makes the aggregate offered load
+    ``offered_gbps`` GB/s (1e9 B/s).  Returns arrays (session, offset, length,
+    arrival_s) sorted by arrival time; offsets are uniform in the pool."""
+    rng = rng_for(5, 200 + seed_sub)
     mean_seg = (seg_lo + seg_hi) / 2.0
-    rate_per_session = offered_gbps * 1e9 / mean_seg / max(1, n_sessions)
-    arrivals = []
-    for s in range(n_sessions):
-        t = 0.0
-        while True:
-            t += float(rng.exponential(1.0 / rate_per_session))
-            if t >= duration_s:
-                break
-            ln = int(rng.integers(seg_lo, seg_hi + 1))
-            off = int(rng.integers(0, pool_bytes - ln + 1))
-            arrivals.append((t, s, off, ln))
-    arrivals.sort()
-    return pats, ks, pool, arrivals
+    rate = offered_gbps * 1e9 / mean_seg / max(1, n_sessions)  # per session, segments / s
+    counts = rng.poisson(rate * duration_s, size=n_sessions)
+    total = int(counts.sum())
+    session = np.repeat(np.arange(n_sessions, dtype=np.uint64), counts)
+    t = rng.uniform(0.0, duration_s, size=total)  # a Poisson process, given its count
+    length = rng.integers(seg_lo, seg_hi + 1, size=total).astype(np.uint32)
+    offset = (rng.random(total) * (pool_bytes - length)).astype(np.uint64)
+    order = np.argsort(t, kind="stable")
+    return session[order], offset[order], length[order], t[order]
 
 
 def small_random(seed: int, n: int, n_patterns: int, mlo: int, mhi: int, alphabet: bytes, kmax: int | None = None,

@@ -51,6 +51,8 @@ def test_record_layouts():
     assert ctypes.sizeof(oasm.oasm_occ) == 32
     assert ctypes.sizeof(oasm.oasm_config) == 32
     assert ctypes.sizeof(oasm.oasm_stats) == 96
+    assert ctypes.sizeof(oasm.oasm_serve_report) == 56
+    assert oasm.SEG_DTYPE.itemsize == 32
 
 
 def test_status_strings(lib):

@@ -1,0 +1,76 @@
+"""The continuous-batching loop (needs an MI355X): every session's results are
+the same alone and in the mix, equal to the oracle on the session's
+concatenated bytes, with and without a memory budget that defers admissions."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1712_03560_amd import oasm  # noqa: E402
+from paper_1712_03560_amd import workloads as W  # noqa: E402
+from parity_util import compare  # noqa: E402
+
+
+def make_trace(seed=5, sessions=40, pool_bytes=1 << 20, duration=0.05):
+    rng = np.random.default_rng(seed)
+    pats = W.make_patterns(rng, 48, 12, 70, W.LETTERS_ACGT)
+    ks = np.array([min(len(p) // 6, 6) for p in pats], dtype=np.uint16)
+    pool = W.LETTERS_ACGT.draw(rng, pool_bytes)
+    W.plant(rng, pool, pats, 400, ks, W.LETTERS_ACGT)
+    rows = []
+    for s in range(sessions):
+        nseg = int(rng.integers(2, 8))
+        times = np.sort(rng.uniform(0, duration, size=nseg))
+        for j, t in enumerate(times):
+            ln = int(rng.integers(1, 4096))
+            off = int(rng.integers(0, pool_bytes - ln))
+            rows.append((1000 + s, off, ln, oasm.OASM_FEED_LAST if j == nseg - 1 else 0, float(t)))
+    rows.sort(key=lambda r: r[4])
+    segs = np.array(rows, dtype=oasm.SEG_DTYPE)
+    return pats, ks, pool, segs
+
+
+def session_bytes(pool, segs, sid):
+    parts = [pool[int(r["offset"]):int(r["offset"]) + int(r["len"])] for r in segs if int(r["stream"]) == sid]
+    return np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+
+
+def serve(pats, ks, dpool, segs, budget=0):
+    with oasm.Matcher(pats, ks, mem_budget=budget) as mt:
+        rep, lat = mt.serve(segs, dpool)
+        res = mt.results()
+    return rep, lat, res
+
+
+def rows_of(res, sid):
+    r = res.raw[res.raw["stream"] == sid]
+    o = res.occ[res.occ["stream"] == sid]
+    return np.sort(r, order=["pattern", "end"]), np.sort(o, order=["pattern", "start"])
+
+
+@pytest.mark.parametrize("budget", [0, 6000])
+def test_alone_equals_mix_equals_oracle(budget):
+    pats, ks, pool, segs = make_trace()
+    dpool = torch.from_numpy(pool).cuda()
+    rep, lat, mix = serve(pats, ks, dpool, segs, budget)
+    print(f"[serving] budget {budget}: {rep}", file=sys.stderr, flush=True)
+    assert rep["segments"] == segs.size and rep["bytes"] == int(segs["len"].sum())
+    assert (lat >= 0).all()
+    if budget:
+        assert rep["deferred"] > 0 and rep["steps"] > 1
+    sids = sorted(set(int(x) for x in segs["stream"]))
+    # alone: three sessions, each served by itself
+    for sid in sids[:3]:
+        _, _, alone = serve(pats, ks, dpool, segs[segs["stream"] == sid])
+        a_raw, a_occ = rows_of(alone, sid)
+        m_raw, m_occ = rows_of(mix, sid)
+        assert np.array_equal(a_raw, m_raw) and np.array_equal(a_occ, m_occ), f"session {sid} differs alone/mix"
+    # oracle on every session's concatenated bytes
+    streams = {sid: session_bytes(pool, segs, sid) for sid in sids}
+    compare(mix, streams, pats, ks, label=f"serving-budget{budget}")
