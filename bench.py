@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--batched-streams", type=int, default=4096)
     ap.add_argument("--multiword-bytes", type=int, default=1 << 26)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="heuristic scan variants instead of measured ones")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serving-sessions", type=int, default=10_000)
     ap.add_argument("--serving-gbps", type=float, default=20.0)
@@ -130,11 +131,12 @@ def cpu_baseline(w, target_s: float):
                       f"(hit ends, hit set and filter), {dt:.1f} s"}
 
 
-def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False):
+def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True):
     """Time `steps` whole-path steps over device-resident streams (after `warmup`)."""
     dev_streams = [torch.from_numpy(t).cuda() for t in w.streams]
     torch.cuda.synchronize()
-    mt = oasm.Matcher(w.patterns, w.ks, chunk_bytes=chunk, plain=plain)
+    mt = oasm.Matcher(w.patterns, w.ks, chunk_bytes=chunk, plain=plain, autotune=autotune)
+    tune = mt.tune_report()
     sid = [0]
 
     def step():
@@ -158,7 +160,7 @@ def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False):
     s1 = mt.stats()
     mt.destroy()
     del dev_streams
-    return {"s0": s0, "s1": s1, "elapsed": elapsed, "res": res}
+    return {"s0": s0, "s1": s1, "elapsed": elapsed, "res": res, "tune": tune}
 
 
 def batched_vs_plain(oasm, torch, args, w=None):
@@ -200,11 +202,11 @@ def serving_measure(oasm, torch, args):
         sess, off, ln, t = W.serving_arrivals(args.serving_sessions, duration, gbps, pool.size)
         segs = np.zeros(t.size, dtype=oasm.SEG_DTYPE)
         segs["stream"], segs["offset"], segs["len"], segs["arrival_s"] = sess, off, ln, t
-        with oasm.Matcher(pats, ks, mem_budget=args.serving_budget, no_raw=True) as mt:
-            # warm the context (kernels, pools) on a small prefix
+        with oasm.Matcher(pats, ks, mem_budget=args.serving_budget, no_raw=True, autotune=True) as mt:
+            # warm the context (kernels, pools, tuning cache) on a small prefix
             mt.serve(segs[:200].copy(), dpool, want_latency=False)
             mt.results()
-        with oasm.Matcher(pats, ks, mem_budget=args.serving_budget, no_raw=True) as mt:
+        with oasm.Matcher(pats, ks, mem_budget=args.serving_budget, no_raw=True, autotune=True) as mt:
             rep, lat = mt.serve(segs, dpool)
             res = mt.results()
         nbytes = int(ln.sum())
@@ -243,7 +245,7 @@ def main():
     if args.calibrate_copy:
         copy_calibration()
     w, desc = make_workload(args.workload, args)
-    r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk)
+    r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk, autotune=not args.no_autotune)
     msum = sum(len(p) for p in w.patterns)
     total_bytes = w.total_bytes
     cells = msum * total_bytes
@@ -286,6 +288,7 @@ def main():
             "sync_waiting": round((s1["wait_ms"] - s0["wait_ms"]) / args.steps, 3),
         },
         "hits": {"hit_ends": int(res.raw.size), "occurrences": int(res.occ.size)},
+        "autotune": [x for x in r["tune"].splitlines() if x],
     }
     if args.workload == "batched" or not args.no_batched:
         line["batched_vs_plain"] = batched_vs_plain(oasm, torch, args, w if args.workload == "batched" else None)

@@ -83,6 +83,7 @@ typedef int32_t oasm_status;
 #define OASM_CFG_PLAIN 1u  /* one launch sequence per stream instead of one batched launch */
 #define OASM_CFG_KEEP_H 2u /* keep the hit set for draining with OASM_H (debugging) */
 #define OASM_CFG_NO_RAW 4u /* do not queue hit ends for draining (they are still computed) */
+#define OASM_CFG_AUTOTUNE 8u /* time the scan variants of every pattern class at create and keep the fastest */
 
 /* Drain kinds. */
 #define OASM_RAW 0u      /* oasm_hit records: hit ends and their distance */
@@ -251,6 +252,11 @@ oasm_status oasm_get_stats(const oasm_ctx *ctx, oasm_stats *out);
 /* Free the context and everything it owns (NULL is a no-op).  Waits for
  * the context's device work to finish. */
 void oasm_destroy(oasm_ctx *ctx);
+
+/* The autotuner's measurements and choices, one line per variant tried
+ * ("W=<words> P=<patterns per lane> lds=<0|1>: <ms>"); empty without
+ * OASM_CFG_AUTOTUNE or when every class came from the process-wide cache. */
+const char *oasm_tune_report(const oasm_ctx *ctx);
 
 /* Message for the last error on this context (never NULL). */
 const char *oasm_last_error(const oasm_ctx *ctx);

@@ -20,6 +20,8 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
+#include <tuple>
 #include <mutex>
 #include <thread>
 #include <string>
@@ -137,6 +139,11 @@ struct oasm_ctx {
     uint64_t wsum = 0;   // sum of 32-bit words (word-steps per byte)
     std::vector<ClassInfo> classes;
     uint32_t ntiles = 0;
+    std::vector<uint8_t> h_patbytes;  // host copies for rebuilding tiles
+    std::vector<PatDesc> h_pd;
+    uint64_t rpeq_words = 0;
+    size_t max_lds = 64 * 1024;       // dynamic LDS a block may use on this device
+    std::string tune_log;             // choices made by the autotuner
     DevBuf d_pats, d_slot_pat, d_tiles, d_peq, d_rpeq, d_class, d_patbytes, d_pat_tile, d_pat_slot, d_tile_wp;
     std::vector<uint32_t> class_w32;  // per pattern: words
 
@@ -657,6 +664,218 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n) {
     return OASM_OK;
 }
 
+// ------------------------------------------------------------------ tiles
+struct TileChoice {
+    int P = 1;         // patterns per lane
+    bool lds = true;   // match-mask image in LDS (else read through L1/L2)
+};
+
+uint32_t pad_pow2_host(uint32_t x) { return x <= 1 ? 1 : x <= 2 ? 2 : x <= 4 ? 4 : 8; }
+
+uint64_t image_bytes(const oasm_ctx *c, int W, int P) {
+    return (uint64_t)c->nclass * 64 * pad_pow2_host((uint32_t)(P * W)) * 4;
+}
+
+std::vector<uint32_t> class_members(const oasm_ctx *c, int W) {
+    std::vector<uint32_t> ids;
+    for (uint32_t i = 0; i < c->npat; ++i)
+        if ((uint32_t)((c->m[i] + 31) / 32) == (uint32_t)W) ids.push_back(i);
+    return ids;
+}
+
+// Heuristic without measurement: more patterns per lane for short patterns
+// when there are enough of them; the image in LDS when it leaves room for
+// two blocks per CU.
+std::vector<TileChoice> default_choices(const oasm_ctx *c) {
+    std::vector<TileChoice> ch(kMaxW32 + 1);
+    for (int W = 1; W <= kMaxW32; ++W) {
+        const size_t n = class_members(c, W).size();
+        int P = 1;
+        if (W == 1) P = n > 128 ? 4 : (n > 64 ? 2 : 1);
+        if (W == 2) P = n > 64 ? 2 : 1;
+        ch[W].P = P;
+        ch[W].lds = image_bytes(c, W, P) <= 64 * 1024;
+    }
+    return ch;
+}
+
+// Lay out tiles (64*P patterns of one word count each), upload the tables and
+// build the match-mask images on the device.
+void build_tiles(oasm_ctx *c, const std::vector<TileChoice> &choice) {
+    hipStream_t st = c->st;
+    const uint32_t n = c->npat;
+    std::vector<TileDesc> tiles;
+    std::vector<uint32_t> tile_wp, slot_pat, pat_tile(n), pat_slot(n);
+    uint64_t img_words = 0;
+    c->classes.clear();
+    for (int W = 1; W <= kMaxW32; ++W) {
+        const std::vector<uint32_t> ids = class_members(c, W);
+        if (ids.empty()) continue;
+        const int P = choice[W].P;
+        ClassInfo ci;
+        ci.W = W;
+        ci.P = P;
+        ci.tile_first = (uint32_t)tiles.size();
+        ci.lds = choice[W].lds && image_bytes(c, W, P) <= c->max_lds;
+        ci.waves = 4;
+        const uint32_t per = 64u * P;
+        for (size_t t0 = 0; t0 < ids.size(); t0 += per) {
+            TileDesc td;
+            td.peq_off = (uint32_t)img_words;
+            td.slot_off = (uint32_t)slot_pat.size();
+            td.n_active = (uint32_t)std::min<size_t>(per, ids.size() - t0);
+            td.pad = 0;
+            for (uint32_t s = 0; s < td.n_active; ++s) {
+                const uint32_t pid = ids[t0 + s];
+                slot_pat.push_back(pid);
+                pat_tile[pid] = (uint32_t)tiles.size();
+                pat_slot[pid] = s;
+            }
+            tiles.push_back(td);
+            tile_wp.push_back((uint32_t)W | ((uint32_t)P << 8));
+            img_words += image_bytes(c, W, P) / 4;
+        }
+        ci.ntiles = (uint32_t)tiles.size() - ci.tile_first;
+        c->classes.push_back(ci);
+    }
+    c->ntiles = (uint32_t)tiles.size();
+    auto upload = [&](DevBuf &d, const void *src, size_t bytes) {
+        d.ensure(std::max<size_t>(bytes, 16), st);
+        if (bytes) ck(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st), "dictionary upload");
+    };
+    upload(c->d_patbytes, c->h_patbytes.data(), c->h_patbytes.size());
+    upload(c->d_pats, c->h_pd.data(), c->h_pd.size() * sizeof(PatDesc));
+    upload(c->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc));
+    upload(c->d_tile_wp, tile_wp.data(), tile_wp.size() * 4);
+    upload(c->d_slot_pat, slot_pat.data(), slot_pat.size() * 4);
+    upload(c->d_pat_tile, pat_tile.data(), pat_tile.size() * 4);
+    upload(c->d_pat_slot, pat_slot.data(), pat_slot.size() * 4);
+    upload(c->d_class, c->class_of, 256);
+    c->d_peq.ensure(std::max<uint64_t>(img_words * 4, 16), st);
+    c->d_rpeq.ensure(std::max<uint64_t>(c->rpeq_words * 8, 16), st);
+    ck(launch_fill_u32(c->d_peq.as<uint32_t>(), 0, img_words, st), "fill peq");
+    ck(launch_peq_build(c->d_patbytes.as<uint8_t>(), c->d_pats.as<PatDesc>(), n, c->d_pat_tile.as<uint32_t>(),
+                        c->d_pat_slot.as<uint32_t>(), c->d_tiles.as<TileDesc>(), c->d_tile_wp.as<uint32_t>(),
+                        c->d_class.as<uint8_t>(), c->nclass, c->d_peq.as<uint32_t>(), c->d_rpeq.as<uint64_t>(), st),
+       "peq build");
+    wait_stream(c, "tile build sync");
+}
+
+// Device time of one scan launch of class `ci` over `nchunks` chunks of a
+// synthetic stream (min of three launches).
+double time_class(oasm_ctx *c, const ClassInfo &ci, const ChunkDesc *d_chunks, uint32_t nchunks) {
+    hipStream_t st = c->st;
+    const uint64_t nitems = (uint64_t)nchunks * ci.ntiles;
+    const uint32_t cap = 64;
+    c->item_rec.ensure(nitems * cap * 4, st);
+    c->item_cnt.ensure(nitems * 4, st);
+    c->ctl.ensure(64, st);
+    ScanArgs a;
+    a.chunks = d_chunks;
+    a.nchunks = nchunks;
+    a.tiles = c->d_tiles.as<TileDesc>();
+    a.tile_first = ci.tile_first;
+    a.ntiles = ci.ntiles;
+    a.peq_img = c->d_peq.as<uint32_t>();
+    a.slot_pat = c->d_slot_pat.as<uint32_t>();
+    a.pats = c->d_pats.as<PatDesc>();
+    a.nclass = c->nclass;
+    a.item_rec = c->item_rec.as<uint32_t>();
+    a.item_cnt = c->item_cnt.as<uint32_t>();
+    a.item_base = 0;
+    a.cap = cap;
+    a.max_cnt = c->ctl.as<uint32_t>();
+    double best = 1e30;
+    for (int r = 0; r < 3; ++r) {
+        ck(hipEventRecord(c->ev0, st), "event");
+        ck(launch_scan(ci.W, ci.P, a, ci.waves, ci.lds, st), "tune scan");
+        ck(hipEventRecord(c->ev1, st), "event");
+        wait_stream(c, "tune sync");
+        float ms = 0;
+        ck(hipEventElapsedTime(&ms, c->ev0, c->ev1), "event time");
+        best = std::min(best, (double)ms);
+    }
+    return best;
+}
+
+// Process-wide memory of tuning results, keyed by the class's shape.
+std::mutex g_tune_mu;
+std::map<std::tuple<uint32_t, int, size_t, int>, TileChoice> g_tune_cache;
+
+// Measure every (patterns per lane, LDS or not) variant of every word-count
+// class on a synthetic stream of uniformly drawn symbol classes, and keep
+// the fastest per class.
+void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
+    hipStream_t st = c->st;
+    const uint32_t chunk = 4096, nchunks = 2048;  // 8 MiB of text, 2048 work items per tile
+    const size_t nbytes = (size_t)chunk * nchunks;
+    std::vector<uint8_t> text(nbytes + kPad);
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    for (auto &b : text) {  // splitmix64 draws of symbol classes
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        b = (uint8_t)((z ^ (z >> 31)) % c->nclass);
+    }
+    DevBuf d_text, d_chunks;
+    d_text.ensure(text.size(), st);
+    ck(hipMemcpyAsync(d_text.p, text.data(), text.size(), hipMemcpyHostToDevice, st), "tune text");
+    std::vector<ChunkDesc> ch(nchunks);
+    for (uint32_t j = 0; j < nchunks; ++j) {
+        const uint64_t e0 = (uint64_t)j * chunk;
+        uint64_t s0 = e0 >= c->lookback ? e0 - c->lookback : 0;
+        s0 &= ~uint64_t(3);
+        ch[j] = ChunkDesc{d_text.as<uint8_t>() + s0, e0, (uint32_t)(e0 + chunk - s0), (uint32_t)(e0 - s0), 0, 0};
+    }
+    d_chunks.ensure(ch.size() * sizeof(ChunkDesc), st);
+    ck(hipMemcpyAsync(d_chunks.p, ch.data(), ch.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st), "tune chunks");
+    for (int W = 1; W <= kMaxW32; ++W) {
+        const size_t nW = class_members(c, W).size();
+        if (nW == 0) continue;
+        const auto key = std::make_tuple(c->nclass, W, nW, (int)c->max_lds);
+        {
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                choice[W] = it->second;
+                continue;
+            }
+        }
+        std::vector<TileChoice> cands;
+        for (int P : {1, 2, 4}) {
+            if (!scan_variant_exists(W, P) || (P > 1 && nW <= (size_t)64 * (P / 2))) continue;
+            cands.push_back(TileChoice{P, false});
+            if (image_bytes(c, W, P) <= c->max_lds) cands.push_back(TileChoice{P, true});
+        }
+        double best = 1e30;
+        TileChoice pick = choice[W];
+        char line[160];
+        for (const TileChoice &cd : cands) {
+            std::vector<TileChoice> trial = choice;
+            trial[W] = cd;
+            build_tiles(c, trial);
+            const ClassInfo *ci = nullptr;
+            for (const ClassInfo &k : c->classes)
+                if (k.W == W) ci = &k;
+            const double ms = time_class(c, *ci, d_chunks.as<ChunkDesc>(), nchunks);
+            // time per pattern word per symbol: classes differ in tiles, not in work per tile
+            const double per = ms / ((double)nW * W);
+            std::snprintf(line, sizeof line, "W=%d P=%d lds=%d: %.3f ms\n", W, cd.P, (int)cd.lds, ms);
+            c->tune_log += line;
+            if (per < best) {
+                best = per;
+                pick = cd;
+            }
+        }
+        choice[W] = pick;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = pick;
+    }
+    d_text.release();
+    d_chunks.release();
+}
+
 }  // namespace
 
 // ====================================================================== ABI
@@ -762,68 +981,16 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         c->hks = 2 * c->kmax + 1;
         c->lookback = c->mmax + c->kmax - 1;
 
-        // tiles: group patterns by 32-bit word count, choose patterns per lane
-        std::vector<std::vector<uint32_t>> byw(kMaxW32 + 1);
-        for (uint32_t i = 0; i < n; ++i) byw[(c->m[i] + 31) / 32].push_back(i);
-        std::vector<TileDesc> tiles;
-        std::vector<uint32_t> tile_wp, slot_pat, pat_tile(n), pat_slot(n);
-        uint64_t img_words = 0;
-        for (int W = 1; W <= kMaxW32; ++W) {
-            const auto &ids = byw[W];
-            if (ids.empty()) continue;
-            int P = 1;
-            if (W == 1) P = ids.size() > 128 ? 4 : (ids.size() > 64 ? 2 : 1);
-            if (W == 2) P = ids.size() > 64 ? 2 : 1;
-            ClassInfo ci;
-            ci.W = W;
-            ci.P = P;
-            ci.tile_first = (uint32_t)tiles.size();
-            const uint32_t per = 64u * P;
-            const uint32_t pws = (uint32_t)(P * W <= 1 ? 1 : P * W <= 2 ? 2 : P * W <= 4 ? 4 : 8);
-            const uint64_t img_bytes = (uint64_t)c->nclass * 64 * pws * 4;
-            ci.lds = img_bytes <= 64 * 1024;
-            ci.waves = 4;
-            for (size_t t0 = 0; t0 < ids.size(); t0 += per) {
-                TileDesc td;
-                td.peq_off = (uint32_t)img_words;
-                td.slot_off = (uint32_t)slot_pat.size();
-                td.n_active = (uint32_t)std::min<size_t>(per, ids.size() - t0);
-                td.pad = 0;
-                for (uint32_t s = 0; s < td.n_active; ++s) {
-                    const uint32_t pid = ids[t0 + s];
-                    slot_pat.push_back(pid);
-                    pat_tile[pid] = (uint32_t)tiles.size();
-                    pat_slot[pid] = s;
-                }
-                tiles.push_back(td);
-                tile_wp.push_back((uint32_t)W | ((uint32_t)P << 8));
-                img_words += (uint64_t)c->nclass * 64 * pws;
-            }
-            ci.ntiles = (uint32_t)tiles.size() - ci.tile_first;
-            c->classes.push_back(ci);
-        }
-        c->ntiles = (uint32_t)tiles.size();
-
-        auto upload = [&](DevBuf &d, const void *src, size_t bytes) {
-            d.ensure(std::max<size_t>(bytes, 16), st);
-            if (bytes) ck(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st), "dictionary upload");
-        };
-        upload(c->d_patbytes, bytes.data(), bytes.size());
-        upload(c->d_pats, pd.data(), pd.size() * sizeof(PatDesc));
-        upload(c->d_tiles, tiles.data(), tiles.size() * sizeof(TileDesc));
-        upload(c->d_tile_wp, tile_wp.data(), tile_wp.size() * 4);
-        upload(c->d_slot_pat, slot_pat.data(), slot_pat.size() * 4);
-        upload(c->d_pat_tile, pat_tile.data(), pat_tile.size() * 4);
-        upload(c->d_pat_slot, pat_slot.data(), pat_slot.size() * 4);
-        upload(c->d_class, c->class_of, 256);
-        c->d_peq.ensure(std::max<uint64_t>(img_words * 4, 16), st);
-        c->d_rpeq.ensure(std::max<uint64_t>(rpeq_words * 8, 16), st);
-        ck(launch_fill_u32(c->d_peq.as<uint32_t>(), 0, img_words, st), "fill peq");
-        ck(launch_peq_build(c->d_patbytes.as<uint8_t>(), c->d_pats.as<PatDesc>(), n, c->d_pat_tile.as<uint32_t>(),
-                            c->d_pat_slot.as<uint32_t>(), c->d_tiles.as<TileDesc>(), c->d_tile_wp.as<uint32_t>(),
-                            c->d_class.as<uint8_t>(), c->nclass, c->d_peq.as<uint32_t>(), c->d_rpeq.as<uint64_t>(),
-                            st),
-           "peq build");
+        c->h_patbytes = bytes;
+        c->h_pd = pd;
+        c->rpeq_words = rpeq_words;
+        int lds_max = 0;
+        if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) == hipSuccess &&
+            lds_max > 0)
+            c->max_lds = (size_t)lds_max;
+        std::vector<TileChoice> choice = default_choices(c);
+        if (c->cfg.flags & OASM_CFG_AUTOTUNE) autotune(c, choice);
+        build_tiles(c, choice);
         ck(hipStreamSynchronize(st), "create sync");
     } catch (const HipFail &f) {
         g_create_error = std::string(f.what) + ": " + hipGetErrorString(f.e);
@@ -1109,6 +1276,8 @@ void oasm_destroy(oasm_ctx *c) {
     if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
     delete c;
 }
+
+const char *oasm_tune_report(const oasm_ctx *c) { return c ? c->tune_log.c_str() : ""; }
 
 const char *oasm_last_error(const oasm_ctx *c) {
     if (!c) return g_create_error.c_str();

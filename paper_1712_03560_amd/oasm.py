@@ -33,6 +33,7 @@ OASM_FEED_LAST = 1
 OASM_CFG_PLAIN = 1
 OASM_CFG_KEEP_H = 2
 OASM_CFG_NO_RAW = 4
+OASM_CFG_AUTOTUNE = 8
 OASM_RAW = 0
 OASM_FILTERED = 1
 OASM_H = 2
@@ -53,6 +54,7 @@ EXPORTED = [
     "oasm_destroy",
     "oasm_last_error",
     "oasm_status_str",
+    "oasm_tune_report",
 ]
 
 
@@ -128,6 +130,8 @@ def _load():
     lib.oasm_destroy.restype = None
     lib.oasm_last_error.argtypes = [P]
     lib.oasm_last_error.restype = ctypes.c_char_p
+    lib.oasm_tune_report.argtypes = [P]
+    lib.oasm_tune_report.restype = ctypes.c_char_p
     lib.oasm_status_str.argtypes = [i32]
     lib.oasm_status_str.restype = ctypes.c_char_p
     return lib
@@ -237,6 +241,10 @@ def oasm_destroy(ctx):
         lib.oasm_destroy(ctx)
 
 
+def oasm_tune_report(ctx) -> str:
+    return lib.oasm_tune_report(ctx).decode()
+
+
 def oasm_last_error(ctx) -> str:
     return lib.oasm_last_error(ctx).decode()
 
@@ -254,12 +262,12 @@ class Matcher:
 
     def __init__(self, patterns, k, rules: int = OASM_RULES_PAPER, *, plain: bool = False, keep_h: bool = False,
                  no_raw: bool = False, chunk_bytes: int = 0, hip_stream: int | None = None, device: int = -1,
-                 mem_budget: int = 0):
+                 mem_budget: int = 0, autotune: bool = False):
         cfg = oasm_config_init()
         cfg.device = device
         cfg.chunk_bytes = chunk_bytes
         cfg.flags = (OASM_CFG_PLAIN if plain else 0) | (OASM_CFG_KEEP_H if keep_h else 0) | (
-            OASM_CFG_NO_RAW if no_raw else 0)
+            OASM_CFG_NO_RAW if no_raw else 0) | (OASM_CFG_AUTOTUNE if autotune else 0)
         cfg.device_mem_budget = mem_budget
         cfg.hip_stream = hip_stream
         self.keep_h = keep_h
@@ -308,6 +316,9 @@ class Matcher:
 
     def stats(self) -> dict:
         return oasm_get_stats(self.ctx)
+
+    def tune_report(self) -> str:
+        return oasm_tune_report(self.ctx)
 
     def destroy(self):
         if self.ctx:

@@ -25,9 +25,10 @@ def say(msg):
 
 
 def run(patterns, ks, streams: dict, *, keep_h=True, plain=False, chunk_bytes=0, pieces=None, device=False,
-        rules=oasm.OASM_RULES_PAPER):
+        rules=oasm.OASM_RULES_PAPER, autotune=False):
     """Feed every stream (optionally in pieces with syncs between), close, sync, drain."""
-    with oasm.Matcher(patterns, ks, rules, keep_h=keep_h, plain=plain, chunk_bytes=chunk_bytes) as mt:
+    with oasm.Matcher(patterns, ks, rules, keep_h=keep_h, plain=plain, chunk_bytes=chunk_bytes,
+                      autotune=autotune) as mt:
         if pieces is None:
             for sid, t in streams.items():
                 mt.feed(sid, torch.from_numpy(t).cuda() if device and t.size else t)
@@ -137,6 +138,15 @@ def test_plain_equals_batched_and_device_feed():
     for x, y in ((a.raw, b.raw), (a.occ, b.occ), (a.h, b.h)):
         assert np.array_equal(np.sort(x, order=list(x.dtype.names)), np.sort(y, order=list(y.dtype.names)))
     compare(b, streams, w.patterns, w.ks, label="device-feed")
+
+
+def test_autotuned_variants_match_oracle():
+    """With the autotuner on, every pattern class runs the variant it measured
+    fastest (patterns per lane, masks in LDS or L1/L2); results are unchanged."""
+    w = W.small_random(50, 6000, 300, 8, 200, bytes(range(256)), kmax=20, n_plants=60, n_streams=2)
+    streams = {i: s for i, s in enumerate(w.streams)}
+    res = run(w.patterns, w.ks, streams, autotune=True)
+    compare(res, streams, w.patterns, w.ks, check_h=True, label="autotuned")
 
 
 def test_rules_none_reports_hits_only():
