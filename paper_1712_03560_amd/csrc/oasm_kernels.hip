@@ -256,7 +256,7 @@ constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
 // start state with an exact test per symbol, and the hits are compacted with
 // a ballot and an mbcnt prefix into the item's own record buffer.
 template <int W, int P, bool LDSPEQ>
-__global__ void __launch_bounds__(256) k_scan(ScanArgs a) {
+__global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) {
     extern __shared__ uint32_t lds_img[];
     constexpr int PW = P * W;
     constexpr int PWS = pad_pow2(PW);

@@ -842,11 +842,15 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
                 continue;
             }
         }
-        std::vector<TileChoice> cands;
+        // the heuristic default first: another variant must beat it by 3 %
+        std::vector<TileChoice> cands{choice[W]};
         for (int P : {1, 2, 4}) {
             if (!scan_variant_exists(W, P) || (P > 1 && nW <= (size_t)64 * (P / 2))) continue;
-            cands.push_back(TileChoice{P, false});
-            if (image_bytes(c, W, P) <= c->max_lds) cands.push_back(TileChoice{P, true});
+            for (bool lds : {false, true}) {
+                if (lds && image_bytes(c, W, P) > c->max_lds) continue;
+                if (P == choice[W].P && lds == choice[W].lds) continue;
+                cands.push_back(TileChoice{P, lds});
+            }
         }
         double best = 1e30;
         TileChoice pick = choice[W];
@@ -863,7 +867,7 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
             const double per = ms / ((double)nW * W);
             std::snprintf(line, sizeof line, "W=%d P=%d lds=%d: %.3f ms\n", W, cd.P, (int)cd.lds, ms);
             c->tune_log += line;
-            if (per < best) {
+            if (per < (&cd == &cands[0] ? 1e30 : best * 0.97)) {
                 best = per;
                 pick = cd;
             }
