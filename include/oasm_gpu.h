@@ -162,6 +162,8 @@ typedef struct oasm_stats {
     uint64_t scan_launches;     /* scan kernel launches */
     double sync_wall_ms;        /* host wall time spent inside oasm_sync */
     double wait_ms;             /* part of it spent waiting for the device */
+    double host_ms[4];          /* host time per step phase: plan and upload, launches,
+                                   result conversion, stream bookkeeping */
 } oasm_stats;
 
 /* Fill `cfg` with defaults (device -1, library stream, autotuned chunks). */

@@ -296,6 +296,14 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which_in, StepPlan &pl
 // ------------------------------------------------------------------ step
 void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     hipStream_t st = c->st;
+    double tmark = now_ms(), twait0 = c->stats.wait_ms;
+    // host time since the last mark, excluding device waits, into phase ph
+    auto phase = [&](int ph) {
+        const double t = now_ms();
+        c->stats.host_ms[ph] += (t - tmark) - (c->stats.wait_ms - twait0);
+        tmark = t;
+        twait0 = c->stats.wait_ms;
+    };
     StepPlan pl;
     build_plan(c, which, pl);
     if ((uint64_t)pl.locals.size() * c->npat >= (1ull << 32))
@@ -312,6 +320,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     std::memcpy(c->pin_plan.p, blob.data(), blob.size());
     c->plan.ensure(blob.size(), st);
     ck(hipMemcpyAsync(c->plan.p, c->pin_plan.p, blob.size(), hipMemcpyHostToDevice, st), "plan upload");
+    phase(0);
     uint8_t *pb = c->plan.as<uint8_t>();
     const ChunkDesc *d_chunks = reinterpret_cast<const ChunkDesc *>(pb + o_chunks);
     const StreamDesc *d_sdesc = reinterpret_cast<const StreamDesc *>(pb + o_sdesc);
@@ -489,6 +498,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += ms;
 
+    phase(1);
     // host bookkeeping: queue results
     const uint32_t *hpat = reinterpret_cast<const uint32_t *>(hp + o_pat);
     const uint32_t *hsl = reinterpret_cast<const uint32_t *>(hp + o_sl);
@@ -526,6 +536,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         const uint64_t sid = c->streams[pl.locals[ho[i].stream_local]].id;
         c->q_occ.push_back(oasm_occ{sid, ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
     }
+    phase(2);
     // the new carry stays on the device; the host keeps per-stream counts
     for (uint32_t si : pl.locals) c->streams[si].ncarry = 0;
     const CarryRec *hc = reinterpret_cast<const CarryRec *>(hp + o_cr);
@@ -567,6 +578,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     c->stats.raw_hits += new_raw;
     c->stats.occurrences += nocc;
     c->stats.syncs++;
+    phase(3);
     c->pin_feed_used = 0;
 }
 

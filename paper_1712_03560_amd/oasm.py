@@ -82,7 +82,8 @@ class oasm_stats(ctypes.Structure):
     _fields_ = [("bytes_scanned", ctypes.c_uint64), ("word_steps", ctypes.c_uint64), ("cells", ctypes.c_uint64),
                 ("raw_hits", ctypes.c_uint64), ("h_records", ctypes.c_uint64), ("occurrences", ctypes.c_uint64),
                 ("syncs", ctypes.c_uint64), ("scan_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
-                ("scan_launches", ctypes.c_uint64), ("sync_wall_ms", ctypes.c_double), ("wait_ms", ctypes.c_double)]
+                ("scan_launches", ctypes.c_uint64), ("sync_wall_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
+                ("host_ms", ctypes.c_double * 4)]
 
 
 class oasm_serve_report(ctypes.Structure):
@@ -233,7 +234,9 @@ def oasm_serve(ctx, segs: np.ndarray, pool_ptr: int, pool_bytes: int, want_laten
 def oasm_get_stats(ctx) -> dict:
     s = oasm_stats()
     _check(ctx, lib.oasm_get_stats(ctx, ctypes.byref(s)))
-    return {name: getattr(s, name) for name, _ in oasm_stats._fields_}
+    d = {name: getattr(s, name) for name, _ in oasm_stats._fields_}
+    d["host_ms"] = list(d["host_ms"])
+    return d
 
 
 def oasm_destroy(ctx):
