@@ -69,6 +69,17 @@ struct OccRec {
     uint32_t k;
 };
 
+// A record count that lives in device memory: min(add + *p, cap) (p may be
+// null).  Kernels after the scan read their sizes this way, so a whole step
+// is queued without the host waiting for intermediate counts; `cap` is the
+// capacity the buffers were sized for (a count above it is detected at the
+// end of the step, which is then run again with larger buffers).
+struct DevN {
+    const uint32_t *p;
+    uint32_t add;
+    uint32_t cap;
+};
+
 // ------------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error.  All run on `st`.
 
@@ -122,42 +133,42 @@ hipError_t launch_place_carry(const CarryRec *carry, uint32_t ncarry, const uint
 hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
                               uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
                               const uint32_t *item_cnt, const uint32_t *item_off, uint32_t item_base, uint32_t cap,
-                              uint32_t base, uint32_t npat, uint32_t *key, uint32_t *val, uint64_t *end,
-                              hipStream_t st);
-size_t sort_tmp_words(uint32_t n);
-hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, uint32_t n,
+                              uint32_t base, uint32_t cap_n, uint32_t npat, uint32_t *key, uint32_t *val,
+                              uint64_t *end, hipStream_t st);
+size_t sort_tmp_words(uint32_t cap);
+hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, DevN n,
                              uint32_t key_bits, uint32_t *tmp, hipStream_t st, bool &result_in_second);
-hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, uint32_t n, uint32_t npat, uint32_t ncarry,
+hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, DevN n, uint32_t npat, uint32_t ncarry,
                              const uint64_t *end_in, const CarryRec *carry, const uint8_t *carry_hk, uint32_t hks,
                              uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist,
                              uint8_t *r_hk, hipStream_t st);
 
 // K2: hit-set recovery at every new hit end (reverse anchored DP).
 hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_flag,
-                          uint32_t n, const PatDesc *pats, const uint64_t *rpeq, const StreamDesc *streams,
+                          DevN n, const PatDesc *pats, const uint64_t *rpeq, const StreamDesc *streams,
                           uint32_t nclass, uint32_t hks, uint8_t *r_hk, uint8_t *r_dist, uint32_t *err,
                           hipStream_t st);
 
 // K3: the filter, one thread per segment of a (stream, pattern) run.
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
-                         uint32_t n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams,
+                         DevN n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams,
                          uint32_t do_filter, uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt,
                          uint32_t *carry_flag, hipStream_t st);
 
 // Gather the filter output into a dense array.
-hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, uint32_t n,
-                              uint32_t out_stride, OccRec *out, hipStream_t st);
+hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, DevN n,
+                              uint32_t out_stride, OccRec *out, uint32_t out_cap, hipStream_t st);
 
 // Gather carried records for the next step.
 hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end,
                                 const uint8_t *r_dist, const uint8_t *r_hk, uint32_t hks, const uint32_t *carry_flag,
-                                const uint32_t *carry_off, const StreamDesc *streams, uint32_t n, CarryRec *out,
-                                uint8_t *out_hk, hipStream_t st);
+                                const uint32_t *carry_off, const StreamDesc *streams, DevN n, CarryRec *out,
+                                uint8_t *out_hk, uint32_t out_cap, hipStream_t st);
 
 // Exclusive prefix sum of n uint32 values; writes the total to *total.
 // `tmp` must hold scan_tmp_words(n) uint32.
-size_t scan_tmp_words(size_t n);
-hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *total, uint32_t *tmp,
+size_t scan_tmp_words(size_t cap);
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, DevN n, uint32_t *total, uint32_t *tmp,
                                  hipStream_t st);
 
 // Fill n uint32 with a value (graph-safe replacement for a memset).

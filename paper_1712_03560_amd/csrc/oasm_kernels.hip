@@ -27,6 +27,11 @@ __device__ __forceinline__ uint32_t lane_id() {
     return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
 }
 
+__device__ __forceinline__ uint32_t dev_n(const DevN &d) {
+    const uint32_t v = d.add + (d.p ? *d.p : 0u);
+    return v < d.cap ? v : d.cap;
+}
+
 // number of set bits of `mask` below this lane
 __device__ __forceinline__ uint32_t mbcnt64(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -439,7 +444,7 @@ __global__ void __launch_bounds__(256) k_compact_raw(const ChunkDesc *__restrict
                                                      const uint32_t *__restrict__ item_rec,
                                                      const uint32_t *__restrict__ item_cnt,
                                                      const uint32_t *__restrict__ item_off, uint32_t item_base,
-                                                     uint32_t cap, uint32_t base, uint32_t npat,
+                                                     uint32_t cap, uint32_t base, uint32_t cap_n, uint32_t npat,
                                                      uint32_t *__restrict__ key, uint32_t *__restrict__ val,
                                                      uint64_t *__restrict__ end) {
     const uint32_t lane = lane_id();
@@ -459,6 +464,7 @@ __global__ void __launch_bounds__(256) k_compact_raw(const ChunkDesc *__restrict
     for (uint32_t i = lane; i < n; i += kWave) {
         const uint32_t r = rec[i];
         const uint32_t d = dst0 + i;
+        if (d >= cap_n) break;  // over capacity: the step is run again with larger buffers
         key[d] = kbase + slot_pat[td.slot_off + (r >> 24)];
         val[d] = d;
         end[d] = cd.abs_first + (r & 0xFFFFFFu);
@@ -476,13 +482,13 @@ hipError_t launch_place_carry(const CarryRec *carry, uint32_t ncarry, const uint
 hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
                               uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
                               const uint32_t *item_cnt, const uint32_t *item_off, uint32_t item_base, uint32_t cap,
-                              uint32_t base, uint32_t npat, uint32_t *key, uint32_t *val, uint64_t *end,
-                              hipStream_t st) {
+                              uint32_t base, uint32_t cap_n, uint32_t npat, uint32_t *key, uint32_t *val,
+                              uint64_t *end, hipStream_t st) {
     const uint64_t items = (uint64_t)nchunks * ntiles;
     if (items == 0) return hipSuccess;
     hipLaunchKernelGGL(k_compact_raw, dim3((uint32_t)((items + 3) / 4)), dim3(256), 0, st, chunks, nchunks, tiles,
-                       tile_first, ntiles, slot_pat, item_rec, item_cnt, item_off, item_base, cap, base, npat, key,
-                       val, end);
+                       tile_first, ntiles, slot_pat, item_rec, item_cnt, item_off, item_base, cap, base, cap_n, npat,
+                       key, val, end);
     return hipGetLastError();
 }
 
@@ -496,10 +502,11 @@ constexpr uint32_t kSortThreads = 256;
 constexpr uint32_t kSortRounds = 8;
 constexpr uint32_t kSortTile = kSortThreads * kSortRounds;
 
-__global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t *__restrict__ key, uint32_t n,
+__global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t *__restrict__ key, DevN dn,
                                                             uint32_t shift, uint32_t nblocks,
                                                             uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[256];
+    const uint32_t n = dev_n(dn);
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t b0 = blockIdx.x * kSortTile;
@@ -512,12 +519,13 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t *__re
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t *__restrict__ kin,
-                                                               const uint32_t *__restrict__ vin, uint32_t n,
+                                                               const uint32_t *__restrict__ vin, DevN dn,
                                                                uint32_t shift, uint32_t nblocks,
                                                                const uint32_t *__restrict__ offs,
                                                                uint32_t *__restrict__ kout,
                                                                uint32_t *__restrict__ vout) {
     __shared__ uint32_t base[256];
+    const uint32_t n = dev_n(dn);
     __shared__ uint32_t wc[4][256];
     const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
     base[t] = offs[t * nblocks + blockIdx.x];
@@ -554,24 +562,27 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t *_
     }
 }
 
-size_t sort_tmp_words(uint32_t n) {
-    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+size_t sort_tmp_words(uint32_t cap) {
+    const uint32_t nb = (cap + kSortTile - 1) / kSortTile;
     return (size_t)256 * nb * 2 + scan_tmp_words((size_t)256 * nb) + 16;
 }
 
-hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, uint32_t n,
+// Sort the first dev_n(n) pairs; blocks are sized for n.cap (blocks past the
+// count see empty tiles).  Each pass ping-pongs between the two arrays.
+hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, DevN n,
                              uint32_t key_bits, uint32_t *tmp, hipStream_t st, bool &result_in_second) {
     result_in_second = false;
-    if (n <= 1 || key_bits == 0) return hipSuccess;
-    const uint32_t nb = (n + kSortTile - 1) / kSortTile;
+    if (n.cap <= 1 || key_bits == 0) return hipSuccess;
+    const uint32_t nb = (n.cap + kSortTile - 1) / kSortTile;
     uint32_t *hist = tmp;
     uint32_t *offs = tmp + (size_t)256 * nb;
     uint32_t *stmp = offs + (size_t)256 * nb;
     uint32_t *total = stmp + scan_tmp_words((size_t)256 * nb);
     uint32_t *ki = key, *vi = val, *ko = key2, *vo = val2;
+    const DevN hn{nullptr, 256u * nb, 256u * nb};
     for (uint32_t shift = 0; shift < key_bits; shift += 8) {
         hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, st, ki, n, shift, nb, hist);
-        hipError_t e = launch_exclusive_scan(hist, offs, (size_t)256 * nb, total, stmp, st);
+        hipError_t e = launch_exclusive_scan(hist, offs, hn, total, stmp, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_sort_scatter, dim3(nb), dim3(kSortThreads), 0, st, ki, vi, n, shift, nb, offs, ko, vo);
         std::swap(ki, ko);
@@ -582,13 +593,13 @@ hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint3
 }
 
 // Sorted (key, source index) -> the per-record arrays of the step.
-__global__ void k_gather_raw(const uint32_t *__restrict__ skey, const uint32_t *__restrict__ sval, uint32_t n,
+__global__ void k_gather_raw(const uint32_t *__restrict__ skey, const uint32_t *__restrict__ sval, DevN dn,
                              uint32_t npat, uint32_t ncarry, const uint64_t *__restrict__ end_in,
                              const CarryRec *__restrict__ carry, const uint8_t *__restrict__ carry_hk, uint32_t hks,
                              uint32_t *__restrict__ r_pat, uint32_t *__restrict__ r_sl, uint64_t *__restrict__ r_end,
                              uint8_t *__restrict__ r_flag, uint8_t *__restrict__ r_dist, uint8_t *__restrict__ r_hk) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= dev_n(dn)) return;
     const uint32_t k = skey[i], src = sval[i];
     r_pat[i] = k % npat;
     r_sl[i] = k / npat;
@@ -601,12 +612,12 @@ __global__ void k_gather_raw(const uint32_t *__restrict__ skey, const uint32_t *
     }
 }
 
-hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, uint32_t n, uint32_t npat, uint32_t ncarry,
+hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, DevN n, uint32_t npat, uint32_t ncarry,
                              const uint64_t *end_in, const CarryRec *carry, const uint8_t *carry_hk, uint32_t hks,
                              uint32_t *r_pat, uint32_t *r_sl, uint64_t *r_end, uint8_t *r_flag, uint8_t *r_dist,
                              uint8_t *r_hk, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_raw, dim3((n + 255) / 256), dim3(256), 0, st, skey, sval, n, npat, ncarry, end_in,
+    if (n.cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_raw, dim3((n.cap + 255) / 256), dim3(256), 0, st, skey, sval, n, npat, ncarry, end_in,
                        carry, carry_hk, hks, r_pat, r_sl, r_end, r_flag, r_dist, r_hk);
     return hipGetLastError();
 }
@@ -620,13 +631,13 @@ hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, uint32_
 // same per-start distances the paper's LEV CALC unit produces.
 __global__ void __launch_bounds__(256) k_recover(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
                                                  const uint64_t *__restrict__ r_end,
-                                                 const uint8_t *__restrict__ r_flag, uint32_t n,
+                                                 const uint8_t *__restrict__ r_flag, DevN dn,
                                                  const PatDesc *__restrict__ pats, const uint64_t *__restrict__ rpeq,
                                                  const StreamDesc *__restrict__ streams, uint32_t nclass, uint32_t hks,
                                                  uint8_t *__restrict__ r_hk, uint8_t *__restrict__ r_dist,
                                                  uint32_t *__restrict__ err) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || r_flag[i]) return;
+    if (i >= dev_n(dn) || r_flag[i]) return;
     const PatDesc d = pats[r_pat[i]];
     const StreamDesc sd = streams[r_sl[i]];
     const uint64_t e = r_end[i];
@@ -690,11 +701,11 @@ __global__ void __launch_bounds__(256) k_recover(const uint32_t *__restrict__ r_
 }
 
 hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_flag,
-                          uint32_t n, const PatDesc *pats, const uint64_t *rpeq, const StreamDesc *streams,
+                          DevN n, const PatDesc *pats, const uint64_t *rpeq, const StreamDesc *streams,
                           uint32_t nclass, uint32_t hks, uint8_t *r_hk, uint8_t *r_dist, uint32_t *err,
                           hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_recover, dim3((n + 255) / 256), dim3(256), 0, st, r_pat, r_sl, r_end, r_flag, n, pats, rpeq,
+    if (n.cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_recover, dim3((n.cap + 255) / 256), dim3(256), 0, st, r_pat, r_sl, r_end, r_flag, n, pats, rpeq,
                        streams, nclass, hks, r_hk, r_dist, err);
     return hipGetLastError();
 }
@@ -722,11 +733,12 @@ constexpr int kMaxLevels = 64;  // K <= 63
 // may still grow: it is not filtered now but carried to the next step.
 __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
                                                const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
-                                               uint32_t n, uint32_t hks, const PatDesc *__restrict__ pats,
+                                               DevN dn, uint32_t hks, const PatDesc *__restrict__ pats,
                                                const StreamDesc *__restrict__ streams, uint32_t do_filter,
                                                uint32_t out_stride, OccRec *__restrict__ seg_out,
                                                uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t n = dev_n(dn);
     if (i >= n) return;
     const uint32_t p = r_pat[i], sl = r_sl[i];
     const uint64_t e0 = r_end[i];
@@ -815,29 +827,29 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
 }
 
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
-                         uint32_t n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams, uint32_t do_filter,
+                         DevN n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams, uint32_t do_filter,
                          uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt, uint32_t *carry_flag,
                          hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter, dim3((n + 63) / 64), dim3(64), 0, st, r_pat, r_sl, r_end, r_hk, n, hks, pats, streams,
+    if (n.cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_filter, dim3((n.cap + 63) / 64), dim3(64), 0, st, r_pat, r_sl, r_end, r_hk, n, hks, pats, streams,
                        do_filter, out_stride, seg_out, seg_cnt, carry_flag);
     return hipGetLastError();
 }
 
 __global__ void k_compact_occ(const OccRec *__restrict__ seg_out, const uint32_t *__restrict__ seg_cnt,
-                              const uint32_t *__restrict__ seg_off, uint32_t n, uint32_t stride,
-                              OccRec *__restrict__ out) {
+                              const uint32_t *__restrict__ seg_off, DevN dn, uint32_t stride,
+                              OccRec *__restrict__ out, uint32_t out_cap) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= dev_n(dn)) return;
     const uint32_t c = seg_cnt[i];
-    for (uint32_t q = 0; q < c; ++q) out[seg_off[i] + q] = seg_out[(size_t)i * stride + q];
+    for (uint32_t q = 0; q < c && seg_off[i] + q < out_cap; ++q) out[seg_off[i] + q] = seg_out[(size_t)i * stride + q];
 }
 
-hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, uint32_t n,
-                              uint32_t out_stride, OccRec *out, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact_occ, dim3((n + 255) / 256), dim3(256), 0, st, seg_out, seg_cnt, seg_off, n,
-                       out_stride, out);
+hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, DevN n,
+                              uint32_t out_stride, OccRec *out, uint32_t out_cap, hipStream_t st) {
+    if (n.cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_occ, dim3((n.cap + 255) / 256), dim3(256), 0, st, seg_out, seg_cnt, seg_off, n,
+                       out_stride, out, out_cap);
     return hipGetLastError();
 }
 
@@ -845,11 +857,12 @@ __global__ void k_compact_carry(const uint32_t *__restrict__ r_pat, const uint32
                                 const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_dist,
                                 const uint8_t *__restrict__ r_hk, uint32_t hks,
                                 const uint32_t *__restrict__ carry_flag, const uint32_t *__restrict__ carry_off,
-                                const StreamDesc *__restrict__ streams, uint32_t n, CarryRec *__restrict__ out,
-                                uint8_t *__restrict__ out_hk) {
+                                const StreamDesc *__restrict__ streams, DevN dn, CarryRec *__restrict__ out,
+                                uint8_t *__restrict__ out_hk, uint32_t out_cap) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || !carry_flag[i]) return;
+    if (i >= dev_n(dn) || !carry_flag[i]) return;
     const uint32_t o = carry_off[i];
+    if (o >= out_cap) return;
     CarryRec c;
     c.end_abs = r_end[i];
     c.pattern = r_pat[i];
@@ -862,11 +875,11 @@ __global__ void k_compact_carry(const uint32_t *__restrict__ r_pat, const uint32
 
 hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end,
                                 const uint8_t *r_dist, const uint8_t *r_hk, uint32_t hks, const uint32_t *carry_flag,
-                                const uint32_t *carry_off, const StreamDesc *streams, uint32_t n, CarryRec *out,
-                                uint8_t *out_hk, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact_carry, dim3((n + 255) / 256), dim3(256), 0, st, r_pat, r_sl, r_end, r_dist, r_hk,
-                       hks, carry_flag, carry_off, streams, n, out, out_hk);
+                                const uint32_t *carry_off, const StreamDesc *streams, DevN n, CarryRec *out,
+                                uint8_t *out_hk, uint32_t out_cap, hipStream_t st) {
+    if (n.cap == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact_carry, dim3((n.cap + 255) / 256), dim3(256), 0, st, r_pat, r_sl, r_end, r_dist,
+                       r_hk, hks, carry_flag, carry_off, streams, n, out, out_hk, out_cap);
     return hipGetLastError();
 }
 
@@ -905,8 +918,9 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t &excl) 
     return total;
 }
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__restrict__ in, size_t n,
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t *__restrict__ in, DevN dn,
                                                               uint32_t *__restrict__ sums) {
+    const size_t n = dev_n(dn);
     const size_t base = (size_t)blockIdx.x * kScanTile;
     uint32_t v = 0;
 #pragma unroll
@@ -934,7 +948,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_sums(uint32_t *__restrict
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__restrict__ in, uint32_t *__restrict__ out,
-                                                             size_t n, const uint32_t *__restrict__ sums) {
+                                                             DevN dn, const uint32_t *__restrict__ sums) {
+    const size_t n = dev_n(dn);
     const size_t base = (size_t)blockIdx.x * kScanTile + (size_t)threadIdx.x * kScanPer;
     uint32_t v[kScanPer];
     uint32_t s = 0;
@@ -953,11 +968,12 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__r
     }
 }
 
-size_t scan_tmp_words(size_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+size_t scan_tmp_words(size_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
 
-hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, size_t n, uint32_t *total, uint32_t *tmp,
+// Exclusive scan of the first dev_n(n) values (blocks sized for n.cap).
+hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, DevN n, uint32_t *total, uint32_t *tmp,
                                  hipStream_t st) {
-    const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
+    const uint32_t nb = (uint32_t)((n.cap + kScanTile - 1) / kScanTile);
     if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n, tmp);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, tmp, nb, total);
     if (nb > 0) hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kScanThreads), 0, st, in, out, n, tmp);

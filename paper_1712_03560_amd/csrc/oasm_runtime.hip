@@ -164,7 +164,10 @@ struct oasm_ctx {
     uint32_t ncarry = 0;
     PinBuf pin_plan, pin_ctl, pin_out, pin_feed;
     size_t pin_feed_used = 0;
-    uint32_t cap = 256;
+    uint32_t cap = 256;         // records per scan item
+    uint32_t cap_n = 1u << 16;  // hit ends per step (carried + new)
+    uint32_t cap_occ = 1u << 16;
+    uint32_t cap_carry = 1u << 12;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
 
     // results
@@ -339,13 +342,42 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     c->pin_ctl.ensure(64, st);
 
     const uint64_t nitems = (uint64_t)nchunks * c->ntiles;
+    const uint32_t hks = c->hks;
+    const uint32_t out_stride = c->kmax + 1;
+    const uint32_t do_filter = c->rules == OASM_RULES_PAPER ? 1u : 0u;
+    uint32_t key_bits = 0;
+    while (key_bits < 32 && ((uint64_t)1 << key_bits) < (uint64_t)pl.locals.size() * c->npat) ++key_bits;
     c->item_cnt.ensure(std::max<uint64_t>(1, nitems) * 4, st);
     c->offsets.ensure(std::max<uint64_t>(1, nitems) * 4, st);
-    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint64_t>(nitems, 1)) * 4, 1024), st);
 
-    uint32_t n_new = 0;
+    // The whole step is queued at once: every kernel after the scan reads its
+    // size from device memory and the buffers are sized by capacities that
+    // grow (and the step runs again) when a count exceeds them.
+    uint32_t n_new = 0, nocc = 0, ncarry_out = 0;
     for (int attempt = 0;; ++attempt) {
+        const uint32_t cap_n = c->cap_n, cap_occ = c->cap_occ, cap_carry = c->cap_carry;
+        const uint64_t n1 = cap_n;
         c->item_rec.ensure(std::max<uint64_t>(1, nitems) * c->cap * 4, st);
+        c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint64_t>({nitems, n1, 1})) * 4, 1024), st);
+        c->sort_key.ensure(n1 * 8, st);  // two halves: ping-pong
+        c->sort_val.ensure(n1 * 8, st);
+        c->sort_end.ensure(n1 * 8, st);
+        c->sort_tmp.ensure(sort_tmp_words((uint32_t)n1) * 4, st);
+        c->r_pat.ensure(n1 * 4, st);
+        c->r_sl.ensure(n1 * 4, st);
+        c->r_end.ensure(n1 * 8, st);
+        c->r_flag.ensure(n1, st);
+        c->r_dist.ensure(n1, st);
+        c->r_hk.ensure(n1 * hks, st);
+        c->seg_cnt.ensure(n1 * 4, st);
+        c->seg_off.ensure(n1 * 4, st);
+        c->carry_flag.ensure(n1 * 4, st);
+        c->carry_off.ensure(n1 * 4, st);
+        c->seg_out.ensure(n1 * out_stride * sizeof(OccRec), st);
+        c->occ_out.ensure((uint64_t)cap_occ * sizeof(OccRec), st);
+        c->carry_buf[cout].ensure((uint64_t)cap_carry * sizeof(CarryRec), st);
+        c->carry_hk_buf[cout].ensure((uint64_t)cap_carry * hks, st);
+
         ck(launch_fill_u32(ctl, 0, 16, st), "fill ctl");
         ck(hipEventRecord(c->ev0, st), "event");
         uint32_t item_base = 0;
@@ -370,98 +402,86 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             c->stats.scan_launches++;
         }
         ck(hipEventRecord(c->ev1, st), "event");
-        ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), nitems, ctl + 1,
+        const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems};
+        ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), items, ctl + 1,
                                  c->scan_tmp.as<uint32_t>(), st),
            "item count scan");
-        ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
-        wait_stream(c, "sync after scan");
-        const uint32_t *h = c->pin_ctl.as<uint32_t>();
-        if (h[0] > c->cap) {  // an item overflowed its record buffer: grow and rescan
-            c->cap = pow2_at_least(h[0]);
-            continue;
+        const DevN dn{ctl + 1, ncarry, cap_n};  // carried + new hit ends
+        uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
+        uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
+        ck(launch_place_carry(d_carry, std::min(ncarry, cap_n), d_s2l, c->npat, key0, val0,
+                              c->sort_end.as<uint64_t>(), st),
+           "place carry");
+        item_base = 0;
+        for (const ClassInfo &ci : c->classes) {
+            ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
+                                  c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(),
+                                  c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), item_base, c->cap, ncarry,
+                                  cap_n, c->npat, key0, val0, c->sort_end.as<uint64_t>(), st),
+               "compact hit ends");
+            item_base += nchunks * ci.ntiles;
         }
+        bool second = false;
+        ck(launch_radix_sort(key0, val0, key1, val1, dn, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
+           "radix sort");
+        ck(launch_gather_raw(second ? key1 : key0, second ? val1 : val0, dn, c->npat, ncarry,
+                             c->sort_end.as<uint64_t>(), d_carry, d_carry_hk, hks, c->r_pat.as<uint32_t>(),
+                             c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(),
+                             c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), st),
+           "gather hit ends");
+        ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                          c->r_flag.as<uint8_t>(), dn, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
+                          c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
+           "recover");
+        ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                         c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, do_filter, out_stride,
+                         c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
+           "filter");
+        ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
+                                 c->scan_tmp.as<uint32_t>(), st),
+           "occ scan");
+        ck(launch_exclusive_scan(c->carry_flag.as<uint32_t>(), c->carry_off.as<uint32_t>(), dn, ctl + 3,
+                                 c->scan_tmp.as<uint32_t>(), st),
+           "carry scan");
+        ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn,
+                              out_stride, c->occ_out.as<OccRec>(), cap_occ, st),
+           "compact occ");
+        ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                                c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
+                                c->carry_off.as<uint32_t>(), d_sdesc, dn, c->carry_buf[cout].as<CarryRec>(),
+                                c->carry_hk_buf[cout].as<uint8_t>(), cap_carry, st),
+           "compact carry");
+        ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
+        wait_stream(c, "step sync");
+        const uint32_t *h = c->pin_ctl.as<uint32_t>();
         n_new = h[1];
+        nocc = h[2];
+        ncarry_out = h[3];
+        const uint64_t n_all = (uint64_t)ncarry + n_new;
+        bool again = false;
+        if (h[0] > c->cap) {  // a scan item overflowed its record buffer
+            c->cap = pow2_at_least(h[0]);
+            again = true;
+        }
+        if (n_all > cap_n) {
+            c->cap_n = pow2_at_least(2 * n_all);
+            again = true;
+        }
+        if (!again && nocc > cap_occ) {
+            c->cap_occ = pow2_at_least(2ull * nocc);
+            again = true;
+        }
+        if (!again && ncarry_out > cap_carry) {
+            c->cap_carry = pow2_at_least(2ull * ncarry_out);
+            again = true;
+        }
+        if (again) continue;
+        if (h[4]) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
         float ms = 0;
         if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->stats.scan_ms += ms;
         break;
     }
-
     const uint32_t n = ncarry + n_new;
-    const uint32_t hks = c->hks;
-    const uint32_t out_stride = c->kmax + 1;
-    const uint64_t n1 = std::max<uint32_t>(n, 1);
-    c->sort_key.ensure(n1 * 8, st);  // two halves: ping-pong
-    c->sort_val.ensure(n1 * 8, st);
-    c->sort_end.ensure(n1 * 8, st);
-    c->sort_tmp.ensure(sort_tmp_words(n1) * 4, st);
-    c->r_pat.ensure(n1 * 4, st);
-    c->r_sl.ensure(n1 * 4, st);
-    c->r_end.ensure(n1 * 8, st);
-    c->r_flag.ensure(n1, st);
-    c->r_dist.ensure(n1, st);
-    c->r_hk.ensure(n1 * hks, st);
-    c->seg_cnt.ensure(n1 * 4, st);
-    c->seg_off.ensure(n1 * 4, st);
-    c->carry_flag.ensure(n1 * 4, st);
-    c->carry_off.ensure(n1 * 4, st);
-    c->seg_out.ensure(n1 * out_stride * sizeof(OccRec), st);
-    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(n1) * 4, 1024), st);
-
-    uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
-    uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
-    ck(launch_place_carry(d_carry, ncarry, d_s2l, c->npat, key0, val0, c->sort_end.as<uint64_t>(), st),
-       "place carry");
-    uint32_t item_base = 0;
-    for (const ClassInfo &ci : c->classes) {
-        ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
-                              c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(), c->item_cnt.as<uint32_t>(),
-                              c->offsets.as<uint32_t>(), item_base, c->cap, ncarry, c->npat, key0, val0,
-                              c->sort_end.as<uint64_t>(), st),
-           "compact hit ends");
-        item_base += nchunks * ci.ntiles;
-    }
-    uint32_t key_bits = 0;
-    while (key_bits < 32 && ((uint64_t)1 << key_bits) < (uint64_t)pl.locals.size() * c->npat) ++key_bits;
-    bool second = false;
-    ck(launch_radix_sort(key0, val0, key1, val1, n, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
-       "radix sort");
-    ck(launch_gather_raw(second ? key1 : key0, second ? val1 : val0, n, c->npat, ncarry, c->sort_end.as<uint64_t>(),
-                         d_carry, d_carry_hk, hks, c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(),
-                         c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(), c->r_dist.as<uint8_t>(),
-                         c->r_hk.as<uint8_t>(), st),
-       "gather hit ends");
-    ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                      c->r_flag.as<uint8_t>(), n, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
-                      c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
-       "recover");
-    const uint32_t do_filter = c->rules == OASM_RULES_PAPER ? 1u : 0u;
-    ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_hk.as<uint8_t>(),
-                     n, hks, c->d_pats.as<PatDesc>(), d_sdesc, do_filter, out_stride, c->seg_out.as<OccRec>(),
-                     c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
-       "filter");
-    ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), n, ctl + 2,
-                             c->scan_tmp.as<uint32_t>(), st),
-       "occ scan");
-    ck(launch_exclusive_scan(c->carry_flag.as<uint32_t>(), c->carry_off.as<uint32_t>(), n, ctl + 3,
-                             c->scan_tmp.as<uint32_t>(), st),
-       "carry scan");
-    ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
-    wait_stream(c, "sync after filter");
-    const uint32_t *h = c->pin_ctl.as<uint32_t>();
-    const uint32_t nocc = h[2], ncarry_out = h[3], rec_err = h[4];
-    if (rec_err) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
-
-    c->occ_out.ensure(std::max<uint32_t>(nocc, 1) * sizeof(OccRec), st);
-    c->carry_buf[cout].ensure(std::max<uint32_t>(ncarry_out, 1) * sizeof(CarryRec), st);
-    c->carry_hk_buf[cout].ensure(std::max<uint32_t>(ncarry_out, 1) * (uint64_t)hks, st);
-    ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), n,
-                          out_stride, c->occ_out.as<OccRec>(), st),
-       "compact occ");
-    ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                            c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
-                            c->carry_off.as<uint32_t>(), d_sdesc, n, c->carry_buf[cout].as<CarryRec>(),
-                            c->carry_hk_buf[cout].as<uint8_t>(), st),
-       "compact carry");
 
     // copy back: raw (pat, sl, end, flag, dist), hk (when kept), occurrences, carry
     const bool keep_raw = !(c->cfg.flags & OASM_CFG_NO_RAW);
