@@ -70,14 +70,19 @@ struct OccRec {
 };
 
 // A record count that lives in device memory: min(add + *p, cap) (p may be
-// null).  Kernels after the scan read their sizes this way, so a whole step
-// is queued without the host waiting for intermediate counts; `cap` is the
-// capacity the buffers were sized for (a count above it is detected at the
-// end of the step, which is then run again with larger buffers).
+// null), or 0 when *gate > gate_max (gate may be null).  Kernels after the
+// scan read their sizes this way, so a whole step is queued without the host
+// waiting for intermediate counts; `cap` is the capacity the buffers were
+// sized for.  The gate is the scan's largest per-item record count: above the
+// per-item capacity some records were dropped, the compacted arrays have
+// unwritten holes, and every later kernel must do nothing (the step is run
+// again with larger buffers, as it is when a count exceeds its capacity).
 struct DevN {
     const uint32_t *p;
     uint32_t add;
     uint32_t cap;
+    const uint32_t *gate;
+    uint32_t gate_max;
 };
 
 // ------------------------------------------------------------------ launchers

@@ -28,6 +28,7 @@ __device__ __forceinline__ uint32_t lane_id() {
 }
 
 __device__ __forceinline__ uint32_t dev_n(const DevN &d) {
+    if (d.gate && *d.gate > d.gate_max) return 0u;
     const uint32_t v = d.add + (d.p ? *d.p : 0u);
     return v < d.cap ? v : d.cap;
 }
@@ -579,7 +580,7 @@ hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint3
     uint32_t *stmp = offs + (size_t)256 * nb;
     uint32_t *total = stmp + scan_tmp_words((size_t)256 * nb);
     uint32_t *ki = key, *vi = val, *ko = key2, *vo = val2;
-    const DevN hn{nullptr, 256u * nb, 256u * nb};
+    const DevN hn{nullptr, 256u * nb, 256u * nb, nullptr, 0u};
     for (uint32_t shift = 0; shift < key_bits; shift += 8) {
         hipLaunchKernelGGL(k_sort_hist, dim3(nb), dim3(kSortThreads), 0, st, ki, n, shift, nb, hist);
         hipError_t e = launch_exclusive_scan(hist, offs, hn, total, stmp, st);
@@ -601,6 +602,7 @@ __global__ void k_gather_raw(const uint32_t *__restrict__ skey, const uint32_t *
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= dev_n(dn)) return;
     const uint32_t k = skey[i], src = sval[i];
+    if (src >= dn.cap) return;  // cannot happen when the gate passed; never index past the arrays
     r_pat[i] = k % npat;
     r_sl[i] = k / npat;
     r_end[i] = end_in[src];

@@ -402,11 +402,11 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             c->stats.scan_launches++;
         }
         ck(hipEventRecord(c->ev1, st), "event");
-        const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems};
+        const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems, nullptr, 0u};
         ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), items, ctl + 1,
                                  c->scan_tmp.as<uint32_t>(), st),
            "item count scan");
-        const DevN dn{ctl + 1, ncarry, cap_n};  // carried + new hit ends
+        const DevN dn{ctl + 1, ncarry, cap_n, ctl + 0, c->cap};  // carried + new hit ends
         uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
         uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
         ck(launch_place_carry(d_carry, std::min(ncarry, cap_n), d_s2l, c->npat, key0, val0,
