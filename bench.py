@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--multiword-bytes", type=int, default=1 << 26)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--no-autotune", action="store_true", help="heuristic scan variants instead of measured ones")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every kernel of a step instead of graph replay")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
     ap.add_argument("--serving-sessions", type=int, default=10_000)
     ap.add_argument("--serving-gbps", type=float, default=20.0)
@@ -131,11 +132,11 @@ def cpu_baseline(w, target_s: float):
                       f"(hit ends, hit set and filter), {dt:.1f} s"}
 
 
-def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True):
+def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True, graphs=True):
     """Time `steps` whole-path steps over device-resident streams (after `warmup`)."""
     dev_streams = [torch.from_numpy(t).cuda() for t in w.streams]
     torch.cuda.synchronize()
-    mt = oasm.Matcher(w.patterns, w.ks, chunk_bytes=chunk, plain=plain, autotune=autotune)
+    mt = oasm.Matcher(w.patterns, w.ks, chunk_bytes=chunk, plain=plain, autotune=autotune, graphs=graphs)
     tune = mt.tune_report()
     sid = [0]
 
@@ -245,7 +246,8 @@ def main():
     if args.calibrate_copy:
         copy_calibration()
     w, desc = make_workload(args.workload, args)
-    r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk, autotune=not args.no_autotune)
+    r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk, autotune=not args.no_autotune,
+                  graphs=not args.no_graphs)
     msum = sum(len(p) for p in w.patterns)
     total_bytes = w.total_bytes
     cells = msum * total_bytes
@@ -289,6 +291,7 @@ def main():
             "host_plan_launch_convert_book": [round((b - a) / args.steps, 3) for a, b in
                                               zip(s0["host_ms"], s1["host_ms"])],
             "python_feed_drain": round(ms_per_step - (s1["sync_wall_ms"] - s0["sync_wall_ms"]) / args.steps, 3),
+            "graph_replays": s1["graph_replays"] - s0["graph_replays"],
         },
         "hits": {"hit_ends": int(res.raw.size), "occurrences": int(res.occ.size)},
         "autotune": [x for x in r["tune"].splitlines() if x],

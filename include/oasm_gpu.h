@@ -84,6 +84,7 @@ typedef int32_t oasm_status;
 #define OASM_CFG_KEEP_H 2u /* keep the hit set for draining with OASM_H (debugging) */
 #define OASM_CFG_NO_RAW 4u /* do not queue hit ends for draining (they are still computed) */
 #define OASM_CFG_AUTOTUNE 8u /* time the scan variants of every pattern class at create and keep the fastest */
+#define OASM_CFG_GRAPHS 16u  /* capture a step's launches as HIP graphs when its shape repeats, and replay them */
 
 /* Drain kinds. */
 #define OASM_RAW 0u      /* oasm_hit records: hit ends and their distance */
@@ -164,6 +165,7 @@ typedef struct oasm_stats {
     double wait_ms;             /* part of it spent waiting for the device */
     double host_ms[4];          /* host time per step phase: plan and upload, launches,
                                    result conversion, stream bookkeeping */
+    uint64_t graph_replays;     /* steps launched from captured graphs */
 } oasm_stats;
 
 /* Fill `cfg` with defaults (device -1, library stream, autotuned chunks). */

@@ -380,9 +380,15 @@ static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStrea
     if (gx == 0 || a.ntiles == 0) return hipSuccess;
     const size_t shmem = lds ? (size_t)a.nclass * kWave * pad_pow2(P * W) * 4 : 0;
     if (lds) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-        if (e != hipSuccess) return e;
+        // raise the instance's dynamic-LDS limit once (never inside a graph
+        // capture: the first launch of a shape is always an eager one)
+        static size_t configured = 0;
+        if (shmem > configured) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+            if (e != hipSuccess) return e;
+            configured = shmem;
+        }
         hipLaunchKernelGGL((k_scan<W, P, true>), dim3(gx, a.ntiles), dim3(waves * kWave), shmem, st, a);
     } else {
         hipLaunchKernelGGL((k_scan<W, P, false>), dim3(gx, a.ntiles), dim3(waves * kWave), 0, st, a);

@@ -169,6 +169,9 @@ struct oasm_ctx {
     uint32_t cap_occ = 1u << 16;
     uint32_t cap_carry = 1u << 12;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    // captured launch sequence of the last repeated step shape
+    hipGraphExec_t graph_a = nullptr, graph_b = nullptr;
+    std::vector<uint64_t> graph_key, graph_prev_key;
 
     // results
     std::vector<oasm_hit> q_raw;
@@ -216,6 +219,13 @@ void wait_stream(oasm_ctx *c, const char *what) {
     const double t0 = now_ms();
     ck(hipStreamSynchronize(c->st), what);
     c->stats.wait_ms += now_ms() - t0;
+}
+
+void drop_graphs(oasm_ctx *c) {
+    if (c->graph_a) (void)hipGraphExecDestroy(c->graph_a);
+    if (c->graph_b) (void)hipGraphExecDestroy(c->graph_b);
+    c->graph_a = c->graph_b = nullptr;
+    c->graph_key.clear();
 }
 
 uint32_t pow2_at_least(uint64_t v) {
@@ -378,79 +388,127 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         c->carry_buf[cout].ensure((uint64_t)cap_carry * sizeof(CarryRec), st);
         c->carry_hk_buf[cout].ensure((uint64_t)cap_carry * hks, st);
 
-        ck(launch_fill_u32(ctl, 0, 16, st), "fill ctl");
-        ck(hipEventRecord(c->ev0, st), "event");
-        uint32_t item_base = 0;
-        for (const ClassInfo &ci : c->classes) {
-            ScanArgs a;
-            a.chunks = d_chunks;
-            a.nchunks = nchunks;
-            a.tiles = c->d_tiles.as<TileDesc>();
-            a.tile_first = ci.tile_first;
-            a.ntiles = ci.ntiles;
-            a.peq_img = c->d_peq.as<uint32_t>();
-            a.slot_pat = c->d_slot_pat.as<uint32_t>();
-            a.pats = c->d_pats.as<PatDesc>();
-            a.nclass = c->nclass;
-            a.item_rec = c->item_rec.as<uint32_t>();
-            a.item_cnt = c->item_cnt.as<uint32_t>();
-            a.item_base = item_base;
-            a.cap = c->cap;
-            a.max_cnt = ctl + 0;
-            ck(launch_scan(ci.W, ci.P, a, ci.waves, ci.lds, st), "scan launch");
-            item_base += nchunks * ci.ntiles;
-            c->stats.scan_launches++;
+        // The step's launch sequence in two parts (the scan, then everything
+        // after it), with the scan-timing event between them.
+        auto part_a = [&]() {
+            ck(launch_fill_u32(ctl, 0, 16, st), "fill ctl");
+            uint32_t item_base = 0;
+            for (const ClassInfo &ci : c->classes) {
+                ScanArgs a;
+                a.chunks = d_chunks;
+                a.nchunks = nchunks;
+                a.tiles = c->d_tiles.as<TileDesc>();
+                a.tile_first = ci.tile_first;
+                a.ntiles = ci.ntiles;
+                a.peq_img = c->d_peq.as<uint32_t>();
+                a.slot_pat = c->d_slot_pat.as<uint32_t>();
+                a.pats = c->d_pats.as<PatDesc>();
+                a.nclass = c->nclass;
+                a.item_rec = c->item_rec.as<uint32_t>();
+                a.item_cnt = c->item_cnt.as<uint32_t>();
+                a.item_base = item_base;
+                a.cap = c->cap;
+                a.max_cnt = ctl + 0;
+                ck(launch_scan(ci.W, ci.P, a, ci.waves, ci.lds, st), "scan launch");
+                item_base += nchunks * ci.ntiles;
+                c->stats.scan_launches++;
+            }
+        };
+        auto part_b = [&]() {
+            const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems, nullptr, 0u};
+            ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), items, ctl + 1,
+                                     c->scan_tmp.as<uint32_t>(), st),
+               "item count scan");
+            const DevN dn{ctl + 1, ncarry, cap_n, ctl + 0, c->cap};  // carried + new hit ends
+            uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
+            uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
+            ck(launch_place_carry(d_carry, std::min(ncarry, cap_n), d_s2l, c->npat, key0, val0,
+                                  c->sort_end.as<uint64_t>(), st),
+               "place carry");
+            uint32_t item_base = 0;
+            for (const ClassInfo &ci : c->classes) {
+                ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
+                                      c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(),
+                                      c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), item_base, c->cap, ncarry,
+                                      cap_n, c->npat, key0, val0, c->sort_end.as<uint64_t>(), st),
+                   "compact hit ends");
+                item_base += nchunks * ci.ntiles;
+            }
+            bool second = false;
+            ck(launch_radix_sort(key0, val0, key1, val1, dn, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
+               "radix sort");
+            ck(launch_gather_raw(second ? key1 : key0, second ? val1 : val0, dn, c->npat, ncarry,
+                                 c->sort_end.as<uint64_t>(), d_carry, d_carry_hk, hks, c->r_pat.as<uint32_t>(),
+                                 c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(),
+                                 c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), st),
+               "gather hit ends");
+            ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                              c->r_flag.as<uint8_t>(), dn, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
+                              c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
+               "recover");
+            ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                             c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, do_filter, out_stride,
+                             c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
+               "filter");
+            ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
+                                     c->scan_tmp.as<uint32_t>(), st),
+               "occ scan");
+            ck(launch_exclusive_scan(c->carry_flag.as<uint32_t>(), c->carry_off.as<uint32_t>(), dn, ctl + 3,
+                                     c->scan_tmp.as<uint32_t>(), st),
+               "carry scan");
+            ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn,
+                                  out_stride, c->occ_out.as<OccRec>(), cap_occ, st),
+               "compact occ");
+            ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                                    c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
+                                    c->carry_off.as<uint32_t>(), d_sdesc, dn, c->carry_buf[cout].as<CarryRec>(),
+                                    c->carry_hk_buf[cout].as<uint8_t>(), cap_carry, st),
+               "compact carry");
+        };
+        // Replay captured graphs when this step has the same shape (every kernel
+        // argument and buffer) as the last; capture when a shape repeats.
+        std::vector<uint64_t> gkey;
+        if (c->cfg.flags & OASM_CFG_GRAPHS) {
+            gkey = {nchunks, ncarry, c->cap, cap_n, cap_occ, cap_carry, key_bits, (uint64_t)pl.locals.size(),
+                    (uint64_t)(uintptr_t)c->plan.p, o_chunks, o_sdesc, o_s2l, (uint64_t)cin,
+                    (uint64_t)(uintptr_t)c->item_rec.p, (uint64_t)(uintptr_t)c->scan_tmp.p,
+                    (uint64_t)(uintptr_t)c->sort_key.p, (uint64_t)(uintptr_t)c->sort_tmp.p,
+                    (uint64_t)(uintptr_t)c->seg_out.p, (uint64_t)(uintptr_t)c->occ_out.p,
+                    (uint64_t)(uintptr_t)c->carry_buf[cin].p, (uint64_t)(uintptr_t)c->carry_buf[cout].p,
+                    (uint64_t)(uintptr_t)c->r_hk.p};
         }
-        ck(hipEventRecord(c->ev1, st), "event");
-        const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems, nullptr, 0u};
-        ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), items, ctl + 1,
-                                 c->scan_tmp.as<uint32_t>(), st),
-           "item count scan");
-        const DevN dn{ctl + 1, ncarry, cap_n, ctl + 0, c->cap};  // carried + new hit ends
-        uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
-        uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
-        ck(launch_place_carry(d_carry, std::min(ncarry, cap_n), d_s2l, c->npat, key0, val0,
-                              c->sort_end.as<uint64_t>(), st),
-           "place carry");
-        item_base = 0;
-        for (const ClassInfo &ci : c->classes) {
-            ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
-                                  c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(),
-                                  c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), item_base, c->cap, ncarry,
-                                  cap_n, c->npat, key0, val0, c->sort_end.as<uint64_t>(), st),
-               "compact hit ends");
-            item_base += nchunks * ci.ntiles;
+        if (!gkey.empty() && gkey == c->graph_key && c->graph_a) {
+            ck(hipEventRecord(c->ev0, st), "event");
+            ck(hipGraphLaunch(c->graph_a, st), "graph launch");
+            ck(hipEventRecord(c->ev1, st), "event");
+            ck(hipGraphLaunch(c->graph_b, st), "graph launch");
+            c->stats.scan_launches += c->classes.size();
+            c->stats.graph_replays++;
+        } else if (!gkey.empty() && gkey == c->graph_prev_key) {
+            drop_graphs(c);
+            hipGraph_t ga = nullptr, gb = nullptr;
+            ck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+            part_a();
+            ck(hipStreamEndCapture(st, &ga), "end capture");
+            ck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+            part_b();
+            ck(hipStreamEndCapture(st, &gb), "end capture");
+            ck(hipGraphInstantiate(&c->graph_a, ga, nullptr, nullptr, 0), "graph instantiate");
+            ck(hipGraphInstantiate(&c->graph_b, gb, nullptr, nullptr, 0), "graph instantiate");
+            ck(hipGraphDestroy(ga), "graph destroy");
+            ck(hipGraphDestroy(gb), "graph destroy");
+            c->graph_key = gkey;
+            ck(hipEventRecord(c->ev0, st), "event");
+            ck(hipGraphLaunch(c->graph_a, st), "graph launch");
+            ck(hipEventRecord(c->ev1, st), "event");
+            ck(hipGraphLaunch(c->graph_b, st), "graph launch");
+        } else {
+            ck(hipEventRecord(c->ev0, st), "event");
+            part_a();
+            ck(hipEventRecord(c->ev1, st), "event");
+            part_b();
         }
-        bool second = false;
-        ck(launch_radix_sort(key0, val0, key1, val1, dn, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
-           "radix sort");
-        ck(launch_gather_raw(second ? key1 : key0, second ? val1 : val0, dn, c->npat, ncarry,
-                             c->sort_end.as<uint64_t>(), d_carry, d_carry_hk, hks, c->r_pat.as<uint32_t>(),
-                             c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(),
-                             c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), st),
-           "gather hit ends");
-        ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                          c->r_flag.as<uint8_t>(), dn, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
-                          c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
-           "recover");
-        ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                         c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, do_filter, out_stride,
-                         c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
-           "filter");
-        ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
-                                 c->scan_tmp.as<uint32_t>(), st),
-           "occ scan");
-        ck(launch_exclusive_scan(c->carry_flag.as<uint32_t>(), c->carry_off.as<uint32_t>(), dn, ctl + 3,
-                                 c->scan_tmp.as<uint32_t>(), st),
-           "carry scan");
-        ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn,
-                              out_stride, c->occ_out.as<OccRec>(), cap_occ, st),
-           "compact occ");
-        ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                                c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
-                                c->carry_off.as<uint32_t>(), d_sdesc, dn, c->carry_buf[cout].as<CarryRec>(),
-                                c->carry_hk_buf[cout].as<uint8_t>(), cap_carry, st),
-           "compact carry");
+        c->graph_prev_key = gkey;
         ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
         wait_stream(c, "step sync");
         const uint32_t *h = c->pin_ctl.as<uint32_t>();
@@ -562,7 +620,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     const CarryRec *hc = reinterpret_cast<const CarryRec *>(hp + o_cr);
     for (uint32_t i = 0; i < ncarry_out; ++i) c->streams[hc[i].stream_slot].ncarry++;
     c->ncarry = ncarry_out;
-    c->carry_cur = cout;
+    if (ncarry_out) c->carry_cur = cout;  // nothing carried: keep the buffers (and the step's shape) as they are
     // stream bookkeeping (matched streams only): keep a look-back tail of
     // each stream's symbols
     for (uint32_t si : which) {
@@ -1305,6 +1363,7 @@ void oasm_destroy(oasm_ctx *c) {
     c->pin_feed.release();
     c->pin_seg.release();
     c->d_seg.release();
+    drop_graphs(c);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev2) (void)hipEventDestroy(c->ev2);

@@ -34,6 +34,7 @@ OASM_CFG_PLAIN = 1
 OASM_CFG_KEEP_H = 2
 OASM_CFG_NO_RAW = 4
 OASM_CFG_AUTOTUNE = 8
+OASM_CFG_GRAPHS = 16
 OASM_RAW = 0
 OASM_FILTERED = 1
 OASM_H = 2
@@ -83,7 +84,7 @@ class oasm_stats(ctypes.Structure):
                 ("raw_hits", ctypes.c_uint64), ("h_records", ctypes.c_uint64), ("occurrences", ctypes.c_uint64),
                 ("syncs", ctypes.c_uint64), ("scan_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
                 ("scan_launches", ctypes.c_uint64), ("sync_wall_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
-                ("host_ms", ctypes.c_double * 4)]
+                ("host_ms", ctypes.c_double * 4), ("graph_replays", ctypes.c_uint64)]
 
 
 class oasm_serve_report(ctypes.Structure):
@@ -265,12 +266,13 @@ class Matcher:
 
     def __init__(self, patterns, k, rules: int = OASM_RULES_PAPER, *, plain: bool = False, keep_h: bool = False,
                  no_raw: bool = False, chunk_bytes: int = 0, hip_stream: int | None = None, device: int = -1,
-                 mem_budget: int = 0, autotune: bool = False):
+                 mem_budget: int = 0, autotune: bool = False, graphs: bool = False):
         cfg = oasm_config_init()
         cfg.device = device
         cfg.chunk_bytes = chunk_bytes
         cfg.flags = (OASM_CFG_PLAIN if plain else 0) | (OASM_CFG_KEEP_H if keep_h else 0) | (
-            OASM_CFG_NO_RAW if no_raw else 0) | (OASM_CFG_AUTOTUNE if autotune else 0)
+            OASM_CFG_NO_RAW if no_raw else 0) | (OASM_CFG_AUTOTUNE if autotune else 0) | (
+            OASM_CFG_GRAPHS if graphs else 0)
         cfg.device_mem_budget = mem_budget
         cfg.hip_stream = hip_stream
         self.keep_h = keep_h

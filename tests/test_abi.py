@@ -50,7 +50,7 @@ def test_record_layouts():
     assert ctypes.sizeof(oasm.oasm_hit) == 24
     assert ctypes.sizeof(oasm.oasm_occ) == 32
     assert ctypes.sizeof(oasm.oasm_config) == 32
-    assert ctypes.sizeof(oasm.oasm_stats) == 128
+    assert ctypes.sizeof(oasm.oasm_stats) == 136
     assert ctypes.sizeof(oasm.oasm_serve_report) == 56
     assert oasm.SEG_DTYPE.itemsize == 32
 

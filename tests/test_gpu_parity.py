@@ -179,3 +179,36 @@ def test_long_config_full_size_sampled_patterns():
     for pl in w.plants[:2000]:
         e = pl.site + pl.length - 1
         assert e in ends.get(pl.pattern, ()), (pl, "planted copy not reported")
+
+
+def test_graph_replays_equal_eager():
+    """Steps of one repeated shape are captured as HIP graphs on the second
+    occurrence and replayed afterwards; every replayed step (with eager feeds,
+    drains and synchronisations in between) must equal an eager run."""
+    w = W.small_random(60, 30000, 40, 8, 90, b"ACGT", kmax=8, n_plants=0)
+    rng = np.random.default_rng(60)
+    pieces = []
+    for i in range(6):  # six streams of one length: six steps of one shape
+        t = rng.integers(65, 69, size=30000).astype(np.uint8)
+        for q in range(20):  # planted copies so every step has hits
+            p = w.patterns[int(rng.integers(0, len(w.patterns)))]
+            o = int(rng.integers(0, t.size - len(p)))
+            t[o:o + len(p)] = np.frombuffer(p, np.uint8)
+        pieces.append(t)
+    outs = {}
+    for graphs in (False, True):
+        steps = []
+        with oasm.Matcher(w.patterns, w.ks, graphs=graphs) as mt:
+            for i, t in enumerate(pieces):
+                mt.feed(i, torch.from_numpy(t).cuda(), last=True)
+                mt.sync()
+                steps.append(mt.results())
+            replays = mt.stats()["graph_replays"]
+        outs[graphs] = (steps, replays)
+    assert outs[False][1] == 0 and outs[True][1] >= 4
+    for a, b in zip(outs[False][0], outs[True][0]):
+        assert np.array_equal(a.raw, b.raw) and np.array_equal(a.occ, b.occ)
+    streams = {i: t for i, t in enumerate(pieces)}
+    merged = oasm.Results(np.concatenate([s.raw for s in outs[True][0]]),
+                          np.concatenate([s.occ for s in outs[True][0]]))
+    compare(merged, streams, w.patterns, w.ks, label="graphs")
