@@ -288,7 +288,7 @@ def main():
             "device_step": round((s1["step_ms"] - s0["step_ms"]) / args.steps, 3),
             "sync_wall": round((s1["sync_wall_ms"] - s0["sync_wall_ms"]) / args.steps, 3),
             "sync_waiting": round((s1["wait_ms"] - s0["wait_ms"]) / args.steps, 3),
-            "host_plan_launch_convert_book": [round((b - a) / args.steps, 3) for a, b in
+            "host_plan_launch_copyback_convert": [round((b - a) / args.steps, 3) for a, b in
                                               zip(s0["host_ms"], s1["host_ms"])],
             "python_feed_drain": round(ms_per_step - (s1["sync_wall_ms"] - s0["sync_wall_ms"]) / args.steps, 3),
             "graph_replays": s1["graph_replays"] - s0["graph_replays"],

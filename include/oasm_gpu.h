@@ -163,8 +163,9 @@ typedef struct oasm_stats {
     uint64_t scan_launches;     /* scan kernel launches */
     double sync_wall_ms;        /* host wall time spent inside oasm_sync */
     double wait_ms;             /* part of it spent waiting for the device */
-    double host_ms[4];          /* host time per step phase: plan and upload, launches,
-                                   result conversion, stream bookkeeping */
+    double host_ms[4];          /* host time per step phase, device waits excluded: plan and
+                                   upload; launches up to the step's end; copy-back of the
+                                   results; result conversion and stream bookkeeping */
     uint64_t graph_replays;     /* steps launched from captured graphs */
 } oasm_stats;
 

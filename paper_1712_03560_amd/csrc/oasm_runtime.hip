@@ -511,6 +511,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         c->graph_prev_key = gkey;
         ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
         wait_stream(c, "step sync");
+        phase(1);
         const uint32_t *h = c->pin_ctl.as<uint32_t>();
         n_new = h[1];
         nocc = h[2];
@@ -576,7 +577,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     float ms = 0;
     if (hipEventElapsedTime(&ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += ms;
 
-    phase(1);
+    phase(2);
     // host bookkeeping: queue results
     const uint32_t *hpat = reinterpret_cast<const uint32_t *>(hp + o_pat);
     const uint32_t *hsl = reinterpret_cast<const uint32_t *>(hp + o_sl);
@@ -614,7 +615,6 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         const uint64_t sid = c->streams[pl.locals[ho[i].stream_local]].id;
         c->q_occ.push_back(oasm_occ{sid, ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
     }
-    phase(2);
     // the new carry stays on the device; the host keeps per-stream counts
     for (uint32_t si : pl.locals) c->streams[si].ncarry = 0;
     const CarryRec *hc = reinterpret_cast<const CarryRec *>(hp + o_cr);
