@@ -170,6 +170,26 @@ hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, con
                                 const uint32_t *carry_off, const StreamDesc *streams, DevN n, CarryRec *out,
                                 uint8_t *out_hk, uint32_t out_cap, hipStream_t st);
 
+// The step's results written straight into mapped pinned host memory (the
+// GPU stores over the bus; the host reads them after its one wait).  Offsets
+// are byte offsets into `host`; a zero-length region is skipped.
+struct PackArgs {
+    const uint32_t *ctl;      // 16 control words
+    DevN n;                   // hit ends of the step
+    const uint32_t *r_pat, *r_sl;
+    const uint64_t *r_end;
+    const uint8_t *r_flag, *r_dist, *r_hk;
+    uint32_t hks;
+    uint32_t with_raw, with_hk;
+    const OccRec *occ;
+    uint32_t cap_occ;
+    const CarryRec *carry;
+    uint32_t cap_carry;
+    uint8_t *host;
+    uint64_t o_ctl, o_pat, o_sl, o_end, o_flag, o_dist, o_hk, o_occ, o_cr;
+};
+hipError_t launch_pack_results(const PackArgs &a, hipStream_t st);
+
 // Exclusive prefix sum of n uint32 values; writes the total to *total.
 // `tmp` must hold scan_tmp_words(n) uint32.
 size_t scan_tmp_words(size_t cap);

@@ -891,6 +891,46 @@ hipError_t launch_compact_carry(const uint32_t *r_pat, const uint32_t *r_sl, con
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ results
+// Grid-stride copies of the step's results into mapped host memory: control
+// words, the hit-end arrays (and hit-set bytes), occurrences, carried ends.
+__global__ void __launch_bounds__(256) k_pack_results(PackArgs a) {
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t n = dev_n(a.n);
+    const uint32_t nocc = min(a.ctl[2], a.cap_occ);
+    const uint32_t ncar = min(a.ctl[3], a.cap_carry);
+    if (tid < 16) reinterpret_cast<uint32_t *>(a.host + a.o_ctl)[tid] = a.ctl[tid];
+    if (a.with_raw) {
+        uint32_t *hp = reinterpret_cast<uint32_t *>(a.host + a.o_pat);
+        uint32_t *hs = reinterpret_cast<uint32_t *>(a.host + a.o_sl);
+        uint64_t *he = reinterpret_cast<uint64_t *>(a.host + a.o_end);
+        uint8_t *hf = a.host + a.o_flag, *hd = a.host + a.o_dist;
+        for (uint32_t i = tid; i < n; i += stride) {
+            hp[i] = a.r_pat[i];
+            hs[i] = a.r_sl[i];
+            he[i] = a.r_end[i];
+            hf[i] = a.r_flag[i];
+            hd[i] = a.r_dist[i];
+        }
+    }
+    if (a.with_hk) {
+        const uint64_t nb = (uint64_t)n * a.hks;
+        for (uint64_t i = tid; i < nb; i += stride) a.host[a.o_hk + i] = a.r_hk[i];
+    }
+    uint64_t *ho = reinterpret_cast<uint64_t *>(a.host + a.o_occ);
+    const uint64_t *so = reinterpret_cast<const uint64_t *>(a.occ);
+    for (uint64_t i = tid; i < (uint64_t)nocc * 3; i += stride) ho[i] = so[i];
+    uint64_t *hc = reinterpret_cast<uint64_t *>(a.host + a.o_cr);
+    const uint64_t *sc = reinterpret_cast<const uint64_t *>(a.carry);
+    for (uint64_t i = tid; i < (uint64_t)ncar * 3; i += stride) hc[i] = sc[i];
+}
+
+hipError_t launch_pack_results(const PackArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_pack_results, dim3(512), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ scan
 // Exclusive prefix sum in three passes: per-block sums, a single-block scan
 // of the block sums, and per-block scans offset by the scanned sums.

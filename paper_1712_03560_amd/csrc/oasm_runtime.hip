@@ -360,10 +360,15 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     c->item_cnt.ensure(std::max<uint64_t>(1, nitems) * 4, st);
     c->offsets.ensure(std::max<uint64_t>(1, nitems) * 4, st);
 
+    const bool keep_raw = !(c->cfg.flags & OASM_CFG_NO_RAW);
+    const bool keep_h_out = (c->cfg.flags & OASM_CFG_KEEP_H) != 0;
+    const bool keep_any_raw = keep_raw || keep_h_out;
+
     // The whole step is queued at once: every kernel after the scan reads its
     // size from device memory and the buffers are sized by capacities that
     // grow (and the step runs again) when a count exceeds them.
     uint32_t n_new = 0, nocc = 0, ncarry_out = 0;
+    PackArgs layout{};
     for (int attempt = 0;; ++attempt) {
         const uint32_t cap_n = c->cap_n, cap_occ = c->cap_occ, cap_carry = c->cap_carry;
         const uint64_t n1 = cap_n;
@@ -387,6 +392,29 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         c->occ_out.ensure((uint64_t)cap_occ * sizeof(OccRec), st);
         c->carry_buf[cout].ensure((uint64_t)cap_carry * sizeof(CarryRec), st);
         c->carry_hk_buf[cout].ensure((uint64_t)cap_carry * hks, st);
+
+        // layout of the mapped pinned results buffer, by capacity
+        PackArgs pk{};
+        {
+            size_t off = 0;
+            auto region = [&](size_t bytes) {
+                const size_t o = (off + 255) & ~size_t(255);
+                off = o + bytes;
+                return (uint64_t)o;
+            };
+            pk.o_ctl = region(64);
+            pk.o_pat = region(keep_any_raw ? n1 * 4 : 0);
+            pk.o_sl = region(keep_any_raw ? n1 * 4 : 0);
+            pk.o_end = region(keep_any_raw ? n1 * 8 : 0);
+            pk.o_flag = region(keep_any_raw ? n1 : 0);
+            pk.o_dist = region(keep_any_raw ? n1 : 0);
+            pk.o_hk = region(keep_h_out ? n1 * hks : 0);
+            pk.o_occ = region((size_t)cap_occ * sizeof(OccRec));
+            pk.o_cr = region((size_t)cap_carry * sizeof(CarryRec));
+            c->pin_out.ensure(off + 256, st);
+        }
+        void *dev_host = nullptr;
+        ck(hipHostGetDevicePointer(&dev_host, c->pin_out.p, 0), "mapped results buffer");
 
         // The step's launch sequence in two parts (the scan, then everything
         // after it), with the scan-timing event between them.
@@ -464,6 +492,23 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                                     c->carry_off.as<uint32_t>(), d_sdesc, dn, c->carry_buf[cout].as<CarryRec>(),
                                     c->carry_hk_buf[cout].as<uint8_t>(), cap_carry, st),
                "compact carry");
+            pk.ctl = ctl;
+            pk.n = dn;
+            pk.r_pat = c->r_pat.as<uint32_t>();
+            pk.r_sl = c->r_sl.as<uint32_t>();
+            pk.r_end = c->r_end.as<uint64_t>();
+            pk.r_flag = c->r_flag.as<uint8_t>();
+            pk.r_dist = c->r_dist.as<uint8_t>();
+            pk.r_hk = c->r_hk.as<uint8_t>();
+            pk.hks = hks;
+            pk.with_raw = keep_any_raw ? 1u : 0u;
+            pk.with_hk = keep_h_out ? 1u : 0u;
+            pk.occ = c->occ_out.as<OccRec>();
+            pk.cap_occ = cap_occ;
+            pk.carry = c->carry_buf[cout].as<CarryRec>();
+            pk.cap_carry = cap_carry;
+            pk.host = reinterpret_cast<uint8_t *>(dev_host);
+            ck(launch_pack_results(pk, st), "pack results");
         };
         // Replay captured graphs when this step has the same shape (every kernel
         // argument and buffer) as the last; capture when a shape repeats.
@@ -475,7 +520,8 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                     (uint64_t)(uintptr_t)c->sort_key.p, (uint64_t)(uintptr_t)c->sort_tmp.p,
                     (uint64_t)(uintptr_t)c->seg_out.p, (uint64_t)(uintptr_t)c->occ_out.p,
                     (uint64_t)(uintptr_t)c->carry_buf[cin].p, (uint64_t)(uintptr_t)c->carry_buf[cout].p,
-                    (uint64_t)(uintptr_t)c->r_hk.p};
+                    (uint64_t)(uintptr_t)c->r_hk.p, (uint64_t)(uintptr_t)c->pin_out.p, (uint64_t)keep_any_raw,
+                    (uint64_t)keep_h_out};
         }
         if (!gkey.empty() && gkey == c->graph_key && c->graph_a) {
             ck(hipEventRecord(c->ev0, st), "event");
@@ -508,11 +554,12 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             ck(hipEventRecord(c->ev1, st), "event");
             part_b();
         }
+        ck(hipEventRecord(c->ev2, st), "event");
         c->graph_prev_key = gkey;
-        ck(hipMemcpyAsync(c->pin_ctl.p, ctl, 64, hipMemcpyDeviceToHost, st), "ctl d2h");
         wait_stream(c, "step sync");
         phase(1);
-        const uint32_t *h = c->pin_ctl.as<uint32_t>();
+        const uint32_t *h = reinterpret_cast<const uint32_t *>(c->pin_out.as<uint8_t>() + pk.o_ctl);
+        layout = pk;
         n_new = h[1];
         nocc = h[2];
         ncarry_out = h[3];
@@ -542,41 +589,14 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     }
     const uint32_t n = ncarry + n_new;
 
-    // copy back: raw (pat, sl, end, flag, dist), hk (when kept), occurrences, carry
-    const bool keep_raw = !(c->cfg.flags & OASM_CFG_NO_RAW);
-    const bool keep_h = (c->cfg.flags & OASM_CFG_KEEP_H) != 0;
-    size_t off = 0;
-    auto slot = [&](size_t bytes) {
-        size_t o = (off + 255) & ~size_t(255);
-        off = o + bytes;
-        return o;
-    };
-    const size_t need_raw = keep_raw || keep_h;
-    const size_t o_pat = slot(need_raw ? n * 4ull : 0), o_sl = slot(need_raw ? n * 4ull : 0);
-    const size_t o_end = slot(need_raw ? n * 8ull : 0), o_flag = slot(need_raw ? n : 0);
-    const size_t o_dist = slot(need_raw ? n : 0), o_hk = slot(keep_h ? (size_t)n * hks : 0);
-    const size_t o_occ = slot((size_t)nocc * sizeof(OccRec));
-    const size_t o_cr = slot((size_t)ncarry_out * sizeof(CarryRec));
-    c->pin_out.ensure(off + 256, st);
+    // results are already in the mapped pinned buffer (written by the pack kernel)
+    float step_ms = 0;
+    if (hipEventElapsedTime(&step_ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += step_ms;
     uint8_t *hp = c->pin_out.as<uint8_t>();
-    auto d2h = [&](size_t o, const void *src, size_t bytes) {
-        if (bytes) ck(hipMemcpyAsync(hp + o, src, bytes, hipMemcpyDeviceToHost, st), "result d2h");
-    };
-    if (need_raw) {
-        d2h(o_pat, c->r_pat.p, n * 4ull);
-        d2h(o_sl, c->r_sl.p, n * 4ull);
-        d2h(o_end, c->r_end.p, n * 8ull);
-        d2h(o_flag, c->r_flag.p, n);
-        d2h(o_dist, c->r_dist.p, n);
-    }
-    if (keep_h) d2h(o_hk, c->r_hk.p, (size_t)n * hks);
-    d2h(o_occ, c->occ_out.p, (size_t)nocc * sizeof(OccRec));
-    d2h(o_cr, c->carry_buf[cout].p, (size_t)ncarry_out * sizeof(CarryRec));
-    ck(hipEventRecord(c->ev2, st), "event");
-    wait_stream(c, "sync after copy-back");
-    float ms = 0;
-    if (hipEventElapsedTime(&ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += ms;
-
+    const size_t o_pat = layout.o_pat, o_sl = layout.o_sl, o_end = layout.o_end, o_flag = layout.o_flag;
+    const size_t o_dist = layout.o_dist, o_hk = layout.o_hk, o_occ = layout.o_occ, o_cr = layout.o_cr;
+    const bool need_raw = keep_any_raw;
+    const bool keep_h = keep_h_out;
     phase(2);
     // host bookkeeping: queue results
     const uint32_t *hpat = reinterpret_cast<const uint32_t *>(hp + o_pat);
