@@ -31,6 +31,11 @@
  *     the lengths accepted so far in this emission (the pseudo-code's acc);
  *   - empty priority levels are skipped at emission;
  *   - positions are 0-based; t[i,l] covers t[i] .. t[i+l-1].
+ * oracle_filter also takes the alternative readings as flag bits (the same
+ * values as the library's OASM_RULES_* bits): acc = the last accepted length,
+ * ">=" in Eq. 3, R2 literally in start order (keep the first equal-priority
+ * hit), and acceptance only of occurrences disjoint from those accepted
+ * before them in the emission.
  *
  * Integer arithmetic only.  No blocking, no bit-parallelism, no cut-offs.
  */
@@ -209,6 +214,15 @@ typedef struct {
  *   Counters: while level idx is incomplete, the counters of levels idx..K
  *      are incremented once per stream symbol.
  *
+ * `rules` selects alternative readings (bit values as in the library):
+ *   2  ACC_LAST:    acc is the length of the last accepted occurrence;
+ *   4  EQ3_GE:      Eq. 3 reads r(j) - acc >= l(j);
+ *   8  START_ORDER: R2 replaces the stored hit only when its level is empty;
+ *   16 DISJOINT:    a lower level is accepted only if, in addition, its
+ *                   interval [i, i+l-1] shares no position with any
+ *                   occurrence accepted before it in this emission.
+ * rules = 1 (or 0) is the reading described above.
+ *
  * Every examined non-empty level at an emission is reported as one event
  * (emission position, level, i, l, r, acc before the test, accepted flag),
  * so the caller can read both S (the accepted events, in emission order) and
@@ -216,11 +230,15 @@ typedef struct {
  * Returns the number of events (writes at most `cap`), or -1.
  */
 int64_t oracle_filter(const int64_t *hs, const int32_t *hl, const int32_t *hk,
-                      int64_t nh, int32_t K, int64_t n, int64_t *ev_pos,
-                      int32_t *ev_level, int64_t *ev_i, int32_t *ev_l,
-                      int64_t *ev_r, int64_t *ev_acc, int32_t *ev_acc_flag,
-                      int64_t cap)
+                      int64_t nh, int32_t K, int64_t n, int32_t rules,
+                      int64_t *ev_pos, int32_t *ev_level, int64_t *ev_i,
+                      int32_t *ev_l, int64_t *ev_r, int64_t *ev_acc,
+                      int32_t *ev_acc_flag, int64_t cap)
 {
+    const int acc_last = (rules & 2) != 0;
+    const int eq3_ge = (rules & 4) != 0;
+    const int start_order = (rules & 8) != 0;
+    const int disjoint = (rules & 16) != 0;
     mem_row *mem = (mem_row *)calloc((size_t)K + 1, sizeof(mem_row));
     if (!mem)
         return -1;
@@ -247,7 +265,11 @@ int64_t oracle_filter(const int64_t *hs, const int32_t *hl, const int32_t *hk,
                 mem[idx].r = 1;
             } else if (k == idx) { /* R2 / R3 as read */
                 mem_row *b = &mem[idx];
-                int take = b->l == 0 || i + l < b->i + b->l ||
+                int take;
+                if (start_order)
+                    take = b->l == 0;
+                else
+                    take = b->l == 0 || i + l < b->i + b->l ||
                            (i + l == b->i + b->l && l < b->l);
                 if (take) {
                     ins = 1;
@@ -258,10 +280,31 @@ int64_t oracle_filter(const int64_t *hs, const int32_t *hl, const int32_t *hk,
             }
         }
         if (ins == 1 && mem[idx].r == mem[idx].l) {
+            int32_t nacc = 0; /* levels accepted so far in this emission */
+            int32_t *acc_lv = (int32_t *)malloc(sizeof(int32_t) * ((size_t)K + 1));
+            if (!acc_lv) {
+                free(mem);
+                return -1;
+            }
             for (int32_t j = idx; j <= K; ++j) {
                 if (mem[j].l == 0)
                     continue;
-                int accept = j == idx || mem[j].r - acc > mem[j].l; /* Eq. 3 */
+                int accept;
+                if (j == idx)
+                    accept = 1;
+                else if (eq3_ge)
+                    accept = mem[j].r - acc >= mem[j].l; /* Eq. 3, ">=" */
+                else
+                    accept = mem[j].r - acc > mem[j].l; /* Eq. 3 */
+                if (accept && disjoint) {
+                    /* closed intervals [i, i+l-1] must share no position */
+                    for (int32_t q = 0; q < nacc; ++q) {
+                        const mem_row *a = &mem[acc_lv[q]];
+                        int64_t a_end = a->i + a->l - 1, j_end = mem[j].i + mem[j].l - 1;
+                        if (!(j_end < a->i || a_end < mem[j].i))
+                            accept = 0;
+                    }
+                }
                 if (nev < cap) {
                     ev_pos[nev] = i;
                     ev_level[nev] = j;
@@ -272,9 +315,12 @@ int64_t oracle_filter(const int64_t *hs, const int32_t *hl, const int32_t *hk,
                     ev_acc_flag[nev] = accept;
                 }
                 ++nev;
-                if (accept)
-                    acc += mem[j].l;
+                if (accept) {
+                    acc = acc_last ? mem[j].l : acc + mem[j].l;
+                    acc_lv[nacc++] = j;
+                }
             }
+            free(acc_lv);
             idx = K;
             ins = 0;
             acc = 0;

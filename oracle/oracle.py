@@ -67,7 +67,7 @@ def _load():
             lib.oracle_hset_all.restype = i64
             lib.oracle_hset_at_ends.argtypes = [P, i32, P, i64, i32, P, i64, P, P, P, i64]
             lib.oracle_hset_at_ends.restype = i64
-            lib.oracle_filter.argtypes = [P, P, P, i64, i32, i64] + [P] * 7 + [i64]
+            lib.oracle_filter.argtypes = [P, P, P, i64, i32, i64, i32] + [P] * 7 + [i64]
             lib.oracle_filter.restype = i64
             _lib = lib
     return _lib
@@ -160,7 +160,16 @@ class FilterResult:
     events: np.ndarray
 
 
-def filter_hits(hs, hl, hk, K: int, n: int) -> FilterResult:
+# Alternative readings of Alg. 1 (bit values equal to the library's
+# OASM_RULES_* bits; see oracle_filter in oasm_oracle.c).
+RULES_PAPER = 1
+RULES_ACC_LAST = 2
+RULES_EQ3_GE = 4
+RULES_START_ORDER = 8
+RULES_DISJOINT = 16
+
+
+def filter_hits(hs, hl, hk, K: int, n: int, rules: int = RULES_PAPER) -> FilterResult:
     """Alg. 1 over H (any order; sorted here by (i, l)) for a text of n symbols."""
     hs = np.ascontiguousarray(hs, dtype=np.int64)
     hl = np.ascontiguousarray(hl, dtype=np.int32)
@@ -170,7 +179,8 @@ def filter_hits(hs, hl, hk, K: int, n: int) -> FilterResult:
     cap = max(16, hs.size * (K + 1) + 16)
     while True:
         cols = [np.empty(cap, dtype=dt) for dt in (np.int64, np.int32, np.int64, np.int32, np.int64, np.int64, np.int32)]
-        cnt = lib.oracle_filter(_ptr(hs), _ptr(hl), _ptr(hk), hs.size, K, n, *[_ptr(c) for c in cols], cap)
+        cnt = lib.oracle_filter(_ptr(hs), _ptr(hl), _ptr(hk), hs.size, K, n, int(rules), *[_ptr(c) for c in cols],
+                                cap)
         if cnt < 0:
             raise MemoryError("oracle_filter")
         if cnt <= cap:
@@ -191,18 +201,18 @@ class PairResult:
     occ: np.ndarray  # S rows (i, l, k) in emission order
 
 
-def run_pair(p, t, K: int, with_filter: bool = True) -> PairResult:
+def run_pair(p, t, K: int, with_filter: bool = True, rules: int = RULES_PAPER) -> PairResult:
     """Raw hits, H at the raw ends and S for one pattern on one text."""
     ends, dists = raw_hits(p, t, K)
     H = hset_at_ends(p, t, K, ends)
-    occ = filter_hits(*H, K, len(t)).occ if with_filter else None
+    occ = filter_hits(*H, K, len(t), rules).occ if with_filter else None
     return PairResult(ends, dists, H, occ)
 
 
-def run_pairs(patterns, ks, text, threads: int | None = None, with_filter: bool = True):
+def run_pairs(patterns, ks, text, threads: int | None = None, with_filter: bool = True, rules: int = RULES_PAPER):
     """run_pair over many patterns of one text, one thread per pattern task."""
     T = _u8(text)
     threads = threads or min(16, os.cpu_count() or 1)
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        futs = [ex.submit(run_pair, p, T, int(k), with_filter) for p, k in zip(patterns, ks)]
+        futs = [ex.submit(run_pair, p, T, int(k), with_filter, rules) for p, k in zip(patterns, ks)]
         return [f.result() for f in futs]
