@@ -57,7 +57,8 @@ def parse():
     ap.add_argument("--serving-budget", type=int, default=64 << 20, help="unmatched-byte budget")
     ap.add_argument("--serving-pool", type=int, default=1 << 26)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 256 MiB device copy three times (PMC traffic calibration)")
+                    help="first run a plain 256 MiB device copy three times and a one-tile scan of the "
+                         "first stream (PMC traffic calibration)")
     return ap.parse_args()
 
 
@@ -73,9 +74,23 @@ def copy_calibration():
     del src, dst
 
 
+def single_tile_calibration(oasm, torch, w):
+    """One scan launch that reads its text exactly once: the workload's first
+    64 patterns (one tile) over its first stream, one step.  Its FETCH_SIZE
+    per dispatch, against the stream's byte count, shows how the counter
+    scores the scan's own (scalar) loads, beside the copy kernel's factor."""
+    t = torch.from_numpy(w.streams[0]).cuda()
+    with oasm.Matcher(w.patterns[:64], w.ks[:64], autotune=False, graphs=False) as mt:
+        mt.feed(0, t, last=True)
+        mt.sync()
+        mt.results()
+    torch.cuda.synchronize()
+    del t
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("oasm_kernels.hip", "oasm_internal.h"):
+    for f in ("oasm_scan.hip", "oasm_device.h", "oasm_internal.h"):
         with open(os.path.join(ROOT, "paper_1712_03560_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -246,6 +261,8 @@ def main():
     if args.calibrate_copy:
         copy_calibration()
     w, desc = make_workload(args.workload, args)
+    if args.calibrate_copy:
+        single_tile_calibration(oasm, torch, w)
     r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk, autotune=not args.no_autotune,
                   graphs=not args.no_graphs)
     msum = sum(len(p) for p in w.patterns)

@@ -72,9 +72,26 @@ typedef int32_t oasm_status;
 #define OASM_E_CLOSED (-4) /* feed to a stream that was closed */
 #define OASM_E_DEVICE (-5) /* HIP error; the context is poisoned, only destroy is valid */
 
-/* Filtering rules. */
+/* Filtering rules.  OASM_RULES_NONE, or OASM_RULES_PAPER optionally OR-ed
+ * with variant bits that replace one reading of Alg. 1 each (Section 4):
+ *   ACC_LAST     Eq. 3 with acc = the length of the occurrence accepted last
+ *                in the emission (the wording around Eq. 3) instead of the sum
+ *                of the lengths accepted so far (Alg. 1's acc update);
+ *   EQ3_GE       Eq. 3 as r(k) - acc >= l(k): an occurrence that ends right
+ *                before the accepted block (adjacent, disjoint) is accepted;
+ *   START_ORDER  R2 literally in start order: an equal-priority hit replaces
+ *                the stored one only when its level is empty, so the first
+ *                hit examined (earliest start, then shortest) is kept;
+ *   DISJOINT     a lower-priority occurrence is accepted only if, besides
+ *                Eq. 3, it shares no position with any occurrence accepted
+ *                before it in the same emission.
+ * The bits combine freely. */
 #define OASM_RULES_NONE 0u  /* report hit ends (and the hit set) only */
 #define OASM_RULES_PAPER 1u /* Alg. 1 with R1-R3 and Eq. 3 as read above */
+#define OASM_RULES_ACC_LAST 2u
+#define OASM_RULES_EQ3_GE 4u
+#define OASM_RULES_START_ORDER 8u
+#define OASM_RULES_DISJOINT 16u
 
 /* Feed flags. */
 #define OASM_FEED_LAST 1u /* this feed ends the stream (as oasm_close_stream) */
@@ -175,9 +192,11 @@ oasm_status oasm_config_init(oasm_config *cfg);
 /*
  * Create a matching context for `n` patterns.  `k` gives one threshold per
  * pattern, or is NULL to use `k_all` for every pattern.  `rules` is
- * OASM_RULES_PAPER or OASM_RULES_NONE.  `cfg` may be NULL (defaults).
+ * OASM_RULES_NONE, or OASM_RULES_PAPER with any OASM_RULES_* variant bits.
+ * `cfg` may be NULL (defaults).
  * Errors: OASM_E_INVAL for n == 0, a NULL pattern, len == 0,
- * len > OASM_MAX_PATTERN_LEN or K >= len; OASM_E_NOMEM; OASM_E_DEVICE.
+ * len > OASM_MAX_PATTERN_LEN, K >= len, or unknown rule bits (variant bits
+ * without OASM_RULES_PAPER included); OASM_E_NOMEM; OASM_E_DEVICE.
  * On success *out receives the context; on error *out is set to NULL.
  */
 oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k, uint16_t k_all,

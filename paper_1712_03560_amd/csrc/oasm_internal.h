@@ -8,9 +8,14 @@
 namespace oasm {
 
 constexpr int kWave = 64;          // CDNA wavefront width
+constexpr uint32_t kXcds = 8;      // accelerator dies (each with its own L2)
 constexpr int kMaxW32 = 8;         // 32-bit words per pattern column (256 rows)
 constexpr int kMaxW64 = 4;         // 64-bit words per column in the recovery kernel
 constexpr uint8_t kNoHit = 0xFF;   // hit-set byte for "distance above K"
+
+// Filter rule bits (the values of the public OASM_RULES_* flags).
+constexpr uint32_t kRulePaper = 1, kRuleAccLast = 2, kRuleEq3Ge = 4, kRuleStartOrder = 8, kRuleDisjoint = 16;
+constexpr uint32_t kRuleAll = 31;
 
 // One scan work item's text: a run of class-mapped symbols of one stream.
 // The first `lookback` symbols only warm the column up (their ends belong to
@@ -110,7 +115,8 @@ struct SegCopy {
 hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *class_of, hipStream_t st);
 
 // K1: the bit-parallel scan for one word-count class (W words, P patterns
-// per lane).  Grid: (ceil(nchunks / waves_per_block), ntiles).
+// per lane).  Grid: ceil(nchunks / waves_per_block) rounded up to a multiple
+// of kXcds, times ntiles, in one dimension (XCD-aware block order).
 struct ScanArgs {
     const ChunkDesc *chunks;
     uint32_t nchunks;
@@ -155,9 +161,10 @@ hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uin
                           hipStream_t st);
 
 // K3: the filter, one thread per segment of a (stream, pattern) run.
+// `rules`: kRule* bits (0 = no filtering, only the open-segment flags).
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
                          DevN n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams,
-                         uint32_t do_filter, uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt,
+                         uint32_t rules, uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt,
                          uint32_t *carry_flag, hipStream_t st);
 
 // Gather the filter output into a dense array.
@@ -195,6 +202,10 @@ hipError_t launch_pack_results(const PackArgs &a, hipStream_t st);
 size_t scan_tmp_words(size_t cap);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, DevN n, uint32_t *total, uint32_t *tmp,
                                  hipStream_t st);
+
+// Fill nwords uint32 with symbol classes drawn uniformly from [0, nclass)
+// by splitmix64 of the byte index (the autotuner's synthetic text).
+hipError_t launch_fill_classes(uint32_t *p, size_t nwords, uint32_t nclass, uint64_t seed, hipStream_t st);
 
 // Fill n uint32 with a value (graph-safe replacement for a memset).
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);

@@ -354,7 +354,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     const uint64_t nitems = (uint64_t)nchunks * c->ntiles;
     const uint32_t hks = c->hks;
     const uint32_t out_stride = c->kmax + 1;
-    const uint32_t do_filter = c->rules == OASM_RULES_PAPER ? 1u : 0u;
+    const uint32_t rules = c->rules;
     uint32_t key_bits = 0;
     while (key_bits < 32 && ((uint64_t)1 << key_bits) < (uint64_t)pl.locals.size() * c->npat) ++key_bits;
     c->item_cnt.ensure(std::max<uint64_t>(1, nitems) * 4, st);
@@ -475,7 +475,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                               c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
                "recover");
             ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                             c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, do_filter, out_stride,
+                             c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, rules, out_stride,
                              c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
                "filter");
             ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
@@ -914,32 +914,17 @@ std::map<std::tuple<uint32_t, int, size_t, int>, TileChoice> g_tune_cache;
 
 // Measure every (patterns per lane, LDS or not) variant of every word-count
 // class on a synthetic stream of uniformly drawn symbol classes, and keep
-// the fastest per class.
+// the fastest per class.  Each trial is planned the way a large step is
+// (the chunk size from the same rule, so about as many work items), with
+// text enough for at least 16,384 of them: variants with fewer tiles are
+// then not starved of wavefronts.
 void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
     hipStream_t st = c->st;
-    const uint32_t chunk = 4096, nchunks = 2048;  // 8 MiB of text, 2048 work items per tile
-    const size_t nbytes = (size_t)chunk * nchunks;
-    std::vector<uint8_t> text(nbytes + kPad);
-    uint64_t x = 0x9E3779B97F4A7C15ull;
-    for (auto &b : text) {  // splitmix64 draws of symbol classes
-        x += 0x9E3779B97F4A7C15ull;
-        uint64_t z = x;
-        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-        b = (uint8_t)((z ^ (z >> 31)) % c->nclass);
-    }
+    const size_t max_bytes = size_t(32) << 20, min_bytes = size_t(4) << 20;
     DevBuf d_text, d_chunks;
-    d_text.ensure(text.size(), st);
-    ck(hipMemcpyAsync(d_text.p, text.data(), text.size(), hipMemcpyHostToDevice, st), "tune text");
-    std::vector<ChunkDesc> ch(nchunks);
-    for (uint32_t j = 0; j < nchunks; ++j) {
-        const uint64_t e0 = (uint64_t)j * chunk;
-        uint64_t s0 = e0 >= c->lookback ? e0 - c->lookback : 0;
-        s0 &= ~uint64_t(3);
-        ch[j] = ChunkDesc{d_text.as<uint8_t>() + s0, e0, (uint32_t)(e0 + chunk - s0), (uint32_t)(e0 - s0), 0, 0};
-    }
-    d_chunks.ensure(ch.size() * sizeof(ChunkDesc), st);
-    ck(hipMemcpyAsync(d_chunks.p, ch.data(), ch.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st), "tune chunks");
+    d_text.ensure(max_bytes + kPad, st);
+    ck(launch_fill_classes(d_text.as<uint32_t>(), (max_bytes + kPad) / 4, c->nclass, 0x9E3779B97F4A7C15ull, st),
+       "tune text");
     for (int W = 1; W <= kMaxW32; ++W) {
         const size_t nW = class_members(c, W).size();
         if (nW == 0) continue;
@@ -972,10 +957,24 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
             const ClassInfo *ci = nullptr;
             for (const ClassInfo &k : c->classes)
                 if (k.W == W) ci = &k;
-            const double ms = time_class(c, *ci, d_chunks.as<ChunkDesc>(), nchunks);
-            // time per pattern word per symbol: classes differ in tiles, not in work per tile
-            const double per = ms / ((double)nW * W);
-            std::snprintf(line, sizeof line, "W=%d P=%d lds=%d: %.3f ms\n", W, cd.P, (int)cd.lds, ms);
+            size_t nbytes = max_bytes / std::max<uint32_t>(1, ci->ntiles);
+            nbytes = std::max(min_bytes, nbytes) & ~size_t(0xFFFF);
+            const uint32_t C = choose_chunk(c, nbytes);
+            std::vector<ChunkDesc> ch;
+            for (uint64_t e0 = 0; e0 < nbytes; e0 += C) {
+                const uint64_t e1 = std::min<uint64_t>(nbytes, e0 + C);
+                uint64_t s0 = e0 >= c->lookback ? e0 - c->lookback : 0;
+                s0 &= ~uint64_t(3);
+                ch.push_back(ChunkDesc{d_text.as<uint8_t>() + s0, e0, (uint32_t)(e1 - s0), (uint32_t)(e0 - s0), 0, 0});
+            }
+            d_chunks.ensure(ch.size() * sizeof(ChunkDesc), st);
+            ck(hipMemcpyAsync(d_chunks.p, ch.data(), ch.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st),
+               "tune chunks");
+            const double ms = time_class(c, *ci, d_chunks.as<ChunkDesc>(), (uint32_t)ch.size());
+            // time per pattern word per text byte: trials differ in tiles and text
+            const double per = ms / ((double)nW * W * (double)nbytes);
+            std::snprintf(line, sizeof line, "W=%d P=%d lds=%d: %.3f ms for %.0f MiB (%.3f ps per word-step)\n", W,
+                          cd.P, (int)cd.lds, ms, nbytes / 1048576.0, per * 1e9);
             c->tune_log += line;
             if (per < (&cd == &cands[0] ? 1e30 : best * 0.97)) {
                 best = per;
@@ -1025,7 +1024,11 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         g_create_error = "empty dictionary";
         return OASM_E_INVAL;
     }
-    if (rules != OASM_RULES_NONE && rules != OASM_RULES_PAPER) {
+    static_assert(OASM_RULES_PAPER == kRulePaper && OASM_RULES_ACC_LAST == kRuleAccLast &&
+                      OASM_RULES_EQ3_GE == kRuleEq3Ge && OASM_RULES_START_ORDER == kRuleStartOrder &&
+                      OASM_RULES_DISJOINT == kRuleDisjoint,
+                  "rule bits");
+    if ((rules & ~kRuleAll) != 0 || (rules != OASM_RULES_NONE && !(rules & OASM_RULES_PAPER))) {
         g_create_error = "unknown rules";
         return OASM_E_INVAL;
     }

@@ -1,0 +1,287 @@
+// K1, the hot kernel of oasm_gpu for CDNA4 (gfx950): the bit-parallel scan
+// that finds every hit end, min over starts of lev(p, t[s..e]) <= K (Section
+// 5.1 "Less Naive"; column recurrence after Myers 1999), for a dictionary
+// tiled over wavefront lanes and many streams cut into chunks.
+//
+// Integer bit-vector work only; no matrix cores.
+#include "oasm_device.h"
+
+namespace oasm {
+
+// ------------------------------------------------------------------ K1
+// Truth-table operands of v_bitop3_b32: the result bit for inputs (a, b, c)
+// is bit (a*4 + b*2 + c) of the immediate.
+constexpr uint32_t TA = 0xF0, TB = 0xCC, TC = 0xAA;
+#define BITOP3(a, b, c, expr) __builtin_amdgcn_bitop3_b32((a), (b), (c), (uint32_t)((expr) & 0xFF))
+
+// (x << 1) | y as one v_lshl_or_b32 (register-only ALU instruction; the
+// compiler would otherwise split it to fuse the OR elsewhere and spend one
+// more instruction per word).
+__device__ __forceinline__ uint32_t shl1_or(uint32_t x, uint32_t y) {
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(r) : "v"(x), "v"(y));
+    return r;
+}
+
+// popcount(x) + acc as one v_bcnt_u32_b32 (register-only ALU instruction).
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+// One column step of the bit-parallel edit-distance recurrence for a
+// W-word column (search mode: a zero horizontal delta enters the first row).
+// pv: rows whose vertical delta is +1; cm: the complement of the rows whose
+// vertical delta is -1 (kept complemented because every use of it is inside
+// three-input logic, which absorbs the complement for free, and its
+// popcount then feeds the hit test without a NOT); eq: rows whose pattern
+// symbol equals the text symbol.  With mv = ~cm and u = (eq & pv) + pv
+// (carry through all W words) the horizontal deltas are
+//   ph = mv | ~(u | pv | eq),    mh = pv & (eq | ~u)
+// and, with ph2 / mh2 the deltas shifted one row down (across words),
+//   pv' = mh2 | ~(eq | mv | ph2),    mv' = ph2 & (eq | mv).
+// (Myers 1999 / Hyyro's formulation, rewritten for three-input logic: nine
+// VALU instructions per 32-bit word on gfx950.)
+template <int W>
+__device__ __forceinline__ void column_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
+    uint32_t ph[W], mh[W];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t x = eq[w] & pv[w];
+        uint32_t u;
+        if (W == 1) {
+            u = x + pv[w];
+        } else {
+            const uint64_t s = (uint64_t)x + pv[w] + carry;
+            u = (uint32_t)s;
+            carry = (uint32_t)(s >> 32);
+        }
+        const uint32_t o = u | pv[w] | eq[w];
+        ph[w] = BITOP3(cm[w], o, 0u, ~(TA & TB));           // ~cm | ~o
+        mh[w] = BITOP3(pv[w], eq[w], u, TA & (TB | ~TC));   // pv & (eq | ~u)
+    }
+    uint32_t npv[W], ncm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t ph2 = w == 0 ? ph[0] << 1 : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
+        const uint32_t t = BITOP3(eq[w], cm[w], ph2, ~(TA | ~TB | TC));  // ~(eq | ~cm | ph2)
+        npv[w] = w == 0 ? shl1_or(mh[0], t) : (__builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31) | t);
+        ncm[w] = BITOP3(ph2, eq[w], cm[w], ~(TA & (TB | ~TC)));        // ~(ph2 & (eq | ~cm))
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        pv[w] = npv[w];
+        cm[w] = ncm[w];
+    }
+}
+
+// Last-row value D = popcount(pv) - popcount(mv) (the column sum of the
+// vertical deltas; wildcard rows contribute 0) = popcount(pv) + popcount(cm)
+// - 32W.  With bias = -32W - bound - 1 the result's sign bit is set exactly
+// when D <= bound.
+template <int W>
+__device__ __forceinline__ int32_t le_bound(const uint32_t (&pv)[W], const uint32_t (&cm)[W], uint32_t bias) {
+    uint32_t d = bias;
+#pragma unroll
+    for (int w = 0; w < W; ++w) d = bcnt_acc(cm[w], d);
+#pragma unroll
+    for (int w = 0; w < W; ++w) d = bcnt_acc(pv[w], d);
+    return (int32_t)d;
+}
+
+// Per-lane row of a tile image: P*W words padded to a power of two so that
+// one aligned LDS (or global) vector read fetches it.
+template <int N>
+struct alignas(N * 4 < 16 ? N * 4 : 16) Words {
+    uint32_t v[N];
+};
+
+constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
+
+// K1.  Block = `waves` wavefronts sharing one tile (its match-mask image in
+// LDS, or read through the L1 when it does not fit); each wavefront scans
+// one chunk.  Lane l holds P patterns of W words (slots l, l+64, ...).
+// The text symbol is wave-uniform (scalar loads).  Hits are screened once per
+// group of 4 symbols: the last-row value moves by at most 1 per symbol, so
+// if D > K + 2 at the group's second symbol no symbol of the group is a hit.
+// Only when some lane passes the screen is the group replayed from its saved
+// start state with an exact test per symbol, and the hits are compacted with
+// a ballot and an mbcnt prefix into the item's own record buffer.
+//
+// The grid is one-dimensional and XCD-aware: workgroups are handed to the 8
+// XCDs round-robin (block b to XCD b % 8), so the ntiles blocks that scan the
+// same chunks with different tiles are given ids b, b + 8, ... on one XCD,
+// one after the other; the text they share is read from HBM once and then
+// hit in that XCD's L2.
+template <int W, int P, bool LDSPEQ>
+__global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) {
+    extern __shared__ uint32_t lds_img[];
+    constexpr int PW = P * W;
+    constexpr int PWS = pad_pow2(PW);
+    const uint32_t xcd = blockIdx.x & (kXcds - 1), r = blockIdx.x / kXcds;
+    const uint32_t tile_local = r % a.ntiles;
+    const uint32_t cblock = (r / a.ntiles) * kXcds + xcd;
+    if (cblock * (blockDim.x >> 6) >= a.nchunks) return;  // padding blocks (uniform per block)
+    const TileDesc td = a.tiles[a.tile_first + tile_local];
+    const uint32_t *gimg = a.peq_img + td.peq_off;
+    if (LDSPEQ) {
+        const uint32_t words = a.nclass * kWave * PWS;  // multiple of 64
+        const uint4 *src = reinterpret_cast<const uint4 *>(gimg);
+        uint4 *dst = reinterpret_cast<uint4 *>(lds_img);
+        for (uint32_t i = threadIdx.x; i < words / 4; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
+    const uint32_t lane = lane_id();
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    const uint32_t chunk = uniform(cblock * (blockDim.x >> 6) + wave);
+    if (chunk >= a.nchunks) return;
+    const ChunkDesc cd = a.chunks[chunk];
+    const uint32_t item = a.item_base + chunk * a.ntiles + tile_local;
+    uint32_t *rec = a.item_rec + (size_t)item * a.cap;
+
+    // Inactive slots hold all-ones +1 deltas (D = 32W) and bounds of 0, so
+    // they never pass the screen or the exact test.  kk / k2 hold the biases
+    // of le_bound for the exact test (D <= K) and the screen (D <= K + 2).
+    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P];
+    bool act[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const uint32_t slot = p * kWave + lane;
+        act[p] = slot < td.n_active;
+        pat[p] = act[p] ? a.slot_pat[td.slot_off + slot] : 0u;
+        const PatDesc d = a.pats[pat[p]];
+        kk[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k : 0u);
+        k2[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k + 2 : 0u);
+        const int g = 32 * W - (int)d.m;  // wildcard rows below the pattern
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            const int lo = g - 32 * w;  // first pattern bit inside word w
+            const uint32_t bits = lo <= 0 ? ~0u : (lo >= 32 ? 0u : (~0u << lo));
+            pv[p][w] = act[p] ? bits : ~0u;
+            mv[p][w] = ~0u;  // complemented: no -1 deltas
+        }
+    }
+    uint32_t cnt = 0;
+
+    const const_u32 *text = (const const_u32 *)(cd.sym);
+    const uint32_t len = cd.scan_len, lb = cd.lookback;
+    const uint32_t lane_off = lane * PWS;
+    const uint32_t *img = LDSPEQ ? lds_img : gimg;
+
+    uint32_t next = text[0];
+    for (uint32_t pos = 0; pos < len; pos += kScanGroup) {
+        const uint32_t cur = next;
+        next = text[(pos >> 2) + 1];
+        Words<PWS> e[kScanGroup];
+#pragma unroll
+        for (int s = 0; s < kScanGroup; ++s) {
+            const uint32_t c = (cur >> (8 * s)) & 0xFFu;
+            e[s] = *reinterpret_cast<const Words<PWS> *>(img + c * (kWave * PWS) + lane_off);
+        }
+        uint32_t pv0[P][W], mv0[P][W];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                pv0[p][w] = pv[p][w];
+                mv0[p][w] = mv[p][w];
+            }
+        int32_t screen[P];
+#pragma unroll
+        for (int s = 0; s < kScanGroup; ++s) {
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                column_step<W>(pv[p], mv[p], &e[s].v[p * W]);
+                if (s == 1) screen[p] = le_bound<W>(pv[p], mv[p], k2[p]);
+            }
+        }
+        uint64_t sb[P], any = 0;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            sb[p] = __ballot(screen[p] < 0);
+            any |= sb[p];
+        }
+        if (any && pos + (kScanGroup - 1) >= lb) {
+            // replay the pattern slots that passed the screen from the group's
+            // start state, with an exact test per symbol
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (!sb[p]) continue;
+#pragma unroll
+                for (int s = 0; s < kScanGroup; ++s) {
+                    const bool inrange = (pos + s >= lb) && (pos + s < len);
+                    column_step<W>(pv0[p], mv0[p], &e[s].v[p * W]);
+                    const uint64_t b = __ballot(le_bound<W>(pv0[p], mv0[p], kk[p]) < 0);
+                    if (inrange && b) {
+                        if ((b >> lane) & 1ull) {
+                            const uint32_t idx = cnt + mbcnt64(b);
+                            if (idx < a.cap) rec[idx] = ((p * kWave + lane) << 24) | (pos + s - lb);
+                        }
+                        cnt += (uint32_t)__popcll(b);
+                    }
+                }
+            }
+        }
+    }
+    if (lane == 0) {
+        a.item_cnt[item] = cnt;
+        atomicMax(a.max_cnt, cnt);
+    }
+}
+
+template <int W, int P>
+static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+    const uint32_t gx = (a.nchunks + waves - 1) / waves;
+    if (gx == 0 || a.ntiles == 0) return hipSuccess;
+    const uint64_t blocks = (uint64_t)((gx + kXcds - 1) / kXcds) * kXcds * a.ntiles;
+    if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
+    const size_t shmem = lds ? (size_t)a.nclass * kWave * pad_pow2(P * W) * 4 : 0;
+    if (lds) {
+        // raise the instance's dynamic-LDS limit once (never inside a graph
+        // capture: the first launch of a shape is always an eager one)
+        static size_t configured = 0;
+        if (shmem > configured) {
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+            if (e != hipSuccess) return e;
+            configured = shmem;
+        }
+        hipLaunchKernelGGL((k_scan<W, P, true>), dim3((uint32_t)blocks), dim3(waves * kWave), shmem, st, a);
+    } else {
+        hipLaunchKernelGGL((k_scan<W, P, false>), dim3((uint32_t)blocks), dim3(waves * kWave), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+bool scan_variant_exists(int W, int P) {
+    switch (W * 16 + P) {
+        case 1 * 16 + 1: case 1 * 16 + 2: case 1 * 16 + 4:
+        case 2 * 16 + 1: case 2 * 16 + 2:
+        case 3 * 16 + 1: case 4 * 16 + 1: case 5 * 16 + 1:
+        case 6 * 16 + 1: case 7 * 16 + 1: case 8 * 16 + 1:
+            return true;
+        default:
+            return false;
+    }
+}
+
+hipError_t launch_scan(int W, int P, const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+    switch (W * 16 + P) {
+        case 1 * 16 + 1: return launch_scan_t<1, 1>(a, waves, lds, st);
+        case 1 * 16 + 2: return launch_scan_t<1, 2>(a, waves, lds, st);
+        case 1 * 16 + 4: return launch_scan_t<1, 4>(a, waves, lds, st);
+        case 2 * 16 + 1: return launch_scan_t<2, 1>(a, waves, lds, st);
+        case 2 * 16 + 2: return launch_scan_t<2, 2>(a, waves, lds, st);
+        case 3 * 16 + 1: return launch_scan_t<3, 1>(a, waves, lds, st);
+        case 4 * 16 + 1: return launch_scan_t<4, 1>(a, waves, lds, st);
+        case 5 * 16 + 1: return launch_scan_t<5, 1>(a, waves, lds, st);
+        case 6 * 16 + 1: return launch_scan_t<6, 1>(a, waves, lds, st);
+        case 7 * 16 + 1: return launch_scan_t<7, 1>(a, waves, lds, st);
+        case 8 * 16 + 1: return launch_scan_t<8, 1>(a, waves, lds, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace oasm

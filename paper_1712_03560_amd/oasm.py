@@ -29,6 +29,10 @@ OASM_E_DEVICE = -5
 
 OASM_RULES_NONE = 0
 OASM_RULES_PAPER = 1
+OASM_RULES_ACC_LAST = 2
+OASM_RULES_EQ3_GE = 4
+OASM_RULES_START_ORDER = 8
+OASM_RULES_DISJOINT = 16
 OASM_FEED_LAST = 1
 OASM_CFG_PLAIN = 1
 OASM_CFG_KEEP_H = 2

@@ -102,7 +102,12 @@ def mixture_bytes(rng: np.random.Generator, n: int, mean_run: float = 40.0, bloc
         cum = np.cumsum(lens)
         k = int(np.searchsorted(cum, want)) + 1
         lens, kinds = lens[:k], kinds[:k]
-        kind_per_byte = np.repeat(kinds, lens)[:want]
+        # kind of every byte (np.repeat(kinds, lens)[:want], built as a
+        # running XOR of the kind changes at the run starts: much faster)
+        flips = np.zeros(want, dtype=np.uint8)
+        starts = cum[:k - 1]
+        flips[starts[starts < want]] = (kinds[1:] ^ kinds[:-1])[starts < want]
+        kind_per_byte = np.bitwise_xor.accumulate(flips) ^ kinds[0]
         rnd = rng.integers(0, 256, size=want, dtype=np.uint16).astype(np.uint8)
         prn = rng.integers(0x20, 0x7F, size=want, dtype=np.uint16).astype(np.uint8)
         out[pos:pos + want] = np.where(kind_per_byte == 1, prn, rnd)

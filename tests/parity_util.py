@@ -26,7 +26,7 @@ def group(rec: np.ndarray, keys=("stream", "pattern")):
     return out
 
 
-def oracle_pairs(streams: dict, patterns, ks, pairs=None, threads=None, with_filter=True):
+def oracle_pairs(streams: dict, patterns, ks, pairs=None, threads=None, with_filter=True, rules=1):
     """Oracle results for every (stream id, pattern index) pair (or the given ones)."""
     if pairs is None:
         pairs = [(sid, pi) for sid in streams for pi in range(len(patterns))]
@@ -34,15 +34,16 @@ def oracle_pairs(streams: dict, patterns, ks, pairs=None, threads=None, with_fil
 
     def one(pair):
         sid, pi = pair
-        return pair, oracle.run_pair(patterns[pi], streams[sid], int(ks[pi]), with_filter)
+        return pair, oracle.run_pair(patterns[pi], streams[sid], int(ks[pi]), with_filter, rules)
 
     with ThreadPoolExecutor(max_workers=threads) as ex:
         return dict(ex.map(one, pairs))
 
 
-def compare(res, streams: dict, patterns, ks, pairs=None, check_h=False, with_filter=True, label=""):
-    """Assert bit-exact agreement of hit ends, distances, H and S per pair."""
-    want = oracle_pairs(streams, patterns, ks, pairs, with_filter=with_filter)
+def compare(res, streams: dict, patterns, ks, pairs=None, check_h=False, with_filter=True, label="", rules=1):
+    """Assert bit-exact agreement of hit ends, distances, H and S per pair
+    (S under the given filter rules, the library's OASM_RULES_* bits)."""
+    want = oracle_pairs(streams, patterns, ks, pairs, with_filter=with_filter, rules=rules)
     raw = group(res.raw)
     occ = group(res.occ)
     hh = group(res.h) if check_h and res.h is not None else {}

@@ -157,6 +157,27 @@ def test_rules_none_reports_hits_only():
     compare(res, streams, w.patterns, w.ks, check_h=True, with_filter=False, label="rules-none")
 
 
+@pytest.mark.parametrize("rules", [
+    oasm.OASM_RULES_ACC_LAST, oasm.OASM_RULES_EQ3_GE, oasm.OASM_RULES_START_ORDER, oasm.OASM_RULES_DISJOINT,
+    oasm.OASM_RULES_ACC_LAST | oasm.OASM_RULES_DISJOINT,
+    oasm.OASM_RULES_ACC_LAST | oasm.OASM_RULES_EQ3_GE | oasm.OASM_RULES_START_ORDER | oasm.OASM_RULES_DISJOINT,
+])
+def test_rule_variants_match_oracle(rules):
+    """Alternative readings of Alg. 1: short patterns with K up to m - 1 on
+    low-entropy text, where emissions hold several priority levels and the
+    readings disagree; split feeds so open segments are carried."""
+    rules |= oasm.OASM_RULES_PAPER
+    w = W.small_random(70, 6000, 24, 4, 14, b"AB", kmax=None, n_plants=40, n_streams=3)
+    ks = [max(1, min(len(p) - 1, 1 + (i % 5))) for i, p in enumerate(w.patterns)]
+    streams = {i: s for i, s in enumerate(w.streams)}
+    say(f"rules {rules}")
+    res = run(w.patterns, ks, streams, rules=rules, pieces=rules)
+    compare(res, streams, w.patterns, ks, check_h=True, label=f"rules{rules}", rules=rules)
+    base = run(w.patterns, ks, streams)
+    assert not np.array_equal(np.sort(res.occ, order=list(res.occ.dtype.names)),
+                              np.sort(base.occ, order=list(base.occ.dtype.names))) or rules == 1
+
+
 def test_long_config_full_size_sampled_patterns():
     """The 64 MiB single-stream workload at full size, in the launch
     configuration the benchmark times; the oracle checks 6 of the 256
