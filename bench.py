@@ -279,6 +279,7 @@ def main():
     achieved = ops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else None
     peak = VALU_PEAK_OPS / 1e12
     traffic = traffic_from_profiles(args.workload)
+    cut = any(x.startswith("class ") and "cut=1" in x for x in r["tune"].splitlines())
     line = {
         "metric": "GCUPS (pattern x text cells/s), whole matching step, 1 MI355X",
         "value": round(gcups, 1),
@@ -298,7 +299,7 @@ def main():
                      "unit": "TOP/s", "frac": round(achieved / peak, 4) if achieved else None,
                      "traffic": traffic, "kernel": "k_scan", "scan_ms_per_step": round(scan_ms, 3),
                      "scan_launches_per_step": launches, "word_steps": word_steps,
-                     "ops_per_word_step": OPS_PER_WORD_STEP},
+                     "ops_per_word_step": OPS_PER_WORD_STEP, "word_cutoff": cut},
         "scan_gcups": round(cells / (scan_ms * 1e-3) / 1e9, 1) if scan_ms > 0 else None,
         "step_breakdown_ms": {
             "scan_kernel": round(scan_ms, 3),

@@ -102,6 +102,7 @@ typedef int32_t oasm_status;
 #define OASM_CFG_NO_RAW 4u /* do not queue hit ends for draining (they are still computed) */
 #define OASM_CFG_AUTOTUNE 8u /* time the scan variants of every pattern class at create and keep the fastest */
 #define OASM_CFG_GRAPHS 16u  /* capture a step's launches as HIP graphs when its shape repeats, and replay them */
+#define OASM_CFG_NO_CUTOFF 32u /* step every word of multi-word patterns (no word cutoff; same results) */
 
 /* Drain kinds. */
 #define OASM_RAW 0u      /* oasm_hit records: hit ends and their distance */
@@ -277,9 +278,11 @@ oasm_status oasm_get_stats(const oasm_ctx *ctx, oasm_stats *out);
  * the context's device work to finish. */
 void oasm_destroy(oasm_ctx *ctx);
 
-/* The autotuner's measurements and choices, one line per variant tried
- * ("W=<words> P=<patterns per lane> lds=<0|1>: <ms>"); empty without
- * OASM_CFG_AUTOTUNE or when every class came from the process-wide cache. */
+/* The scan variants in use and how they were chosen: one line per variant
+ * the autotuner timed ("W=<words> P=<patterns per lane> lds=<0|1>
+ * cut=<0|1>: <ms> ...", only with OASM_CFG_AUTOTUNE and for classes not
+ * already in the process-wide cache), then one line per word-count class
+ * ("class W=<words>: P=.. lds=.. cut=.. tiles=.."). */
 const char *oasm_tune_report(const oasm_ctx *ctx);
 
 /* Message for the last error on this context (never NULL). */

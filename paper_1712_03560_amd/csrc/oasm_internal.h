@@ -133,8 +133,10 @@ struct ScanArgs {
     uint32_t cap;
     uint32_t *max_cnt;       // atomic max of per-item counts
 };
-hipError_t launch_scan(int W, int P, const ScanArgs &a, int waves_per_block, bool peq_in_lds, hipStream_t st);
-bool scan_variant_exists(int W, int P);
+// `cut`: the word-cutoff variant (one pattern per lane, W >= 2).
+hipError_t launch_scan(int W, int P, bool cut, const ScanArgs &a, int waves_per_block, bool peq_in_lds,
+                       hipStream_t st);
+bool scan_variant_exists(int W, int P, bool cut);
 
 // Ordering of the step's hit ends: carried ends first, then the scan items'
 // records (key = stream_local * npat + pattern, val = own index, end), then a

@@ -115,6 +115,7 @@ struct ClassInfo {
     int W = 1, P = 1;
     uint32_t tile_first = 0, ntiles = 0;
     bool lds = true;
+    bool cut = false;  // word-cutoff scan variant
     int waves = 4;
 };
 
@@ -437,7 +438,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                 a.item_base = item_base;
                 a.cap = c->cap;
                 a.max_cnt = ctl + 0;
-                ck(launch_scan(ci.W, ci.P, a, ci.waves, ci.lds, st), "scan launch");
+                ck(launch_scan(ci.W, ci.P, ci.cut, a, ci.waves, ci.lds, st), "scan launch");
                 item_base += nchunks * ci.ntiles;
                 c->stats.scan_launches++;
             }
@@ -778,6 +779,7 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n) {
 struct TileChoice {
     int P = 1;         // patterns per lane
     bool lds = true;   // match-mask image in LDS (else read through L1/L2)
+    bool cut = false;  // word cutoff (P = 1, W >= 2)
 };
 
 uint32_t pad_pow2_host(uint32_t x) { return x <= 1 ? 1 : x <= 2 ? 2 : x <= 4 ? 4 : 8; }
@@ -786,23 +788,29 @@ uint64_t image_bytes(const oasm_ctx *c, int W, int P) {
     return (uint64_t)c->nclass * 64 * pad_pow2_host((uint32_t)(P * W)) * 4;
 }
 
+// The patterns of one word count, shortest first: neighbouring lanes then
+// have similar numbers of wildcard rows, and so similar cutoff depths.
 std::vector<uint32_t> class_members(const oasm_ctx *c, int W) {
     std::vector<uint32_t> ids;
     for (uint32_t i = 0; i < c->npat; ++i)
         if ((uint32_t)((c->m[i] + 31) / 32) == (uint32_t)W) ids.push_back(i);
+    std::stable_sort(ids.begin(), ids.end(), [c](uint32_t a, uint32_t b) { return c->m[a] < c->m[b]; });
     return ids;
 }
 
 // Heuristic without measurement: more patterns per lane for short patterns
-// when there are enough of them; the image in LDS when it leaves room for
-// two blocks per CU.
+// when there are enough of them; the word cutoff for multi-word patterns
+// (unless disabled); the image in LDS when it leaves room for two blocks per
+// CU.
 std::vector<TileChoice> default_choices(const oasm_ctx *c) {
     std::vector<TileChoice> ch(kMaxW32 + 1);
+    const bool cut_ok = !(c->cfg.flags & OASM_CFG_NO_CUTOFF);
     for (int W = 1; W <= kMaxW32; ++W) {
         const size_t n = class_members(c, W).size();
         int P = 1;
         if (W == 1) P = n > 128 ? 4 : (n > 64 ? 2 : 1);
-        if (W == 2) P = n > 64 ? 2 : 1;
+        ch[W].cut = cut_ok && W >= 2;
+        if (W == 2 && !ch[W].cut) P = n > 64 ? 2 : 1;
         ch[W].P = P;
         ch[W].lds = image_bytes(c, W, P) <= 64 * 1024;
     }
@@ -827,6 +835,7 @@ void build_tiles(oasm_ctx *c, const std::vector<TileChoice> &choice) {
         ci.P = P;
         ci.tile_first = (uint32_t)tiles.size();
         ci.lds = choice[W].lds && image_bytes(c, W, P) <= c->max_lds;
+        ci.cut = choice[W].cut && P == 1 && W >= 2;
         ci.waves = 4;
         const uint32_t per = 64u * P;
         for (size_t t0 = 0; t0 < ids.size(); t0 += per) {
@@ -898,7 +907,7 @@ double time_class(oasm_ctx *c, const ClassInfo &ci, const ChunkDesc *d_chunks, u
     double best = 1e30;
     for (int r = 0; r < 3; ++r) {
         ck(hipEventRecord(c->ev0, st), "event");
-        ck(launch_scan(ci.W, ci.P, a, ci.waves, ci.lds, st), "tune scan");
+        ck(launch_scan(ci.W, ci.P, ci.cut, a, ci.waves, ci.lds, st), "tune scan");
         ck(hipEventRecord(c->ev1, st), "event");
         wait_stream(c, "tune sync");
         float ms = 0;
@@ -928,7 +937,8 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
     for (int W = 1; W <= kMaxW32; ++W) {
         const size_t nW = class_members(c, W).size();
         if (nW == 0) continue;
-        const auto key = std::make_tuple(c->nclass, W, nW, (int)c->max_lds);
+        const bool cut_ok = !(c->cfg.flags & OASM_CFG_NO_CUTOFF);
+        const auto key = std::make_tuple(c->nclass, W, nW, (int)c->max_lds * 2 + (cut_ok ? 1 : 0));
         {
             std::lock_guard<std::mutex> g(g_tune_mu);
             auto it = g_tune_cache.find(key);
@@ -940,11 +950,14 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
         // the heuristic default first: another variant must beat it by 3 %
         std::vector<TileChoice> cands{choice[W]};
         for (int P : {1, 2, 4}) {
-            if (!scan_variant_exists(W, P) || (P > 1 && nW <= (size_t)64 * (P / 2))) continue;
-            for (bool lds : {false, true}) {
-                if (lds && image_bytes(c, W, P) > c->max_lds) continue;
-                if (P == choice[W].P && lds == choice[W].lds) continue;
-                cands.push_back(TileChoice{P, lds});
+            for (bool cut : {false, true}) {
+                if (cut && !cut_ok) continue;
+                if (!scan_variant_exists(W, P, cut) || (P > 1 && nW <= (size_t)64 * (P / 2))) continue;
+                for (bool lds : {false, true}) {
+                    if (lds && image_bytes(c, W, P) > c->max_lds) continue;
+                    if (P == choice[W].P && lds == choice[W].lds && cut == choice[W].cut) continue;
+                    cands.push_back(TileChoice{P, lds, cut});
+                }
             }
         }
         double best = 1e30;
@@ -973,8 +986,8 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
             const double ms = time_class(c, *ci, d_chunks.as<ChunkDesc>(), (uint32_t)ch.size());
             // time per pattern word per text byte: trials differ in tiles and text
             const double per = ms / ((double)nW * W * (double)nbytes);
-            std::snprintf(line, sizeof line, "W=%d P=%d lds=%d: %.3f ms for %.0f MiB (%.3f ps per word-step)\n", W,
-                          cd.P, (int)cd.lds, ms, nbytes / 1048576.0, per * 1e9);
+            std::snprintf(line, sizeof line, "W=%d P=%d lds=%d cut=%d: %.3f ms for %.0f MiB (%.3f ps per word-step)\n",
+                          W, cd.P, (int)cd.lds, (int)cd.cut, ms, nbytes / 1048576.0, per * 1e9);
             c->tune_log += line;
             if (per < (&cd == &cands[0] ? 1e30 : best * 0.97)) {
                 best = per;
@@ -1108,6 +1121,12 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         std::vector<TileChoice> choice = default_choices(c);
         if (c->cfg.flags & OASM_CFG_AUTOTUNE) autotune(c, choice);
         build_tiles(c, choice);
+        for (const ClassInfo &ci : c->classes) {
+            char line[128];
+            std::snprintf(line, sizeof line, "class W=%d: P=%d lds=%d cut=%d tiles=%u\n", ci.W, ci.P, (int)ci.lds,
+                          (int)ci.cut, ci.ntiles);
+            c->tune_log += line;
+        }
         ck(hipStreamSynchronize(st), "create sync");
     } catch (const HipFail &f) {
         g_create_error = std::string(f.what) + ": " + hipGetErrorString(f.e);

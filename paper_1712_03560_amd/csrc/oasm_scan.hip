@@ -43,15 +43,19 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
 //   pv' = mh2 | ~(eq | mv | ph2),    mv' = ph2 & (eq | mv).
 // (Myers 1999 / Hyyro's formulation, rewritten for three-input logic: nine
 // VALU instructions per 32-bit word on gfx950.)
-template <int W>
-__device__ __forceinline__ void column_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
-    uint32_t ph[W], mh[W];
+//
+// column_step_n<N> advances only the first N words of a W-word column (the
+// word cutoff below); column_step<W> advances all of them.
+template <int N, int W>
+__device__ __forceinline__ void column_step_n(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
+    static_assert(N >= 1 && N <= W, "words");
+    uint32_t ph[N], mh[N];
     uint32_t carry = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
+    for (int w = 0; w < N; ++w) {
         const uint32_t x = eq[w] & pv[w];
         uint32_t u;
-        if (W == 1) {
+        if (N == 1) {
             u = x + pv[w];
         } else {
             const uint64_t s = (uint64_t)x + pv[w] + carry;
@@ -62,19 +66,24 @@ __device__ __forceinline__ void column_step(uint32_t (&pv)[W], uint32_t (&cm)[W]
         ph[w] = BITOP3(cm[w], o, 0u, ~(TA & TB));           // ~cm | ~o
         mh[w] = BITOP3(pv[w], eq[w], u, TA & (TB | ~TC));   // pv & (eq | ~u)
     }
-    uint32_t npv[W], ncm[W];
+    uint32_t npv[N], ncm[N];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
+    for (int w = 0; w < N; ++w) {
         const uint32_t ph2 = w == 0 ? ph[0] << 1 : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
         const uint32_t t = BITOP3(eq[w], cm[w], ph2, ~(TA | ~TB | TC));  // ~(eq | ~cm | ph2)
         npv[w] = w == 0 ? shl1_or(mh[0], t) : (__builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31) | t);
         ncm[w] = BITOP3(ph2, eq[w], cm[w], ~(TA & (TB | ~TC)));        // ~(ph2 & (eq | ~cm))
     }
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
+    for (int w = 0; w < N; ++w) {
         pv[w] = npv[w];
         cm[w] = ncm[w];
     }
+}
+
+template <int W>
+__device__ __forceinline__ void column_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
+    column_step_n<W, W>(pv, cm, eq);
 }
 
 // Last-row value D = popcount(pv) - popcount(mv) (the column sum of the
@@ -100,6 +109,67 @@ struct alignas(N * 4 < 16 ? N * 4 : 16) Words {
 
 constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
 
+// ------------------------------------------------------------------ cutoff
+// Word cutoff for multi-word columns (Ukkonen's cutoff, kept per 32-row word
+// as in Myers' block-based algorithm, but decided once per group of 4
+// symbols).  Words 0..y are advanced; the words below y are left stale.
+// Invariant: every cell of the rows in words > y has a value > K.  Then
+// those cells can never matter for a value <= K (a cell <= K is reached
+// from a neighbour whose value is <= its own), and no hit can end while the
+// last word is inactive.
+//
+// Decision at the end of a group, from s_b, the value at the bottom row of
+// word b (a prefix sum of the vertical deltas):
+//   * word b+1 must be active if s_b <= K + 4: otherwise, since a value
+//     changes by at most 1 per symbol, s_b stays above K + 3 for the next 4
+//     symbols, and the first row of word b+1 (reached from row s_b's cell on
+//     the diagonal, or from above) cannot come down to K;
+//   * word b must stay active if s_b <= K + 31: the 31 rows above the bottom
+//     row of a word are at least s_b - 31, so otherwise all of them are > K.
+// The new y is the largest index either rule asks for, over every lane (the
+// whole wavefront steps the same words).  A word that becomes active again
+// is reset to +1 vertical deltas: values s_y + 1, s_y + 2, ..., which are
+// upper bounds of the true ones (a value grows by at most 1 per row), and
+// cells whose true value is > K may be overestimated without changing any
+// value <= K.  The screen and exact test then read the last row only while
+// every word is active.
+//
+// `kc` = -(K + 5) per lane: acc = kc + popcount of the vertical deltas of
+// words 0..b (counted as popc(pv) + popc(~mv)) makes s_b <= K + 4 exactly
+// acc < 32(b+1), and s_b <= K + 31 exactly acc < 32(b+1) + 27.
+template <int W, int N>
+__device__ __forceinline__ uint32_t cut_decide(const uint32_t (&pv)[W], const uint32_t (&cm)[W], uint32_t kc) {
+    uint32_t acc = kc, ynew = 0;
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+        acc = bcnt_acc(cm[b], acc);
+        acc = bcnt_acc(pv[b], acc);
+        if (__ballot((int32_t)acc < 32 * (b + 1))) {
+            ynew = b + 1;
+        } else if (__ballot((int32_t)acc < 32 * (b + 1) + 27)) {
+            ynew = ynew > (uint32_t)b ? ynew : (uint32_t)b;
+        }
+    }
+    return ynew < (uint32_t)(W - 1) ? ynew : (uint32_t)(W - 1);
+}
+
+// One group of 4 symbols with only words 0..N-1 active (N < W): partial
+// mask reads, N-word column steps, then the cutoff decision.
+template <int W, int N>
+__device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img,
+                                              uint32_t lane_off, uint32_t cur, uint32_t kc) {
+    constexpr int PWS = pad_pow2(W), NS = pad_pow2(N);
+    Words<NS> e[kScanGroup];
+#pragma unroll
+    for (int s = 0; s < kScanGroup; ++s) {
+        const uint32_t c = (cur >> (8 * s)) & 0xFFu;
+        e[s] = *reinterpret_cast<const Words<NS> *>(img + c * (kWave * PWS) + lane_off);
+    }
+#pragma unroll
+    for (int s = 0; s < kScanGroup; ++s) column_step_n<N, W>(pv, cm, e[s].v);
+    return cut_decide<W, N>(pv, cm, kc);
+}
+
 // K1.  Block = `waves` wavefronts sharing one tile (its match-mask image in
 // LDS, or read through the L1 when it does not fit); each wavefront scans
 // one chunk.  Lane l holds P patterns of W words (slots l, l+64, ...).
@@ -115,8 +185,11 @@ constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
 // same chunks with different tiles are given ids b, b + 8, ... on one XCD,
 // one after the other; the text they share is read from HBM once and then
 // hit in that XCD's L2.
-template <int W, int P, bool LDSPEQ>
-__global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) {
+//
+// CUT: the word cutoff described above (one pattern per lane, W >= 2).
+template <int W, int P, bool LDSPEQ, bool CUT>
+__global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) {
+    static_assert(!CUT || (P == 1 && W >= 2), "the cutoff is for one multi-word pattern per lane");
     extern __shared__ uint32_t lds_img[];
     constexpr int PW = P * W;
     constexpr int PWS = pad_pow2(PW);
@@ -144,7 +217,7 @@ __global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) 
     // Inactive slots hold all-ones +1 deltas (D = 32W) and bounds of 0, so
     // they never pass the screen or the exact test.  kk / k2 hold the biases
     // of le_bound for the exact test (D <= K) and the screen (D <= K + 2).
-    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P];
+    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P], kc = 0;
     bool act[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -154,6 +227,7 @@ __global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) 
         const PatDesc d = a.pats[pat[p]];
         kk[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k : 0u);
         k2[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k + 2 : 0u);
+        if (CUT) kc = (uint32_t)(-5) - (act[p] ? (uint32_t)d.k : 0u);
         const int g = 32 * W - (int)d.m;  // wildcard rows below the pattern
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -170,10 +244,39 @@ __global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) 
     const uint32_t lane_off = lane * PWS;
     const uint32_t *img = LDSPEQ ? lds_img : gimg;
 
+    uint32_t y = W - 1;  // last active word (CUT); every word starts active
     uint32_t next = text[0];
     for (uint32_t pos = 0; pos < len; pos += kScanGroup) {
         const uint32_t cur = next;
         next = text[(pos >> 2) + 1];
+        if (CUT && y < W - 1) {
+            uint32_t ynew = y;
+            switch (y) {  // wave-uniform
+#define OASM_CUT_CASE(n) \
+    case n:              \
+        if constexpr (n + 1 < W) ynew = cut_group<W, n + 1>(pv[0], mv[0], img, lane_off, cur, kc); \
+        break;
+                OASM_CUT_CASE(0)
+                OASM_CUT_CASE(1)
+                OASM_CUT_CASE(2)
+                OASM_CUT_CASE(3)
+                OASM_CUT_CASE(4)
+                OASM_CUT_CASE(5)
+                OASM_CUT_CASE(6)
+#undef OASM_CUT_CASE
+                default: break;
+            }
+            if (ynew > y) {  // reactivated words restart from +1 deltas
+#pragma unroll
+                for (int w = 1; w < W; ++w)
+                    if ((uint32_t)w > y && (uint32_t)w <= ynew) {
+                        pv[0][w] = ~0u;
+                        mv[0][w] = ~0u;
+                    }
+            }
+            y = ynew;
+            continue;
+        }
         Words<PWS> e[kScanGroup];
 #pragma unroll
         for (int s = 0; s < kScanGroup; ++s) {
@@ -224,6 +327,7 @@ __global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) 
                 }
             }
         }
+        if (CUT) y = cut_decide<W, W>(pv[0], mv[0], kc);
     }
     if (lane == 0) {
         a.item_cnt[item] = cnt;
@@ -231,7 +335,7 @@ __global__ void __launch_bounds__(256, (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) 
     }
 }
 
-template <int W, int P>
+template <int W, int P, bool CUT>
 static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStream_t st) {
     const uint32_t gx = (a.nchunks + waves - 1) / waves;
     if (gx == 0 || a.ntiles == 0) return hipSuccess;
@@ -243,19 +347,20 @@ static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStrea
         // capture: the first launch of a shape is always an eager one)
         static size_t configured = 0;
         if (shmem > configured) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true>),
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true, CUT>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
             if (e != hipSuccess) return e;
             configured = shmem;
         }
-        hipLaunchKernelGGL((k_scan<W, P, true>), dim3((uint32_t)blocks), dim3(waves * kWave), shmem, st, a);
+        hipLaunchKernelGGL((k_scan<W, P, true, CUT>), dim3((uint32_t)blocks), dim3(waves * kWave), shmem, st, a);
     } else {
-        hipLaunchKernelGGL((k_scan<W, P, false>), dim3((uint32_t)blocks), dim3(waves * kWave), 0, st, a);
+        hipLaunchKernelGGL((k_scan<W, P, false, CUT>), dim3((uint32_t)blocks), dim3(waves * kWave), 0, st, a);
     }
     return hipGetLastError();
 }
 
-bool scan_variant_exists(int W, int P) {
+bool scan_variant_exists(int W, int P, bool cut) {
+    if (cut) return P == 1 && W >= 2 && W <= kMaxW32;
     switch (W * 16 + P) {
         case 1 * 16 + 1: case 1 * 16 + 2: case 1 * 16 + 4:
         case 2 * 16 + 1: case 2 * 16 + 2:
@@ -267,19 +372,32 @@ bool scan_variant_exists(int W, int P) {
     }
 }
 
-hipError_t launch_scan(int W, int P, const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+hipError_t launch_scan(int W, int P, bool cut, const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+    if (cut) {
+        if (P != 1) return hipErrorInvalidValue;
+        switch (W) {
+            case 2: return launch_scan_t<2, 1, true>(a, waves, lds, st);
+            case 3: return launch_scan_t<3, 1, true>(a, waves, lds, st);
+            case 4: return launch_scan_t<4, 1, true>(a, waves, lds, st);
+            case 5: return launch_scan_t<5, 1, true>(a, waves, lds, st);
+            case 6: return launch_scan_t<6, 1, true>(a, waves, lds, st);
+            case 7: return launch_scan_t<7, 1, true>(a, waves, lds, st);
+            case 8: return launch_scan_t<8, 1, true>(a, waves, lds, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (W * 16 + P) {
-        case 1 * 16 + 1: return launch_scan_t<1, 1>(a, waves, lds, st);
-        case 1 * 16 + 2: return launch_scan_t<1, 2>(a, waves, lds, st);
-        case 1 * 16 + 4: return launch_scan_t<1, 4>(a, waves, lds, st);
-        case 2 * 16 + 1: return launch_scan_t<2, 1>(a, waves, lds, st);
-        case 2 * 16 + 2: return launch_scan_t<2, 2>(a, waves, lds, st);
-        case 3 * 16 + 1: return launch_scan_t<3, 1>(a, waves, lds, st);
-        case 4 * 16 + 1: return launch_scan_t<4, 1>(a, waves, lds, st);
-        case 5 * 16 + 1: return launch_scan_t<5, 1>(a, waves, lds, st);
-        case 6 * 16 + 1: return launch_scan_t<6, 1>(a, waves, lds, st);
-        case 7 * 16 + 1: return launch_scan_t<7, 1>(a, waves, lds, st);
-        case 8 * 16 + 1: return launch_scan_t<8, 1>(a, waves, lds, st);
+        case 1 * 16 + 1: return launch_scan_t<1, 1, false>(a, waves, lds, st);
+        case 1 * 16 + 2: return launch_scan_t<1, 2, false>(a, waves, lds, st);
+        case 1 * 16 + 4: return launch_scan_t<1, 4, false>(a, waves, lds, st);
+        case 2 * 16 + 1: return launch_scan_t<2, 1, false>(a, waves, lds, st);
+        case 2 * 16 + 2: return launch_scan_t<2, 2, false>(a, waves, lds, st);
+        case 3 * 16 + 1: return launch_scan_t<3, 1, false>(a, waves, lds, st);
+        case 4 * 16 + 1: return launch_scan_t<4, 1, false>(a, waves, lds, st);
+        case 5 * 16 + 1: return launch_scan_t<5, 1, false>(a, waves, lds, st);
+        case 6 * 16 + 1: return launch_scan_t<6, 1, false>(a, waves, lds, st);
+        case 7 * 16 + 1: return launch_scan_t<7, 1, false>(a, waves, lds, st);
+        case 8 * 16 + 1: return launch_scan_t<8, 1, false>(a, waves, lds, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -39,6 +39,7 @@ OASM_CFG_KEEP_H = 2
 OASM_CFG_NO_RAW = 4
 OASM_CFG_AUTOTUNE = 8
 OASM_CFG_GRAPHS = 16
+OASM_CFG_NO_CUTOFF = 32
 OASM_RAW = 0
 OASM_FILTERED = 1
 OASM_H = 2
@@ -270,13 +271,13 @@ class Matcher:
 
     def __init__(self, patterns, k, rules: int = OASM_RULES_PAPER, *, plain: bool = False, keep_h: bool = False,
                  no_raw: bool = False, chunk_bytes: int = 0, hip_stream: int | None = None, device: int = -1,
-                 mem_budget: int = 0, autotune: bool = False, graphs: bool = False):
+                 mem_budget: int = 0, autotune: bool = False, graphs: bool = False, cutoff: bool = True):
         cfg = oasm_config_init()
         cfg.device = device
         cfg.chunk_bytes = chunk_bytes
         cfg.flags = (OASM_CFG_PLAIN if plain else 0) | (OASM_CFG_KEEP_H if keep_h else 0) | (
             OASM_CFG_NO_RAW if no_raw else 0) | (OASM_CFG_AUTOTUNE if autotune else 0) | (
-            OASM_CFG_GRAPHS if graphs else 0)
+            OASM_CFG_GRAPHS if graphs else 0) | (0 if cutoff else OASM_CFG_NO_CUTOFF)
         cfg.device_mem_budget = mem_budget
         cfg.hip_stream = hip_stream
         self.keep_h = keep_h

@@ -25,10 +25,10 @@ def say(msg):
 
 
 def run(patterns, ks, streams: dict, *, keep_h=True, plain=False, chunk_bytes=0, pieces=None, device=False,
-        rules=oasm.OASM_RULES_PAPER, autotune=False):
+        rules=oasm.OASM_RULES_PAPER, autotune=False, cutoff=True):
     """Feed every stream (optionally in pieces with syncs between), close, sync, drain."""
     with oasm.Matcher(patterns, ks, rules, keep_h=keep_h, plain=plain, chunk_bytes=chunk_bytes,
-                      autotune=autotune) as mt:
+                      autotune=autotune, cutoff=cutoff) as mt:
         if pieces is None:
             for sid, t in streams.items():
                 mt.feed(sid, torch.from_numpy(t).cuda() if device and t.size else t)
@@ -71,6 +71,21 @@ def test_random_dictionaries(seed, mlo, mhi, alphabet, kmax):
     say(f"random seed {seed}: m in [{mlo},{mhi}], |alphabet|={len(alphabet)}")
     res = run(w.patterns, w.ks, streams)
     compare(res, streams, w.patterns, w.ks, check_h=True, label=f"random{seed}")
+
+
+@pytest.mark.parametrize("seed,alphabet,kmax", [(80, b"AB", 40), (81, b"ACGT", 30), (82, bytes(range(32, 127)), 25)])
+def test_word_cutoff_matches_full_columns_and_oracle(seed, alphabet, kmax):
+    """Multi-word patterns (33..256 symbols) with thresholds up to 40 on text
+    with planted copies: the word cutoff (the default) and full columns give
+    the same results, equal to the oracle's."""
+    w = W.small_random(seed, 12000, 48, 33, 256, alphabet, kmax=kmax, n_plants=60, n_streams=2)
+    streams = {i: s for i, s in enumerate(w.streams)}
+    say(f"cutoff seed {seed}")
+    a = run(w.patterns, w.ks, streams)
+    b = run(w.patterns, w.ks, streams, cutoff=False)
+    for x, y in ((a.raw, b.raw), (a.occ, b.occ), (a.h, b.h)):
+        assert np.array_equal(np.sort(x, order=list(x.dtype.names)), np.sort(y, order=list(y.dtype.names)))
+    compare(a, streams, w.patterns, w.ks, check_h=True, label=f"cutoff{seed}")
 
 
 @pytest.mark.parametrize("m", [31, 32, 33, 63, 64, 65, 127, 128, 129, 192, 193, 255, 256])
