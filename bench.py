@@ -106,7 +106,8 @@ def traffic_from_profiles(workload: str):
         d = json.load(fh)
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    one = d.get("one_tile_scan") or {}
+    return d.get("hbm_bytes_per_launch"), one.get("full_launch_fetch_over_one_tile_fetch")
 
 
 def make_workload(name: str, args):
@@ -278,7 +279,7 @@ def main():
     ops = word_steps * OPS_PER_WORD_STEP
     achieved = ops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else None
     peak = VALU_PEAK_OPS / 1e12
-    traffic = traffic_from_profiles(args.workload)
+    traffic, vs_one_tile = traffic_from_profiles(args.workload) or (None, None)
     cut = any(x.startswith("class ") and "cut=1" in x for x in r["tune"].splitlines())
     line = {
         "metric": "GCUPS (pattern x text cells/s), whole matching step, 1 MI355X",
@@ -299,7 +300,10 @@ def main():
                      "unit": "TOP/s", "frac": round(achieved / peak, 4) if achieved else None,
                      "traffic": traffic, "kernel": "k_scan", "scan_ms_per_step": round(scan_ms, 3),
                      "scan_launches_per_step": launches, "word_steps": word_steps,
-                     "ops_per_word_step": OPS_PER_WORD_STEP, "word_cutoff": cut},
+                     "ops_per_word_step": OPS_PER_WORD_STEP, "word_cutoff": cut,
+                     # FETCH_SIZE of the launch over that of a one-tile scan of
+                     # the same text (which reads it exactly once)
+                     "fetch_vs_one_tile_scan": round(vs_one_tile, 3) if vs_one_tile else None},
         "scan_gcups": round(cells / (scan_ms * 1e-3) / 1e9, 1) if scan_ms > 0 else None,
         "step_breakdown_ms": {
             "scan_kernel": round(scan_ms, 3),

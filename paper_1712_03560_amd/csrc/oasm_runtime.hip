@@ -881,8 +881,8 @@ void build_tiles(oasm_ctx *c, const std::vector<TileChoice> &choice) {
 }
 
 // Device time of one scan launch of class `ci` over `nchunks` chunks of a
-// synthetic stream (min of three launches).
-double time_class(oasm_ctx *c, const ClassInfo &ci, const ChunkDesc *d_chunks, uint32_t nchunks) {
+// synthetic stream (min of `reps` launches).
+double time_class(oasm_ctx *c, const ClassInfo &ci, const ChunkDesc *d_chunks, uint32_t nchunks, int reps) {
     hipStream_t st = c->st;
     const uint64_t nitems = (uint64_t)nchunks * ci.ntiles;
     const uint32_t cap = 64;
@@ -905,7 +905,7 @@ double time_class(oasm_ctx *c, const ClassInfo &ci, const ChunkDesc *d_chunks, u
     a.cap = cap;
     a.max_cnt = c->ctl.as<uint32_t>();
     double best = 1e30;
-    for (int r = 0; r < 3; ++r) {
+    for (int r = 0; r < reps; ++r) {
         ck(hipEventRecord(c->ev0, st), "event");
         ck(launch_scan(ci.W, ci.P, ci.cut, a, ci.waves, ci.lds, st), "tune scan");
         ck(hipEventRecord(c->ev1, st), "event");
@@ -960,36 +960,49 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
                 }
             }
         }
+        // three rounds over all candidates (interleaved, so that clock and
+        // thermal drift during tuning does not favour any one), min per
+        // candidate; the first round's first launch of each is a warm-up
+        std::vector<double> best_ms(cands.size(), 1e30);
+        std::vector<size_t> nbytes_of(cands.size(), 0);
+        for (int round = 0; round < 3; ++round) {
+            for (size_t q = 0; q < cands.size(); ++q) {
+                std::vector<TileChoice> trial = choice;
+                trial[W] = cands[q];
+                build_tiles(c, trial);
+                const ClassInfo *ci = nullptr;
+                for (const ClassInfo &k : c->classes)
+                    if (k.W == W) ci = &k;
+                size_t nbytes = max_bytes / std::max<uint32_t>(1, ci->ntiles);
+                nbytes = std::max(min_bytes, nbytes) & ~size_t(0xFFFF);
+                nbytes_of[q] = nbytes;
+                const uint32_t C = choose_chunk(c, nbytes);
+                std::vector<ChunkDesc> ch;
+                for (uint64_t e0 = 0; e0 < nbytes; e0 += C) {
+                    const uint64_t e1 = std::min<uint64_t>(nbytes, e0 + C);
+                    uint64_t s0 = e0 >= c->lookback ? e0 - c->lookback : 0;
+                    s0 &= ~uint64_t(3);
+                    ch.push_back(
+                        ChunkDesc{d_text.as<uint8_t>() + s0, e0, (uint32_t)(e1 - s0), (uint32_t)(e0 - s0), 0, 0});
+                }
+                d_chunks.ensure(ch.size() * sizeof(ChunkDesc), st);
+                ck(hipMemcpyAsync(d_chunks.p, ch.data(), ch.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st),
+                   "tune chunks");
+                const double ms = time_class(c, *ci, d_chunks.as<ChunkDesc>(), (uint32_t)ch.size(), round ? 1 : 2);
+                best_ms[q] = std::min(best_ms[q], ms);
+            }
+        }
         double best = 1e30;
         TileChoice pick = choice[W];
         char line[160];
-        for (const TileChoice &cd : cands) {
-            std::vector<TileChoice> trial = choice;
-            trial[W] = cd;
-            build_tiles(c, trial);
-            const ClassInfo *ci = nullptr;
-            for (const ClassInfo &k : c->classes)
-                if (k.W == W) ci = &k;
-            size_t nbytes = max_bytes / std::max<uint32_t>(1, ci->ntiles);
-            nbytes = std::max(min_bytes, nbytes) & ~size_t(0xFFFF);
-            const uint32_t C = choose_chunk(c, nbytes);
-            std::vector<ChunkDesc> ch;
-            for (uint64_t e0 = 0; e0 < nbytes; e0 += C) {
-                const uint64_t e1 = std::min<uint64_t>(nbytes, e0 + C);
-                uint64_t s0 = e0 >= c->lookback ? e0 - c->lookback : 0;
-                s0 &= ~uint64_t(3);
-                ch.push_back(ChunkDesc{d_text.as<uint8_t>() + s0, e0, (uint32_t)(e1 - s0), (uint32_t)(e0 - s0), 0, 0});
-            }
-            d_chunks.ensure(ch.size() * sizeof(ChunkDesc), st);
-            ck(hipMemcpyAsync(d_chunks.p, ch.data(), ch.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st),
-               "tune chunks");
-            const double ms = time_class(c, *ci, d_chunks.as<ChunkDesc>(), (uint32_t)ch.size());
+        for (size_t q = 0; q < cands.size(); ++q) {
+            const TileChoice &cd = cands[q];
             // time per pattern word per text byte: trials differ in tiles and text
-            const double per = ms / ((double)nW * W * (double)nbytes);
+            const double per = best_ms[q] / ((double)nW * W * (double)nbytes_of[q]);
             std::snprintf(line, sizeof line, "W=%d P=%d lds=%d cut=%d: %.3f ms for %.0f MiB (%.3f ps per word-step)\n",
-                          W, cd.P, (int)cd.lds, (int)cd.cut, ms, nbytes / 1048576.0, per * 1e9);
+                          W, cd.P, (int)cd.lds, (int)cd.cut, best_ms[q], nbytes_of[q] / 1048576.0, per * 1e9);
             c->tune_log += line;
-            if (per < (&cd == &cands[0] ? 1e30 : best * 0.97)) {
+            if (per < (q == 0 ? 1e30 : best * 0.97)) {
                 best = per;
                 pick = cd;
             }
