@@ -1,14 +1,22 @@
 """Benchmark of the OASM matching path on one MI355X.
 
-One step = the whole hot path over one batch of synthetic input: ingest of a
-device-resident 64 MiB text (symbol mapping), the bit-parallel scan for 256
-patterns, ordering of the hit ends, hit-set recovery, the shadow-hit filter,
-and the copy-back of hit ends and occurrences.  Throughput is reported in
-GCUPS (pattern x text cells per second, cells = sum of pattern lengths x text
-bytes) over the whole step; the scan kernel's share is measured with HIP
-events on the library's stream and set against the integer-VALU roofline.
+One step = the whole hot path over one batch of synthetic input: ingest of
+device-resident streams (symbol mapping), the bit-parallel scan for every
+(stream, pattern) pair, ordering of the hit ends, hit-set recovery, the
+shadow-hit filter, and the delivery of hit ends and occurrences to the host.
+Throughput is reported in GCUPS (pattern x text cells per second, cells = sum
+of pattern lengths x text bytes) over the whole step; the scan kernel's share
+is measured with HIP events on the library's stream and set against the
+integer-VALU roofline.
 
-    python bench.py [--steps K] [--warmup W] [--workload long|batched|tiny]
+The headline workload is the many-stream one (4096 streams of 1 KiB - 1 MiB,
+602 MiB, 1024 patterns): all streams in one batched step, compared with one
+launch sequence per stream on the same kernels (`vs_plain`).  The same line
+carries the single 64 MiB stream (`long_stream`), the serving loop's p50/p99
+segment latency (`serving`, `p99_chunk_latency_ms`) and the oracle timed on a
+sample of the headline workload (`cpu_baseline`).
+
+    python bench.py [--steps K] [--warmup W] [--workload batched|long|multiword|tiny]
 """
 from __future__ import annotations
 
@@ -24,6 +32,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "GCUPS (pattern×text cells/s) batched vs plain, 1 MI355X; p99 chunk latency"
 # MI355X: 256 CUs x 4 SIMD x 16 lanes, 2.4 GHz -> int32 VALU lane-ops per second
 VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # Algorithmic int32 VALU work per 32-bit column word per text symbol: the
@@ -32,7 +41,6 @@ VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # vertical deltas).  Hit screening, addressing and replays are overhead and
 # show up as a lower roofline fraction.
 OPS_PER_WORD_STEP = 9
-HBM_PEAK_GBPS = 8000.0
 
 
 def parse():
@@ -40,13 +48,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="long", choices=["long", "batched", "tiny", "multiword"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "long", "tiny", "multiword"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--chunk", type=int, default=0, help="chunk bytes (0 = library default)")
     ap.add_argument("--batched-streams", type=int, default=4096)
     ap.add_argument("--multiword-bytes", type=int, default=1 << 26)
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--plain-steps", type=int, default=2, help="timed steps of the per-stream comparison")
+    ap.add_argument("--no-plain", action="store_true", help="skip the per-stream launch comparison")
+    ap.add_argument("--no-long", action="store_true", help="skip the single-stream leg")
     ap.add_argument("--no-autotune", action="store_true", help="heuristic scan variants instead of measured ones")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel of a step instead of graph replay")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
@@ -58,7 +68,7 @@ def parse():
     ap.add_argument("--serving-pool", type=int, default=1 << 26)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times and a one-tile scan of the "
-                         "first stream (PMC traffic calibration)")
+                         "workload's text (PMC traffic calibration)")
     return ap.parse_args()
 
 
@@ -75,17 +85,19 @@ def copy_calibration():
 
 
 def single_tile_calibration(oasm, torch, w):
-    """One scan launch that reads its text exactly once: the workload's first
-    64 patterns (one tile) over its first stream, one step.  Its FETCH_SIZE
-    per dispatch, against the stream's byte count, shows how the counter
-    scores the scan's own (scalar) loads, beside the copy kernel's factor."""
-    t = torch.from_numpy(w.streams[0]).cuda()
-    with oasm.Matcher(w.patterns[:64], w.ks[:64], autotune=False, graphs=False) as mt:
-        mt.feed(0, t, last=True)
+    """One scan launch that reads its text exactly once: 64 one-word patterns
+    of the workload (one tile) over all of its streams, one step.  Its
+    FETCH_SIZE per dispatch, against the text's byte count, shows how the
+    counter scores the scan's own (scalar) loads, beside the copy kernel's
+    factor."""
+    idx = [i for i, p in enumerate(w.patterns) if len(p) <= 32][:64]
+    dev = [torch.from_numpy(t).cuda() for t in w.streams]
+    with oasm.Matcher([w.patterns[i] for i in idx], [w.ks[i] for i in idx], autotune=False, graphs=False) as mt:
+        mt.feed_many([(i, t, True) for i, t in enumerate(dev)])
         mt.sync()
         mt.results()
     torch.cuda.synchronize()
-    del t
+    del dev
 
 
 def kernel_source_hash() -> str:
@@ -98,54 +110,91 @@ def kernel_source_hash() -> str:
 
 def traffic_from_profiles(workload: str):
     """HBM bytes per scan launch from committed rocprofv3 PMC summaries, if
-    they were taken with the current kernel source."""
+    they were taken with the current kernel source; and the launch's fetch
+    over a one-tile scan's of the same text."""
     path = os.path.join(ROOT, "profiles", f"scan_{workload}_traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     with open(path) as fh:
         d = json.load(fh)
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
-        return None
+        return None, None
     one = d.get("one_tile_scan") or {}
     return d.get("hbm_bytes_per_launch"), one.get("full_launch_fetch_over_one_tile_fetch")
+
+
+WORKLOADS = {
+    "long": "long-stream: one 64 MiB ACGT text, 256 patterns m~U[16,32], K=3, 10,000 planted copies",
+    "tiny": "tiny: 100,000 ACGT symbols, 16 patterns m~U[8,16], K=2, 200 planted copies",
+}
 
 
 def make_workload(name: str, args):
     from paper_1712_03560_amd import workloads as W
 
     if name == "long":
-        return W.long_stream(), "long-stream: one 64 MiB ACGT text, 256 patterns m~U[16,32], K=3, 10,000 planted copies"
+        return W.long_stream(), WORKLOADS["long"]
     if name == "tiny":
-        return W.tiny(), "tiny: 100,000 ACGT symbols, 16 patterns m~U[8,16], K=2, 200 planted copies"
+        return W.tiny(), WORKLOADS["tiny"]
     if name == "multiword":
         w = W.multiword(n=args.multiword_bytes)
         return w, (f"multiword: one {args.multiword_bytes >> 20} MiB stream of mixture bytes (uniform / printable "
                    f"runs, mean 40), 4096 patterns m~U[16,256], K=floor(m/10), planted copies over 0.1 % of bytes")
     w = W.batched(n_streams=args.batched_streams)
-    return w, (f"batched: {len(w.streams)} streams log-uniform in [1 KiB, 1 MiB], Zipf(1.1) 20 letters, "
-               f"1024 patterns m~U[8,64], K=floor(m/10)")
+    return w, (f"batched: {len(w.streams)} streams log-uniform in [1 KiB, 1 MiB] ({w.total_bytes} bytes), "
+               f"Zipf(1.1) 20 letters, 1024 patterns m~U[8,64], K=floor(m/10), one batched step")
 
 
 def cpu_baseline(w, target_s: float):
-    """The oracle (C, one thread per pattern) on a bounded prefix of the workload."""
+    """The oracle (C; raw hits, hit set and filter per (stream, pattern) pair,
+    16 threads over the pairs) on a bounded sample of the workload: a prefix
+    of a single stream, or a seeded subset of the streams with every pattern,
+    sized to about `target_s` seconds from a probe."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import oracle
 
     threads = min(16, os.cpu_count() or 1)
-    text = w.streams[0] if len(w.streams) == 1 else np.concatenate(w.streams[:64])
     msum = sum(len(p) for p in w.patterns)
-    # calibrate on a small prefix, then size the sample to ~target_s
-    probe = min(text.size, 1 << 18)
-    t0 = time.perf_counter()
-    oracle.run_pairs(w.patterns, w.ks, text[:probe], threads=threads)
-    dt = max(time.perf_counter() - t0, 1e-3)
-    nbytes = int(min(text.size, max(probe, probe * target_s / dt)))
-    t0 = time.perf_counter()
-    oracle.run_pairs(w.patterns, w.ks, text[:nbytes], threads=threads)
-    dt = time.perf_counter() - t0
-    cells = msum * nbytes
-    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": threads, "kind": "oracle",
-            "sample": f"first {nbytes} bytes of the stream x all {len(w.patterns)} patterns "
-                      f"(hit ends, hit set and filter), {dt:.1f} s"}
+
+    def run(streams):
+        jobs = [(t, i) for t in streams for i in range(len(w.patterns))]
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(lambda j: oracle.run_pair(w.patterns[j[1]], j[0], int(w.ks[j[1]])), jobs))
+
+    if len(w.streams) == 1:
+        text = w.streams[0]
+        probe = min(text.size, 1 << 18)
+        t0 = time.perf_counter()
+        run([text[:probe]])
+        dt = max(time.perf_counter() - t0, 1e-3)
+        nbytes = int(min(text.size, max(probe, probe * target_s / dt)))
+        t0 = time.perf_counter()
+        run([text[:nbytes]])
+        dt = time.perf_counter() - t0
+        what = f"first {nbytes} bytes of the stream x all {len(w.patterns)} patterns"
+    else:
+        order = np.random.default_rng(12).permutation(len(w.streams))
+        probe_set = [w.streams[i] for i in order[:8]]
+        t0 = time.perf_counter()
+        run(probe_set)
+        dt = max(time.perf_counter() - t0, 1e-3)
+        rate = sum(t.size for t in probe_set) / dt
+        want = rate * target_s
+        chosen, tot = [], 0
+        for i in order[8:]:
+            if tot >= want:
+                break
+            chosen.append(w.streams[i])
+            tot += w.streams[i].size
+        t0 = time.perf_counter()
+        run(chosen)
+        dt = time.perf_counter() - t0
+        nbytes = tot
+        what = (f"{len(chosen)} of the {len(w.streams)} streams (seeded choice, {nbytes} bytes) x all "
+                f"{len(w.patterns)} patterns")
+    return {"value": round(msum * nbytes / dt / 1e9, 3), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{what} (hit ends, hit set and filter), {dt:.1f} s"}
 
 
 def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True, graphs=True):
@@ -156,10 +205,18 @@ def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True
     tune = mt.tune_report()
     sid = [0]
 
+    # the device buffers stay the same from step to step: build the batched
+    # feed's table once and give each step new stream ids
+    segs = np.zeros(len(dev_streams), dtype=oasm.FEED_SEG_DTYPE)
+    segs["data"] = [t.data_ptr() for t in dev_streams]
+    segs["len"] = [t.numel() for t in dev_streams]
+    segs["flags"] = oasm.OASM_FEED_LAST
+    ids = np.arange(len(dev_streams), dtype=np.uint64)
+    hs = torch.cuda.current_stream().cuda_stream
+
     def step():
-        base = sid[0]
-        for i, t in enumerate(dev_streams):
-            mt.feed(base + i, t, last=True)
+        segs["stream"] = ids + np.uint64(sid[0])
+        mt.feed_segs(segs, (), hs)
         sid[0] += len(dev_streams)
         mt.sync()
         return mt.results()
@@ -177,26 +234,54 @@ def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True
     s1 = mt.stats()
     mt.destroy()
     del dev_streams
-    return {"s0": s0, "s1": s1, "elapsed": elapsed, "res": res, "tune": tune}
+    return {"s0": s0, "s1": s1, "elapsed": elapsed, "res": res, "tune": tune, "steps": steps}
 
 
-def batched_vs_plain(oasm, torch, args, w=None):
-    """The many-stream workload: one batched launch sequence over all streams
-    versus one launch sequence per stream (the same kernels)."""
-    from paper_1712_03560_amd import workloads as W
-
-    if w is None:
-        w = W.batched(n_streams=args.batched_streams)
-    cells = sum(len(p) for p in w.patterns) * w.total_bytes
-    b = run_steps(oasm, torch, w, 2, 1)
-    p = run_steps(oasm, torch, w, 2, 1, plain=True)
-    tb, tp = b["elapsed"] / 2, p["elapsed"] / 2
-    assert b["res"].occ.size == p["res"].occ.size and b["res"].raw.size == p["res"].raw.size
-    return {"workload": f"{len(w.streams)} streams log-uniform in [1 KiB, 1 MiB] ({w.total_bytes} bytes), Zipf(1.1) "
-                        f"20 letters, {len(w.patterns)} patterns m~U[8,64], K=floor(m/10)",
-            "batched_gcups": round(cells / tb / 1e9, 1), "plain_gcups": round(cells / tp / 1e9, 1),
-            "batched_ms": round(tb * 1e3, 2), "plain_ms": round(tp * 1e3, 2), "speedup": round(tp / tb, 2),
-            "hit_ends": int(b["res"].raw.size), "occurrences": int(b["res"].occ.size)}
+def summarize(w, r, workload):
+    """GCUPS, the scan's roofline and the step breakdown of a run_steps result."""
+    steps = r["steps"]
+    msum = sum(len(p) for p in w.patterns)
+    cells = msum * w.total_bytes
+    word_steps = sum((len(p) + 31) // 32 for p in w.patterns) * w.total_bytes
+    s0, s1, elapsed, res = r["s0"], r["s1"], r["elapsed"], r["res"]
+    scan_ms = (s1["scan_ms"] - s0["scan_ms"]) / steps
+    done = (s1["word_steps_done"] - s0["word_steps_done"]) / steps
+    cut = any(x.startswith("class ") and "cut=1" in x for x in r["tune"].splitlines())
+    # the algorithmic unit is the word-step; with the word cutoff the
+    # recurrence needs only the words it leaves active (the kernel counts
+    # them), without it every word of every pattern column
+    ops = done * OPS_PER_WORD_STEP
+    achieved = ops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else None
+    peak = VALU_PEAK_OPS / 1e12
+    traffic, vs_one_tile = traffic_from_profiles(workload)
+    return {
+        "gcups": cells / (elapsed / steps) / 1e9,
+        "ms_per_step": elapsed / steps * 1e3,
+        "cells": cells,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2) if achieved else None, "peak": round(peak, 2),
+                     "unit": "TOP/s", "frac": round(achieved / peak, 4) if achieved else None,
+                     "traffic": traffic, "kernel": "k_scan", "scan_ms_per_step": round(scan_ms, 3),
+                     "scan_launches_per_step": (s1["scan_launches"] - s0["scan_launches"]) / steps,
+                     "word_steps": int(done), "word_steps_full_columns": word_steps,
+                     "ops_per_word_step": OPS_PER_WORD_STEP, "word_cutoff": cut,
+                     # FETCH_SIZE of a launch over that of a one-tile scan of
+                     # the same text (which reads it exactly once)
+                     "fetch_vs_one_tile_scan": round(vs_one_tile, 3) if vs_one_tile else None},
+        "scan_gcups": round(cells / (scan_ms * 1e-3) / 1e9, 1) if scan_ms > 0 else None,
+        "step_breakdown_ms": {
+            "scan_kernel": round(scan_ms, 3),
+            "device_step": round((s1["step_ms"] - s0["step_ms"]) / steps, 3),
+            "sync_wall": round((s1["sync_wall_ms"] - s0["sync_wall_ms"]) / steps, 3),
+            "sync_waiting": round((s1["wait_ms"] - s0["wait_ms"]) / steps, 3),
+            "host_plan_launch_copyback_convert": [round((b - a) / steps, 3) for a, b in
+                                                  zip(s0["host_ms"], s1["host_ms"])],
+            "python_feed_drain": round(elapsed / steps * 1e3 - (s1["sync_wall_ms"] - s0["sync_wall_ms"]) / steps, 3),
+            "graph_replays": s1["graph_replays"] - s0["graph_replays"],
+        },
+        "hits": {"hit_ends": int(res.raw.size), "occurrences": int(res.occ.size),
+                 "filtered_hits_per_s": round(res.occ.size / (elapsed / steps), 1)},
+        "autotune": [x for x in r["tune"].splitlines() if x],
+    }
 
 
 def serving_measure(oasm, torch, args):
@@ -266,63 +351,49 @@ def main():
         single_tile_calibration(oasm, torch, w)
     r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk, autotune=not args.no_autotune,
                   graphs=not args.no_graphs)
-    msum = sum(len(p) for p in w.patterns)
-    total_bytes = w.total_bytes
-    cells = msum * total_bytes
-    word_steps = sum((len(p) + 31) // 32 for p in w.patterns) * total_bytes
-    s0, s1, elapsed, res = r["s0"], r["s1"], r["elapsed"], r["res"]
-
-    ms_per_step = elapsed / args.steps * 1e3
-    gcups = cells / (elapsed / args.steps) / 1e9
-    scan_ms = (s1["scan_ms"] - s0["scan_ms"]) / args.steps
-    launches = (s1["scan_launches"] - s0["scan_launches"]) / args.steps
-    ops = word_steps * OPS_PER_WORD_STEP
-    achieved = ops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else None
-    peak = VALU_PEAK_OPS / 1e12
-    traffic, vs_one_tile = traffic_from_profiles(args.workload) or (None, None)
-    cut = any(x.startswith("class ") and "cut=1" in x for x in r["tune"].splitlines())
+    m = summarize(w, r, args.workload)
     line = {
-        "metric": "GCUPS (pattern x text cells/s), whole matching step, 1 MI355X",
-        "value": round(gcups, 1),
+        "metric": METRIC,
+        "value": round(m["gcups"], 1),
         "unit": "GCUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(m["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": desc, "streams": len(w.streams), "patterns": len(w.patterns),
-                   "text_bytes": total_bytes, "cells": cells},
-        "roofline": {"bound": "alu", "achieved": round(achieved, 2) if achieved else None, "peak": round(peak, 2),
-                     "unit": "TOP/s", "frac": round(achieved / peak, 4) if achieved else None,
-                     "traffic": traffic, "kernel": "k_scan", "scan_ms_per_step": round(scan_ms, 3),
-                     "scan_launches_per_step": launches, "word_steps": word_steps,
-                     "ops_per_word_step": OPS_PER_WORD_STEP, "word_cutoff": cut,
-                     # FETCH_SIZE of the launch over that of a one-tile scan of
-                     # the same text (which reads it exactly once)
-                     "fetch_vs_one_tile_scan": round(vs_one_tile, 3) if vs_one_tile else None},
-        "scan_gcups": round(cells / (scan_ms * 1e-3) / 1e9, 1) if scan_ms > 0 else None,
-        "step_breakdown_ms": {
-            "scan_kernel": round(scan_ms, 3),
-            "device_step": round((s1["step_ms"] - s0["step_ms"]) / args.steps, 3),
-            "sync_wall": round((s1["sync_wall_ms"] - s0["sync_wall_ms"]) / args.steps, 3),
-            "sync_waiting": round((s1["wait_ms"] - s0["wait_ms"]) / args.steps, 3),
-            "host_plan_launch_copyback_convert": [round((b - a) / args.steps, 3) for a, b in
-                                              zip(s0["host_ms"], s1["host_ms"])],
-            "python_feed_drain": round(ms_per_step - (s1["sync_wall_ms"] - s0["sync_wall_ms"]) / args.steps, 3),
-            "graph_replays": s1["graph_replays"] - s0["graph_replays"],
-        },
-        "hits": {"hit_ends": int(res.raw.size), "occurrences": int(res.occ.size)},
-        "autotune": [x for x in r["tune"].splitlines() if x],
+                   "text_bytes": w.total_bytes, "cells": m["cells"]},
+        "roofline": m["roofline"],
+        "scan_gcups": m["scan_gcups"],
+        "step_breakdown_ms": m["step_breakdown_ms"],
+        "hits": m["hits"],
+        "autotune": m["autotune"],
     }
-    if args.workload == "batched" or not args.no_batched:
-        line["batched_vs_plain"] = batched_vs_plain(oasm, torch, args, w if args.workload == "batched" else None)
+    if len(w.streams) > 1 and not args.no_plain:
+        # the same workload with one launch sequence per stream (same kernels)
+        p = run_steps(oasm, torch, w, args.plain_steps, 1, plain=True, autotune=not args.no_autotune)
+        assert p["res"].occ.size == r["res"].occ.size and p["res"].raw.size == r["res"].raw.size
+        tp = p["elapsed"] / args.plain_steps
+        line["vs_plain"] = {"plain_gcups": round(m["cells"] / tp / 1e9, 1), "plain_ms_per_step": round(tp * 1e3, 2),
+                            "batched_gcups": line["value"], "speedup": round(tp * 1e3 / m["ms_per_step"], 2)}
+    del r
+    if args.workload != "long" and not args.no_long:
+        wl, dl = make_workload("long", args)
+        rl = run_steps(oasm, torch, wl, max(args.steps, 10), 2, autotune=not args.no_autotune,
+                       graphs=not args.no_graphs)
+        ml = summarize(wl, rl, "long")
+        line["long_stream"] = {"workload": dl, "gcups": round(ml["gcups"], 1),
+                               "ms_per_step": round(ml["ms_per_step"], 3), "roofline": ml["roofline"],
+                               "step_breakdown_ms": ml["step_breakdown_ms"], "hits": ml["hits"]}
+        del rl, wl
     if not args.no_serving:
         line["serving"] = serving_measure(oasm, torch, args)
-    if not args.no_cpu_baseline and args.workload != "batched":
+        line["p99_chunk_latency_ms"] = line["serving"]["at_0p8_capacity"]["latency_p99_ms"]
+    if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 

@@ -156,6 +156,16 @@ typedef struct oasm_segment {
     double arrival_s;
 } oasm_segment;
 
+/* One piece of a batched device feed: `len` bytes at device address `data`
+ * appended to stream `stream`. */
+typedef struct oasm_feed_seg {
+    uint64_t stream;
+    const void *data;
+    uint64_t len;
+    uint32_t flags;     /* OASM_FEED_LAST: the stream ends with this piece */
+    uint32_t reserved;  /* 0 */
+} oasm_feed_seg;
+
 /* Summary of a serving run. */
 typedef struct oasm_serve_report {
     uint64_t segments;        /* segments served */
@@ -185,6 +195,8 @@ typedef struct oasm_stats {
                                    upload; launches up to the step's end; copy-back of the
                                    results; result conversion and stream bookkeeping */
     uint64_t graph_replays;     /* steps launched from captured graphs */
+    uint64_t word_steps_done;   /* pattern-column words the scan advanced over the symbols it
+                                   reported: word_steps less the words the word cutoff skipped */
 } oasm_stats;
 
 /* Fill `cfg` with defaults (device -1, library stream, autotuned chunks). */
@@ -223,6 +235,21 @@ oasm_status oasm_feed(oasm_ctx *ctx, uint64_t stream_id, const uint8_t *bytes, s
  */
 oasm_status oasm_feed_device(oasm_ctx *ctx, uint64_t stream_id, const void *dev, size_t n, void *hip_stream,
                              uint32_t flags);
+
+/*
+ * Feed many device buffers in one call: the same as calling
+ * oasm_feed_device for segs[0], segs[1], ... in order (a stream may appear
+ * several times; its pieces are appended in order), with one mapping launch
+ * for all of them.  The buffers are read on the library's stream after the
+ * work already queued on `hip_stream` (NULL = the library's stream); the
+ * caller keeps them alive until the next oasm_sync.  All or nothing: on
+ * error no piece is fed.  Errors: OASM_E_INVAL (NULL segs with n > 0, a NULL
+ * data pointer with len > 0, len > 2 GiB, nonzero reserved), OASM_E_CLOSED
+ * (a stream closed earlier or by an earlier piece of this call), OASM_E_AGAIN
+ * (the pieces together exceed the device-memory budget), OASM_E_NOMEM,
+ * OASM_E_DEVICE.
+ */
+oasm_status oasm_feed_device_many(oasm_ctx *ctx, const oasm_feed_seg *segs, size_t n, void *hip_stream);
 
 /* Close a stream: the next oasm_sync finishes its filter (Alg. 1 run to the
  * last byte).  Closing an unknown or already closed stream is OASM_E_INVAL. */

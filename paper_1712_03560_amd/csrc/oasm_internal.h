@@ -132,6 +132,7 @@ struct ScanArgs {
     uint32_t item_base;      // first item index of this class
     uint32_t cap;
     uint32_t *max_cnt;       // atomic max of per-item counts
+    unsigned long long *wsteps;  // += pattern words advanced over reported symbols (may be null)
 };
 // `cut`: the word-cutoff variant (one pattern per lane, W >= 2).
 hipError_t launch_scan(int W, int P, bool cut, const ScanArgs &a, int waves_per_block, bool peq_in_lds,

@@ -117,15 +117,29 @@ hipError_t launch_map_symbols(const uint8_t *src, uint8_t *dst, uint64_t n, cons
     return hipGetLastError();
 }
 
-// Many segments at once (one block per segment): the serving loop's batched
-// ingest from a device pool into the streams' staging buffers.
+// Many segments at once (one block per segment piece; the host cuts long
+// segments into pieces): batched ingest into the streams' staging buffers.
+// Four symbols per thread and step when source and destination are 4-byte
+// aligned, else one.
 __global__ void __launch_bounds__(256) k_map_segments(const SegCopy *__restrict__ segs,
                                                       const uint8_t *__restrict__ class_of) {
     __shared__ uint8_t tab[256];
     tab[threadIdx.x] = class_of[threadIdx.x];
     __syncthreads();
     const SegCopy sc = segs[blockIdx.x];
-    for (uint32_t i = threadIdx.x; i < sc.len; i += blockDim.x) sc.dst[i] = tab[sc.src[i]];
+    uint32_t done = 0;
+    if ((((uintptr_t)sc.src | (uintptr_t)sc.dst) & 3) == 0) {
+        const uint32_t nw = sc.len / 4;
+        const uint32_t *s4 = reinterpret_cast<const uint32_t *>(sc.src);
+        uint32_t *d4 = reinterpret_cast<uint32_t *>(sc.dst);
+        for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
+            const uint32_t x = s4[i];
+            d4[i] = (uint32_t)tab[x & 0xFF] | ((uint32_t)tab[(x >> 8) & 0xFF] << 8) |
+                    ((uint32_t)tab[(x >> 16) & 0xFF] << 16) | ((uint32_t)tab[x >> 24] << 24);
+        }
+        done = nw * 4;
+    }
+    for (uint32_t i = done + threadIdx.x; i < sc.len; i += blockDim.x) sc.dst[i] = tab[sc.src[i]];
 }
 
 hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *class_of, hipStream_t st) {

@@ -170,6 +170,8 @@ struct oasm_ctx {
     uint32_t cap_occ = 1u << 16;
     uint32_t cap_carry = 1u << 12;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
+    hipEvent_t ev_seg = nullptr;  // after the last upload from pin_seg
+    bool seg_pending = false;
     // captured launch sequence of the last repeated step shape
     hipGraphExec_t graph_a = nullptr, graph_b = nullptr;
     std::vector<uint64_t> graph_key, graph_prev_key;
@@ -438,6 +440,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
                 a.item_base = item_base;
                 a.cap = c->cap;
                 a.max_cnt = ctl + 0;
+                a.wsteps = reinterpret_cast<unsigned long long *>(ctl + 8);
                 ck(launch_scan(ci.W, ci.P, ci.cut, a, ci.waves, ci.lds, st), "scan launch");
                 item_base += nchunks * ci.ntiles;
                 c->stats.scan_launches++;
@@ -584,6 +587,7 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         }
         if (again) continue;
         if (h[4]) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
+        c->stats.word_steps_done += (uint64_t)h[8] | ((uint64_t)h[9] << 32);
         float ms = 0;
         if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->stats.scan_ms += ms;
         break;
@@ -904,6 +908,7 @@ double time_class(oasm_ctx *c, const ClassInfo &ci, const ChunkDesc *d_chunks, u
     a.item_base = 0;
     a.cap = cap;
     a.max_cnt = c->ctl.as<uint32_t>();
+    a.wsteps = nullptr;
     double best = 1e30;
     for (int r = 0; r < reps; ++r) {
         ck(hipEventRecord(c->ev0, st), "event");
@@ -1087,6 +1092,7 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         ck(hipEventCreate(&c->ev1), "event");
         ck(hipEventCreate(&c->ev2), "event");
         ck(hipEventCreate(&c->ev3), "event");
+        ck(hipEventCreate(&c->ev_seg), "event");
         hipStream_t st = c->st;
 
         // dictionary on the host: lengths, thresholds, symbol classes
@@ -1153,6 +1159,32 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
     return OASM_OK;
 }
 
+// Map a list of (source, staging destination, length) copies with one
+// launch: long copies are cut into 64 KiB pieces (one block each), the table
+// goes up through pinned memory (reused once its previous upload is done).
+static void map_copies(oasm_ctx *c, const std::vector<SegCopy> &in) {
+    constexpr uint32_t kPiece = 64 * 1024;
+    std::vector<SegCopy> copies;
+    copies.reserve(in.size());
+    for (const SegCopy &sc : in)
+        for (uint32_t o = 0; o < sc.len; o += kPiece)
+            copies.push_back(SegCopy{sc.src + o, sc.dst + o, std::min(kPiece, sc.len - o), 0});
+    if (copies.empty()) return;
+    if (c->seg_pending) {
+        ck(hipEventSynchronize(c->ev_seg), "segment table reuse");
+        c->seg_pending = false;
+    }
+    const size_t bytes = copies.size() * sizeof(SegCopy);
+    c->pin_seg.ensure(bytes, c->st);
+    c->d_seg.ensure(bytes, c->st);
+    std::memcpy(c->pin_seg.p, copies.data(), bytes);
+    ck(hipMemcpyAsync(c->d_seg.p, c->pin_seg.p, bytes, hipMemcpyHostToDevice, c->st), "segment table upload");
+    ck(hipEventRecord(c->ev_seg, c->st), "segment event");
+    c->seg_pending = true;
+    ck(launch_map_segments(c->d_seg.as<SegCopy>(), (uint32_t)copies.size(), c->d_class.as<uint8_t>(), c->st),
+       "map segments");
+}
+
 static oasm_status feed_common(oasm_ctx *c, uint64_t stream_id, const void *src, size_t n, bool device,
                                void *user_stream, uint32_t flags) {
     if (!c) return OASM_E_INVAL;
@@ -1214,6 +1246,70 @@ oasm_status oasm_feed(oasm_ctx *c, uint64_t stream_id, const uint8_t *bytes, siz
 oasm_status oasm_feed_device(oasm_ctx *c, uint64_t stream_id, const void *dev, size_t n, void *hip_stream,
                              uint32_t flags) {
     return feed_common(c, stream_id, dev, n, true, hip_stream, flags);
+}
+
+oasm_status oasm_feed_device_many(oasm_ctx *c, const oasm_feed_seg *segs, size_t n, void *hip_stream) {
+    if (!c) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (n > 0 && !segs) return fail(c, OASM_E_INVAL, "NULL segs with n > 0");
+    // validate everything before touching any stream (all or nothing)
+    uint64_t total = 0;
+    std::unordered_map<uint64_t, uint64_t> add;  // stream id -> bytes in this call
+    std::unordered_map<uint64_t, char> closing;  // stream id -> closed by a piece of this call
+    for (size_t i = 0; i < n; ++i) {
+        const oasm_feed_seg &sg = segs[i];
+        if (sg.reserved != 0) return fail(c, OASM_E_INVAL, "reserved field must be 0");
+        if (sg.len > 0 && !sg.data) return fail(c, OASM_E_INVAL, "NULL data with len > 0");
+        if (sg.len > (uint64_t(1) << 31)) return fail(c, OASM_E_INVAL, "piece larger than 2 GiB");
+        if (closing.count(sg.stream)) return fail(c, OASM_E_CLOSED, "feed to a stream closed earlier in the call");
+        auto it = c->slot_of.find(sg.stream);
+        if (it != c->slot_of.end()) {
+            const StreamState &s = c->streams[it->second];
+            if (s.closed || s.close_pending) return fail(c, OASM_E_CLOSED, "feed to a closed stream");
+        }
+        if (sg.flags & OASM_FEED_LAST) closing[sg.stream] = 1;
+        add[sg.stream] += sg.len;
+        total += sg.len;
+    }
+    if (total > 0 && c->cfg.device_mem_budget && c->pending_bytes + total > c->cfg.device_mem_budget)
+        return fail(c, OASM_E_AGAIN, "device memory budget for unmatched stream data exhausted");
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        for (auto &kv : add) {
+            StreamState &s = get_stream(c, kv.first, true);
+            if (kv.second) {
+                oasm_status r = reserve_stream(c, s, kv.second);
+                if (r != OASM_OK) return r;
+            }
+        }
+        std::vector<SegCopy> copies;
+        copies.reserve(n);
+        for (size_t i = 0; i < n; ++i) {
+            const oasm_feed_seg &sg = segs[i];
+            StreamState &s = c->streams[c->slot_of[sg.stream]];
+            if (sg.len) {
+                copies.push_back(SegCopy{reinterpret_cast<const uint8_t *>(sg.data), s.sym + s.valid,
+                                         (uint32_t)sg.len, 0});
+                s.valid += sg.len;
+                c->pending_bytes += sg.len;
+                c->stats.cells += sg.len * c->msum;
+                c->stats.word_steps += sg.len * c->wsum;
+            }
+            if (sg.flags & OASM_FEED_LAST) s.close_pending = true;
+        }
+        hipStream_t us = reinterpret_cast<hipStream_t>(hip_stream);
+        if (!copies.empty() && us && us != c->st) {
+            ck(hipEventRecord(c->ev3, us), "feed event");
+            ck(hipStreamWaitEvent(c->st, c->ev3, 0), "feed wait");
+        }
+        map_copies(c, copies);
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
+    } catch (const std::bad_alloc &) {
+        return fail(c, OASM_E_NOMEM, "host allocation failed");
+    }
+    return OASM_OK;
 }
 
 oasm_status oasm_close_stream(oasm_ctx *c, uint64_t stream_id) {
@@ -1308,17 +1404,7 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
                 c->stats.word_steps += (uint64_t)sg.len * c->wsum;
             }
             const double tb = now_ms();
-            if (!copies.empty()) {
-                c->pin_seg.ensure(copies.size() * sizeof(SegCopy), c->st);
-                c->d_seg.ensure(copies.size() * sizeof(SegCopy), c->st);
-                std::memcpy(c->pin_seg.p, copies.data(), copies.size() * sizeof(SegCopy));
-                ck(hipMemcpyAsync(c->d_seg.p, c->pin_seg.p, copies.size() * sizeof(SegCopy), hipMemcpyHostToDevice,
-                                  c->st),
-                   "segment table upload");
-                ck(launch_map_segments(c->d_seg.as<SegCopy>(), (uint32_t)copies.size(), c->d_class.as<uint8_t>(),
-                                       c->st),
-                   "map segments");
-            }
+            map_copies(c, copies);
             sync_all(c);
             const double te = now_ms();
             rep.busy_s += (te - tb) * 1e-3;
@@ -1423,6 +1509,7 @@ void oasm_destroy(oasm_ctx *c) {
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->ev2) (void)hipEventDestroy(c->ev2);
     if (c->ev3) (void)hipEventDestroy(c->ev3);
+    if (c->ev_seg) (void)hipEventDestroy(c->ev_seg);
     if (c->own_stream && c->st) (void)hipStreamDestroy(c->st);
     delete c;
 }

@@ -238,6 +238,12 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
         }
     }
     uint32_t cnt = 0;
+    // active pattern slots of this wavefront, and the pattern words it
+    // advances over the symbols whose ends it reports (a scalar tally)
+    uint32_t nact = 0;
+#pragma unroll
+    for (int p = 0; p < P; ++p) nact += (uint32_t)__popcll(__ballot(act[p]));
+    uint64_t wsteps = 0;
 
     const const_u32 *text = (const const_u32 *)(cd.sym);
     const uint32_t len = cd.scan_len, lb = cd.lookback;
@@ -249,6 +255,10 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
     for (uint32_t pos = 0; pos < len; pos += kScanGroup) {
         const uint32_t cur = next;
         next = text[(pos >> 2) + 1];
+        {
+            const uint32_t s0 = pos > lb ? pos : lb, s1 = pos + kScanGroup < len ? pos + kScanGroup : len;
+            if (s1 > s0) wsteps += (uint64_t)(s1 - s0) * (CUT ? y + 1 : W) * nact;
+        }
         if (CUT && y < W - 1) {
             uint32_t ynew = y;
             switch (y) {  // wave-uniform
@@ -332,6 +342,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
     if (lane == 0) {
         a.item_cnt[item] = cnt;
         atomicMax(a.max_cnt, cnt);
+        if (a.wsteps) atomicAdd(a.wsteps, (unsigned long long)wsteps);
     }
 }
 

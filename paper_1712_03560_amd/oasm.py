@@ -51,6 +51,7 @@ EXPORTED = [
     "oasm_create",
     "oasm_feed",
     "oasm_feed_device",
+    "oasm_feed_device_many",
     "oasm_close_stream",
     "oasm_sync",
     "oasm_hits",
@@ -89,7 +90,8 @@ class oasm_stats(ctypes.Structure):
                 ("raw_hits", ctypes.c_uint64), ("h_records", ctypes.c_uint64), ("occurrences", ctypes.c_uint64),
                 ("syncs", ctypes.c_uint64), ("scan_ms", ctypes.c_double), ("step_ms", ctypes.c_double),
                 ("scan_launches", ctypes.c_uint64), ("sync_wall_ms", ctypes.c_double), ("wait_ms", ctypes.c_double),
-                ("host_ms", ctypes.c_double * 4), ("graph_replays", ctypes.c_uint64)]
+                ("host_ms", ctypes.c_double * 4), ("graph_replays", ctypes.c_uint64),
+                ("word_steps_done", ctypes.c_uint64)]
 
 
 class oasm_serve_report(ctypes.Structure):
@@ -99,6 +101,8 @@ class oasm_serve_report(ctypes.Structure):
 
 
 SEG_DTYPE = np.dtype([("stream", "<u8"), ("offset", "<u8"), ("len", "<u4"), ("flags", "<u4"), ("arrival_s", "<f8")])
+FEED_SEG_DTYPE = np.dtype([("stream", "<u8"), ("data", "<u8"), ("len", "<u8"), ("flags", "<u4"),
+                           ("reserved", "<u4")])
 HIT_DTYPE = np.dtype([("stream", "<u8"), ("end", "<u8"), ("pattern", "<u4"), ("dist", "<u4")])
 OCC_DTYPE = np.dtype([("stream", "<u8"), ("start", "<u8"), ("pattern", "<u4"), ("len", "<u4"), ("k", "<u4"),
                       ("reserved", "<u4")])
@@ -120,6 +124,8 @@ def _load():
     lib.oasm_feed.argtypes = [P, u64, P, sz, u32]
     lib.oasm_feed.restype = i32
     lib.oasm_feed_device.argtypes = [P, u64, P, sz, P, u32]
+    lib.oasm_feed_device_many.restype = i32
+    lib.oasm_feed_device_many.argtypes = [P, P, sz, P]
     lib.oasm_feed_device.restype = i32
     lib.oasm_close_stream.argtypes = [P, u64]
     lib.oasm_close_stream.restype = i32
@@ -197,6 +203,12 @@ def oasm_feed(ctx, stream_id: int, data, flags: int = 0):
 
 def oasm_feed_device(ctx, stream_id: int, ptr: int, n: int, hip_stream: int | None, flags: int = 0):
     _check(ctx, lib.oasm_feed_device(ctx, stream_id, ptr, n, hip_stream, flags))
+
+
+def oasm_feed_device_many(ctx, segs: np.ndarray, hip_stream: int | None):
+    """segs: a FEED_SEG_DTYPE array (stream, data = device address, len, flags, reserved)."""
+    segs = np.ascontiguousarray(segs, dtype=FEED_SEG_DTYPE)
+    _check(ctx, lib.oasm_feed_device_many(ctx, segs.ctypes.data if segs.size else None, segs.size, hip_stream))
 
 
 def oasm_close_stream(ctx, stream_id: int):
@@ -301,6 +313,31 @@ class Matcher:
                 return
             data = data.numpy()
         oasm_feed(self.ctx, stream_id, data, flags)
+
+    def feed_many(self, items):
+        """Append many device tensors in one call: items = [(stream_id, tensor, last), ...],
+        each a contiguous uint8 CUDA tensor on the current stream's device."""
+        import torch  # only for device buffers and streams
+
+        if not items:
+            return
+        for _, t, _ in items:
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.uint8 or not t.is_contiguous():
+                raise ValueError("feed_many takes contiguous uint8 CUDA tensors")
+        segs = np.zeros(len(items), dtype=FEED_SEG_DTYPE)
+        segs["stream"] = [sid for sid, _, _ in items]
+        segs["data"] = [t.data_ptr() for _, t, _ in items]
+        segs["len"] = [t.numel() for _, t, _ in items]
+        segs["flags"] = [OASM_FEED_LAST if last else 0 for _, _, last in items]
+        self.feed_segs(segs, [t for _, t, _ in items], torch.cuda.current_stream(items[0][1].device).cuda_stream)
+
+    def feed_segs(self, segs: np.ndarray, keep=(), hip_stream: int | None = None):
+        """The raw batched device feed: `segs` is a FEED_SEG_DTYPE array of
+        device addresses; `keep` holds the objects that own that memory (kept
+        alive until the next sync); `hip_stream` is the stream the data was
+        produced on (None = the library's stream)."""
+        oasm_feed_device_many(self.ctx, segs, hip_stream)
+        self._device_refs.extend(keep)
 
     def close(self, stream_id: int):
         oasm_close_stream(self.ctx, stream_id)

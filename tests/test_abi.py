@@ -50,9 +50,46 @@ def test_record_layouts():
     assert ctypes.sizeof(oasm.oasm_hit) == 24
     assert ctypes.sizeof(oasm.oasm_occ) == 32
     assert ctypes.sizeof(oasm.oasm_config) == 32
-    assert ctypes.sizeof(oasm.oasm_stats) == 136
+    assert ctypes.sizeof(oasm.oasm_stats) == 144
     assert ctypes.sizeof(oasm.oasm_serve_report) == 56
     assert oasm.SEG_DTYPE.itemsize == 32
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets
+    that a C compiler gives the header's struct."""
+    import shutil
+    import subprocess
+
+    from paper_1712_03560_amd import oasm
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"oasm_config": oasm.oasm_config, "oasm_stats": oasm.oasm_stats,
+               "oasm_serve_report": oasm.oasm_serve_report}
+    dtypes = {"oasm_segment": oasm.SEG_DTYPE, "oasm_hit": oasm.HIT_DTYPE, "oasm_occ": oasm.OCC_DTYPE,
+              "oasm_feed_seg": oasm.FEED_SEG_DTYPE}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "oasm_gpu.h"', "int main(void) {"]
+    for name, fields in [(n, [f for f, _ in c._fields_]) for n, c in structs.items()] + \
+            [(n, list(d.names)) for n, d in dtypes.items()]:
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field in fields:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(x.split()[:2]): int(x.split()[2]) for x in out if x}
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+    for name, dt in dtypes.items():
+        assert got[(name, "size")] == dt.itemsize, name
+        for field in dt.names:
+            assert got[(name, field)] == dt.fields[field][1], (name, field)
 
 
 def test_status_strings(lib):

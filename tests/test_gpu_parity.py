@@ -155,6 +155,42 @@ def test_plain_equals_batched_and_device_feed():
     compare(b, streams, w.patterns, w.ks, label="device-feed")
 
 
+def test_feed_many_equals_single_feeds():
+    """One batched device feed (pieces of several streams, a stream in
+    several pieces, closes inside the call) gives the same results as one
+    call per piece, equal to the oracle's; a piece for a stream closed earlier
+    in the call is refused and nothing of the call is fed."""
+    w = W.small_random(45, 20000, 40, 8, 100, b"ACGT", kmax=8, n_plants=60, n_streams=5)
+    streams = {i: s for i, s in enumerate(w.streams)}
+    dev = {i: torch.from_numpy(s).cuda() for i, s in streams.items() if s.size}
+    items = []
+    for i, t in dev.items():  # each stream in two pieces, the second closes it
+        h = t.numel() // 3
+        items.append((i, t[:h], False))
+    for i, t in dev.items():
+        items.append((i, t[t.numel() // 3:], True))
+    with oasm.Matcher(w.patterns, w.ks, keep_h=True) as mt:
+        mt.feed_many(items)
+        for i in streams:
+            if i not in dev:
+                mt.close(i)
+        mt.sync()
+        a = mt.results()
+    b = run(w.patterns, w.ks, streams, device=True)
+    for x, y in ((a.raw, b.raw), (a.occ, b.occ), (a.h, b.h)):
+        assert np.array_equal(np.sort(x, order=list(x.dtype.names)), np.sort(y, order=list(y.dtype.names)))
+    compare(a, streams, w.patterns, w.ks, check_h=True, label="feed-many")
+    t0 = next(iter(dev.values()))
+    with oasm.Matcher(w.patterns, w.ks) as mt:
+        with pytest.raises(oasm.OasmError) as ei:
+            mt.feed_many([(7, t0, True), (8, t0, False), (7, t0, False)])
+        assert ei.value.status == oasm.OASM_E_CLOSED
+        assert mt.stats()["cells"] == 0  # nothing of the refused call was fed
+        mt.feed_many([(7, t0, True)])
+        mt.sync()
+        assert mt.stats()["bytes_scanned"] == t0.numel()
+
+
 def test_autotuned_variants_match_oracle():
     """With the autotuner on, every pattern class runs the variant it measured
     fastest (patterns per lane, masks in LDS or L1/L2); results are unchanged."""
