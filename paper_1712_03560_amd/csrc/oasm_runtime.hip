@@ -26,6 +26,7 @@
 #include <thread>
 #include <string>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/oasm_gpu.h"
@@ -150,6 +151,8 @@ struct oasm_ctx {
 
     // streams
     std::unordered_map<uint64_t, uint32_t> slot_of;
+    std::vector<uint32_t> free_slots;      // slots of finished streams, for reuse
+    std::unordered_set<uint64_t> closed_ids;  // ids of finished streams (feeds to them are refused)
     std::vector<StreamState> streams;
 
     // step buffers
@@ -190,7 +193,7 @@ struct oasm_ctx {
     // Staging buffers of closed streams, kept for reuse.  Every byte of them
     // was written by this context (cleared at allocation, then mapped
     // symbols), so they hold valid symbol classes only.
-    std::vector<std::pair<uint8_t *, size_t>> pool;
+    std::multimap<size_t, uint8_t *> pool;  // released staging buffers by capacity
 };
 
 namespace {
@@ -654,6 +657,8 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         c->pending_bytes -= s.valid - s.scanned;
         s.scanned = s.valid;
         if (s.close_pending) {
+            // finished: a closed stream carries nothing (its filter segments
+            // all completed in this step), so its slot is free for reuse
             s.close_pending = false;
             s.closed = true;
             c->staged_bytes -= s.cap;
@@ -661,6 +666,9 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             s.sym = nullptr;
             s.cap = 0;
             s.valid = s.scanned = 0;
+            c->closed_ids.insert(s.id);
+            c->slot_of.erase(s.id);
+            c->free_slots.push_back(s.slot);
             continue;
         }
         const size_t keep = std::min<size_t>(s.valid, c->lookback + 4);
@@ -711,30 +719,38 @@ void sync_all(oasm_ctx *c) {
     if (c->cfg.flags & OASM_CFG_KEEP_H) sort_h_queue_tail(c, h0);
 }
 
+// A live stream by id, created on first use in a free slot (the caller has
+// checked closed_ids: finished streams are not live).
 StreamState &get_stream(oasm_ctx *c, uint64_t id, bool create) {
     auto it = c->slot_of.find(id);
     if (it != c->slot_of.end()) return c->streams[it->second];
     if (!create) throw std::out_of_range("stream");
-    const uint32_t slot = (uint32_t)c->streams.size();
-    c->streams.emplace_back();
-    StreamState &s = c->streams.back();
+    uint32_t slot;
+    if (!c->free_slots.empty()) {
+        slot = c->free_slots.back();
+        c->free_slots.pop_back();
+        c->streams[slot] = StreamState{};
+    } else {
+        slot = (uint32_t)c->streams.size();
+        c->streams.emplace_back();
+    }
+    StreamState &s = c->streams[slot];
     s.id = id;
     s.slot = slot;
     c->slot_of[id] = slot;
     return s;
 }
 
+bool is_finished(const oasm_ctx *c, uint64_t id) { return c->closed_ids.count(id) != 0; }
+
 // A staging buffer of at least `need` bytes: the smallest pooled one that
 // fits, else a new allocation cleared to class 0.
 uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap) {
-    size_t best = c->pool.size();
-    for (size_t i = 0; i < c->pool.size(); ++i)
-        if (c->pool[i].second >= need && (best == c->pool.size() || c->pool[i].second < c->pool[best].second))
-            best = i;
-    if (best < c->pool.size()) {
-        uint8_t *p = c->pool[best].first;
-        cap = c->pool[best].second;
-        c->pool.erase(c->pool.begin() + (ptrdiff_t)best);
+    auto it = c->pool.lower_bound(need);
+    if (it != c->pool.end()) {
+        uint8_t *p = it->second;
+        cap = it->first;
+        c->pool.erase(it);
         return p;
     }
     size_t want = (need + 255) & ~size_t(255);
@@ -743,7 +759,7 @@ uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap) {
         (void)hipGetLastError();
         // give the pool back to the device and try once more
         ck(hipStreamSynchronize(c->st), "sync before pool release");
-        for (auto &b : c->pool) ck(hipFree(b.first), "hipFree pool");
+        for (auto &b : c->pool) ck(hipFree(b.second), "hipFree pool");
         c->pool.clear();
         if (hipMalloc(&p, want) != hipSuccess) {
             (void)hipGetLastError();
@@ -758,7 +774,7 @@ uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap) {
 }
 
 void release_staging(oasm_ctx *c, uint8_t *p, size_t cap) {
-    if (p) c->pool.emplace_back(p, cap);
+    if (p) c->pool.emplace(cap, p);
 }
 
 // Make room for `n` more symbols in a stream's staging buffer.
@@ -1194,6 +1210,7 @@ static oasm_status feed_common(oasm_ctx *c, uint64_t stream_id, const void *src,
     if (n > (size_t(1) << 31)) return fail(c, OASM_E_INVAL, "feed larger than 2 GiB");
     try {
         if (device) ck(hipSetDevice(c->device), "hipSetDevice");
+        if (is_finished(c, stream_id)) return fail(c, OASM_E_CLOSED, "feed to a closed stream");
         StreamState &s = get_stream(c, stream_id, true);
         if (s.closed || s.close_pending) return fail(c, OASM_E_CLOSED, "feed to a closed stream");
         if (n > 0 && c->cfg.device_mem_budget && c->pending_bytes + n > c->cfg.device_mem_budget)
@@ -1263,6 +1280,7 @@ oasm_status oasm_feed_device_many(oasm_ctx *c, const oasm_feed_seg *segs, size_t
         if (sg.len > 0 && !sg.data) return fail(c, OASM_E_INVAL, "NULL data with len > 0");
         if (sg.len > (uint64_t(1) << 31)) return fail(c, OASM_E_INVAL, "piece larger than 2 GiB");
         if (closing.count(sg.stream)) return fail(c, OASM_E_CLOSED, "feed to a stream closed earlier in the call");
+        if (is_finished(c, sg.stream)) return fail(c, OASM_E_CLOSED, "feed to a closed stream");
         auto it = c->slot_of.find(sg.stream);
         if (it != c->slot_of.end()) {
             const StreamState &s = c->streams[it->second];
@@ -1315,6 +1333,7 @@ oasm_status oasm_feed_device_many(oasm_ctx *c, const oasm_feed_seg *segs, size_t
 oasm_status oasm_close_stream(oasm_ctx *c, uint64_t stream_id) {
     if (!c) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
+    if (is_finished(c, stream_id)) return fail(c, OASM_E_INVAL, "stream already closed");
     auto it = c->slot_of.find(stream_id);
     if (it == c->slot_of.end()) return fail(c, OASM_E_INVAL, "unknown stream");
     StreamState &s = c->streams[it->second];
@@ -1380,6 +1399,7 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
                     rep.deferred++;
                     break;
                 }
+                if (is_finished(c, sg.stream)) return fail(c, OASM_E_INVAL, "segment for a closed stream");
                 StreamState &s = get_stream(c, sg.stream, true);
                 if (s.closed || s.close_pending) return fail(c, OASM_E_INVAL, "segment for a closed stream");
                 add[s.slot] += sg.len;
@@ -1490,7 +1510,7 @@ void oasm_destroy(oasm_ctx *c) {
     if (c->st) (void)hipStreamSynchronize(c->st);
     for (auto &s : c->streams)
         if (s.sym) (void)hipFree(s.sym);
-    for (auto &b : c->pool) (void)hipFree(b.first);
+    for (auto &b : c->pool) (void)hipFree(b.second);
     DevBuf *bufs[] = {&c->d_pats, &c->d_slot_pat, &c->d_tiles, &c->d_peq, &c->d_rpeq, &c->d_class, &c->d_patbytes,
                       &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->offsets, &c->item_rec,
                       &c->item_cnt, &c->ctl, &c->scan_tmp, &c->sort_key, &c->sort_val, &c->sort_end, &c->sort_tmp,

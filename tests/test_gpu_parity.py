@@ -189,6 +189,15 @@ def test_feed_many_equals_single_feeds():
         mt.feed_many([(7, t0, True)])
         mt.sync()
         assert mt.stats()["bytes_scanned"] == t0.numel()
+        # stream 7 is finished (its slot may be reused): feeds and closes to it are refused
+        with pytest.raises(oasm.OasmError) as ei:
+            mt.feed_many([(7, t0, False)])
+        assert ei.value.status == oasm.OASM_E_CLOSED
+        with pytest.raises(oasm.OasmError) as ei:
+            mt.feed(7, t0)
+        assert ei.value.status == oasm.OASM_E_CLOSED
+        with pytest.raises(oasm.OasmError):
+            mt.close(7)
 
 
 def test_autotuned_variants_match_oracle():
