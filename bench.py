@@ -33,14 +33,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GCUPS (pattern×text cells/s) batched vs plain, 1 MI355X; p99 chunk latency"
-# MI355X: 256 CUs x 4 SIMD x 16 lanes, 2.4 GHz -> int32 VALU lane-ops per second
-VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# Algorithmic int32 VALU work per 32-bit column word per text symbol: the
-# column recurrence alone in its shortest gfx950 form (and, add, or3, two
-# bitop3 for the horizontal deltas, shift, bitop3, lshl_or, bitop3 for the new
-# vertical deltas).  Hit screening, addressing and replays are overhead and
-# show up as a lower roofline fraction.
-OPS_PER_WORD_STEP = 9
+# MI355X int32 VALU peak from its unit counts and clock: the fp32 vector rate
+# of 157.3 TFLOP/s is 128 32-bit lanes per CU per clock (256 CUs, 2.4 GHz,
+# an FMA counted as two flops), i.e. 78.6 T 32-bit lane-ops/s.  Measured on
+# the chip, v_and / v_xor / v_add_u32 / v_bitop3 reach 52-62 T lane-ops/s and
+# shifts, v_bcnt, v_or3 and the carry adds 34-38 T (the half-rate class).
+VALU_PEAK_OPS = 256 * 128 * 2.4e9
+# Algorithmic int32 VALU work per 32-bit column word per text symbol, frozen
+# from the built kernel's ISA: the column recurrence alone (and, add, three
+# bitop3, two self-adds for the shifts, bitop3, or, bitop3).  Hit screening,
+# addressing, the cutoff's decisions and replays are overhead and show up as
+# a lower roofline fraction.
+OPS_PER_WORD_STEP = 10
 
 
 def parse():

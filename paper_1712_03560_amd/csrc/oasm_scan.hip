@@ -14,12 +14,15 @@ namespace oasm {
 constexpr uint32_t TA = 0xF0, TB = 0xCC, TC = 0xAA;
 #define BITOP3(a, b, c, expr) __builtin_amdgcn_bitop3_b32((a), (b), (c), (uint32_t)((expr) & 0xFF))
 
-// (x << 1) | y as one v_lshl_or_b32 (register-only ALU instruction; the
-// compiler would otherwise split it to fuse the OR elsewhere and spend one
-// more instruction per word).
-__device__ __forceinline__ uint32_t shl1_or(uint32_t x, uint32_t y) {
+// Measured on MI355X (independent chains, full occupancy): v_and, v_xor,
+// v_add_u32 and v_bitop3 sustain 52-62 T lane-ops/s; shifts, v_or3,
+// v_bcnt, v_lshl_or, v_add3, v_alignbit and the carry adds 34-38 T.  The
+// column step is written with the fast ones only where it can be.
+//
+// x + x (= x << 1) as v_add_u32 (the compiler would turn it into a shift).
+__device__ __forceinline__ uint32_t add_self(uint32_t x) {
     uint32_t r;
-    asm("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(r) : "v"(x), "v"(y));
+    asm("v_add_u32 %0, %1, %1" : "=v"(r) : "v"(x));
     return r;
 }
 
@@ -41,8 +44,11 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
 //   ph = mv | ~(u | pv | eq),    mh = pv & (eq | ~u)
 // and, with ph2 / mh2 the deltas shifted one row down (across words),
 //   pv' = mh2 | ~(eq | mv | ph2),    mv' = ph2 & (eq | mv).
-// (Myers 1999 / Hyyro's formulation, rewritten for three-input logic: nine
-// VALU instructions per 32-bit word on gfx950.)
+// (Myers 1999 / Hyyro's formulation, rewritten for three-input logic: ten
+// VALU instructions per 32-bit word on gfx950, all of the fast kind in the
+// first word: and, add, three bitop3, two self-adds for the shifts, bitop3,
+// or, bitop3.  Nine are possible with a shift-or and a three-way or, but
+// those issue at about two thirds of the rate.)
 //
 // column_step_n<N> advances only the first N words of a W-word column (the
 // word cutoff below); column_step<W> advances all of them.
@@ -62,16 +68,16 @@ __device__ __forceinline__ void column_step_n(uint32_t (&pv)[W], uint32_t (&cm)[
             u = (uint32_t)s;
             carry = (uint32_t)(s >> 32);
         }
-        const uint32_t o = u | pv[w] | eq[w];
+        const uint32_t o = BITOP3(u, pv[w], eq[w], TA | TB | TC);
         ph[w] = BITOP3(cm[w], o, 0u, ~(TA & TB));           // ~cm | ~o
         mh[w] = BITOP3(pv[w], eq[w], u, TA & (TB | ~TC));   // pv & (eq | ~u)
     }
     uint32_t npv[N], ncm[N];
 #pragma unroll
     for (int w = 0; w < N; ++w) {
-        const uint32_t ph2 = w == 0 ? ph[0] << 1 : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
+        const uint32_t ph2 = w == 0 ? add_self(ph[0]) : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
         const uint32_t t = BITOP3(eq[w], cm[w], ph2, ~(TA | ~TB | TC));  // ~(eq | ~cm | ph2)
-        npv[w] = w == 0 ? shl1_or(mh[0], t) : (__builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31) | t);
+        npv[w] = (w == 0 ? add_self(mh[0]) : __builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31)) | t;
         ncm[w] = BITOP3(ph2, eq[w], cm[w], ~(TA & (TB | ~TC)));        // ~(ph2 & (eq | ~cm))
     }
 #pragma unroll
