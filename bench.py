@@ -70,10 +70,33 @@ def parse():
     ap.add_argument("--serving-window2", type=float, default=2.0, help="arrival window at 0.8x capacity, s")
     ap.add_argument("--serving-budget", type=int, default=64 << 20, help="unmatched-byte budget")
     ap.add_argument("--serving-pool", type=int, default=1 << 26)
+    ap.add_argument("--no-valu-probe", action="store_true", help="skip the VALU throughput probe")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times and a one-tile scan of the "
                          "workload's text (PMC traffic calibration)")
     return ap.parse_args()
+
+
+def valu_probe():
+    """Measured int32 VALU rates of single instructions and of the scan's
+    column step (the probe built beside the library; a child process that
+    owns its own GPU context, run before this process touches the GPU)."""
+    import subprocess
+
+    from paper_1712_03560_amd import build as B
+
+    if not os.path.exists(B.PROBE):
+        return None
+    try:
+        res = subprocess.run([B.PROBE], capture_output=True, text=True, timeout=120)
+    except subprocess.TimeoutExpired:
+        return None
+    if res.returncode != 0:
+        return None
+    try:
+        return json.loads(res.stdout.strip().splitlines()[-1])
+    except (ValueError, IndexError):
+        return None
 
 
 def copy_calibration():
@@ -337,6 +360,7 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode "
               f"in this build", file=sys.stderr)
         sys.exit(2)
+    probe = None if args.no_valu_probe else valu_probe()
     import torch
 
     if not torch.cuda.is_available():
@@ -372,6 +396,7 @@ def main():
         "config": {"workload": desc, "streams": len(w.streams), "patterns": len(w.patterns),
                    "text_bytes": w.total_bytes, "cells": m["cells"]},
         "roofline": m["roofline"],
+        "valu_probe": probe,
         "scan_gcups": m["scan_gcups"],
         "step_breakdown_ms": m["step_breakdown_ms"],
         "hits": m["hits"],

@@ -9,6 +9,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboasm_gpu.so")
+PROBE = os.path.join(HERE, "valu_probe")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["oasm_scan.hip", "oasm_kernels.hip", "oasm_runtime.hip"]
 ARCH = os.environ.get("OASM_OFFLOAD_ARCH", "gfx950")
@@ -56,6 +57,13 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, LIB)
+    # the VALU throughput probe the benchmark runs beside the library
+    tmp = PROBE + f".tmp{os.getpid()}"
+    cmd = [hipcc, *HIPCC_FLAGS, os.path.join(CSRC, "valu_probe.hip"), "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"hipcc failed for valu_probe.hip:\n{res.stdout}\n{res.stderr}")
+    os.replace(tmp, PROBE)
     return LIB
 
 

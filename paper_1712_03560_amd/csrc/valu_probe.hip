@@ -1,0 +1,153 @@
+// VALU throughput probe for gfx950 (a measurement tool beside the library,
+// run by the benchmark): int32 lane-ops per second of single instructions
+// and of the scan's column recurrence, with registers only.
+//
+// Every kernel runs independent chains per thread (no memory in the loop,
+// one store per thread at the end to keep the work live) on 16 blocks of 4
+// wavefronts per CU.  Instructions are written with inline asm so that each
+// test issues exactly the named instruction.  Output: one JSON object.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+namespace {
+
+#define ASM2(ins) asm volatile(ins " %0, %1, %2" : "=v"(x) : "v"(x), "v"(y))
+#define ASM3(ins) asm volatile(ins " %0, %1, %2, %3" : "=v"(x) : "v"(x), "v"(y), "v"(z))
+
+constexpr int kChains = 16;
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_op(uint32_t *out, int iters, uint32_t seed) {
+    uint32_t a[kChains];
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) a[j] = seed * (threadIdx.x + 1) + j * 0x9E3779B9u + blockIdx.x;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int j = 0; j < kChains; ++j) {
+            uint32_t x = a[j];
+            const uint32_t y = a[(j + 1) % kChains], z = a[(j + 3) % kChains];
+            if (KIND == 0) asm volatile("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(x) : "v"(x), "v"(y), "v"(z));
+            if (KIND == 1) ASM2("v_add_u32");
+            if (KIND == 2) ASM2("v_and_b32");
+            if (KIND == 3) ASM2("v_xor_b32");
+            if (KIND == 4) ASM2("v_or_b32");
+            if (KIND == 5) ASM3("v_or3_b32");
+            if (KIND == 6) asm volatile("v_lshlrev_b32 %0, 1, %1" : "=v"(x) : "v"(x));
+            if (KIND == 7) asm volatile("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(x) : "v"(x), "v"(y));
+            if (KIND == 8) ASM2("v_bcnt_u32_b32");
+            if (KIND == 9) ASM3("v_alignbit_b32");
+            if (KIND == 10) asm volatile("v_add_co_u32 %0, vcc, %1, %2" : "=v"(x) : "v"(x), "v"(y) : "vcc");
+            a[j] = x;
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < kChains; ++j) r ^= a[j];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
+// The scan's one-word column step (ten instructions: and, add, three
+// bitop3, two self-adds, bitop3, or, bitop3) on 4 independent columns per
+// thread, with match masks taken from registers (the asm is not volatile,
+// so the compiler may interleave the columns as it does in the scan).
+__global__ void __launch_bounds__(256) k_column(uint32_t *out, int iters, uint32_t seed) {
+    constexpr int C = 4;
+    uint32_t pv[C], cm[C], eq[8];
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        pv[j] = ~0u;
+        cm[j] = ~0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) eq[j] = (seed + j) * 0x9E3779B9u ^ (threadIdx.x * 0x85EBCA6Bu + blockIdx.x);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const uint32_t e = eq[(s + j) & 7];
+                uint32_t x, u, o, ph, mh, ph2, mh2, t, npv, ncm;
+                asm("v_and_b32 %0, %1, %2" : "=v"(x) : "v"(e), "v"(pv[j]));
+                asm("v_add_u32 %0, %1, %2" : "=v"(u) : "v"(x), "v"(pv[j]));
+                asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xfe" : "=v"(o) : "v"(u), "v"(pv[j]), "v"(e));
+                asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x3f" : "=v"(ph) : "v"(cm[j]), "v"(o), "v"(o));
+                asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xd0" : "=v"(mh) : "v"(pv[j]), "v"(e), "v"(u));
+                asm("v_add_u32 %0, %1, %1" : "=v"(ph2) : "v"(ph));
+                asm("v_add_u32 %0, %1, %1" : "=v"(mh2) : "v"(mh));
+                asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x04" : "=v"(t) : "v"(e), "v"(cm[j]), "v"(ph2));
+                asm("v_or_b32 %0, %1, %2" : "=v"(npv) : "v"(mh2), "v"(t));
+                asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x2f" : "=v"(ncm) : "v"(ph2), "v"(e), "v"(cm[j]));
+                pv[j] = npv;
+                cm[j] = ncm;
+            }
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) r ^= pv[j] ^ cm[j];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
+double seconds(void (*launch)(uint32_t *, int, int), uint32_t *d, int blocks, int iters) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1;
+    launch(d, blocks, 4);  // warm-up
+    (void)hipEventRecord(e0, 0);
+    launch(d, blocks, iters);
+    (void)hipEventRecord(e1, 0);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms * 1e-3;
+}
+
+template <int KIND>
+void launch_op(uint32_t *d, int blocks, int iters) {
+    hipLaunchKernelGGL(k_op<KIND>, dim3(blocks), dim3(256), 0, 0, d, iters, 1u);
+}
+
+void launch_column(uint32_t *d, int blocks, int iters) {
+    hipLaunchKernelGGL(k_column, dim3(blocks), dim3(256), 0, 0, d, iters, 1u);
+}
+
+}  // namespace
+
+int main() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        std::fprintf(stderr, "no device\n");
+        return 1;
+    }
+    const int blocks = cus * 16;
+    uint32_t *d = nullptr;
+    if (hipMalloc(&d, (size_t)blocks * 256 * sizeof(uint32_t)) != hipSuccess) return 1;
+    struct Op {
+        const char *name;
+        void (*fn)(uint32_t *, int, int);
+    };
+    const Op ops[] = {{"v_bitop3_b32", launch_op<0>},  {"v_add_u32", launch_op<1>},      {"v_and_b32", launch_op<2>},
+                      {"v_xor_b32", launch_op<3>},     {"v_or_b32", launch_op<4>},       {"v_or3_b32", launch_op<5>},
+                      {"v_lshlrev_b32", launch_op<6>}, {"v_lshl_or_b32", launch_op<7>},  {"v_bcnt_u32_b32", launch_op<8>},
+                      {"v_alignbit_b32", launch_op<9>}, {"v_add_co_u32", launch_op<10>}};
+    const int iters = 8000;
+    std::printf("{\"cus\": %d, \"blocks\": %d, \"unit\": \"T int32 lane-ops/s\", \"ops\": {", cus, blocks);
+    bool first = true;
+    for (const Op &op : ops) {
+        const double s = seconds(op.fn, d, blocks, iters);
+        const double rate = (double)blocks * 256 * iters * kChains / s / 1e12;
+        std::printf("%s\"%s\": %.2f", first ? "" : ", ", op.name, rate);
+        first = false;
+    }
+    const int citers = 2000;
+    const double s = seconds(launch_column, d, blocks, citers);
+    const double steps = (double)blocks * 256 * citers * 8 * 4;  // word-steps
+    std::printf("}, \"column_step\": {\"ops_per_word_step\": 10, \"word_steps_per_s\": %.4g, \"lane_ops\": %.2f}}\n",
+                steps / s, steps * 10 / s / 1e12);
+    (void)hipFree(d);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
