@@ -52,9 +52,51 @@ __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
 //
 // column_step_n<N> advances only the first N words of a W-word column (the
 // word cutoff below); column_step<W> advances all of them.
+// (hi:lo) as one 64-bit value, and back
+__device__ __forceinline__ uint64_t pack64(uint32_t lo, uint32_t hi) { return ((uint64_t)hi << 32) | lo; }
+
+// a + b on 64 bits as one v_lshl_add_u64 (about twice the rate per 32-bit
+// word of a carry-add pair)
+__device__ __forceinline__ uint64_t add64(uint64_t a, uint64_t b) {
+    uint64_t r;
+    asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// a << 1 on 64 bits as one v_lshl_add_u64
+__device__ __forceinline__ uint64_t shl1_64(uint64_t a) {
+    uint64_t r;
+    asm("v_lshl_add_u64 %0, %1, 1, 0" : "=v"(r) : "v"(a));
+    return r;
+}
+
 template <int N, int W>
 __device__ __forceinline__ void column_step_n(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
     static_assert(N >= 1 && N <= W, "words");
+    if constexpr (N == 2) {
+        // two words as one 64-bit column: the carry add and the one-row
+        // shifts are single 64-bit instructions
+        const uint64_t u = add64(pack64(eq[0] & pv[0], eq[1] & pv[1]), pack64(pv[0], pv[1]));
+        const uint32_t uw[2] = {(uint32_t)u, (uint32_t)(u >> 32)};
+        uint32_t ph[2], mh[2];
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const uint32_t o = BITOP3(uw[w], pv[w], eq[w], TA | TB | TC);
+            ph[w] = BITOP3(cm[w], o, 0u, ~(TA & TB));
+            mh[w] = BITOP3(pv[w], eq[w], uw[w], TA & (TB | ~TC));
+        }
+        const uint64_t ph2 = shl1_64(pack64(ph[0], ph[1])), mh2 = shl1_64(pack64(mh[0], mh[1]));
+        const uint32_t p2[2] = {(uint32_t)ph2, (uint32_t)(ph2 >> 32)};
+        const uint32_t m2[2] = {(uint32_t)mh2, (uint32_t)(mh2 >> 32)};
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const uint32_t t = BITOP3(eq[w], cm[w], p2[w], ~(TA | ~TB | TC));
+            const uint32_t ncm = BITOP3(p2[w], eq[w], cm[w], ~(TA & (TB | ~TC)));
+            pv[w] = m2[w] | t;
+            cm[w] = ncm;
+        }
+        return;
+    }
     uint32_t ph[N], mh[N];
     uint32_t carry = 0;
 #pragma unroll
