@@ -19,13 +19,20 @@ namespace oasm {
 // ------------------------------------------------------------------ K0
 // One thread per (pattern, symbol class).
 //
-// Scan image (K1): the pattern's rows occupy the top m bits of its W-word
-// column (row j at bit 32W - m + j); the 32W - m rows below it are wildcard
-// rows whose mask bit is set for every symbol.  Started with vertical delta
-// 0, such rows stay at delta 0 forever and shift a zero horizontal delta into
-// the first pattern row, which is exactly the free-start boundary (the zero
-// first row of the Less Naive matrix).  They also make the column sum of the
-// vertical deltas equal to the last-row value.
+// Scan image (K1), high placement (full-column variants): the pattern's rows
+// occupy the top m bits of its W-word column (row j at bit 32W - m + j); the
+// 32W - m rows below it are wildcard rows whose mask bit is set for every
+// symbol.  Started with vertical delta 0, such rows stay at delta 0 forever
+// and shift a zero horizontal delta into the first pattern row, which is
+// exactly the free-start boundary (the zero first row of the Less Naive
+// matrix).  They also make the column sum of the vertical deltas equal to the
+// last-row value.
+//
+// Low placement (word-cutoff variants, tile_wp bit 16): row j at bit j, so
+// that the first word holds 32 pattern rows; the zero horizontal delta into
+// row 0 comes from the shift itself, and the rows above the last pattern row
+// (mask bits 0) do not influence the pattern rows; the scan reads the last
+// row through a mask.
 //
 // Reversed masks (K2): row j <-> p[m-1-j], low placement, 64-bit words.
 __global__ void k_peq_build(const uint8_t *__restrict__ pat_bytes, const PatDesc *__restrict__ pats, uint32_t npat,
@@ -41,19 +48,25 @@ __global__ void k_peq_build(const uint8_t *__restrict__ pat_bytes, const PatDesc
     const int m = d.m;
     const uint32_t tile = pat_tile[p], slot = pat_slot[p];
     const uint32_t wp = tile_wp[tile];
-    const int W = (int)(wp & 0xFF), P = (int)(wp >> 8);
+    const int W = (int)(wp & 0xFF), P = (int)((wp >> 8) & 0xFF);
+    const bool low = ((wp >> 16) & 1u) != 0;
     const int lane = (int)(slot % kWave), pp = (int)(slot / kWave);
-    const int g = 32 * W - m;
+    const int g = low ? 0 : 32 * W - m;
     const int pws = pad_pow2(P * W);
-    uint32_t *img = peq_img + tiles[tile].peq_off + ((size_t)c * kWave + lane) * (size_t)pws + (size_t)pp * W;
+    // lane-major rows [class][lane][P*W padded] (full-column tiles), or
+    // word-major [class][word][lane] (cutoff tiles, P = 1)
+    uint32_t *img = peq_img + tiles[tile].peq_off;
     for (int w = 0; w < W; ++w) {
         uint32_t word = 0;
         for (int b = 0; b < 32; ++b) {
             int row = 32 * w + b - g;  // pattern row held by bit b of word w
-            bool set = row < 0 ? true : class_of[pb[row]] == c;
+            bool set = row < 0 ? true : (row < m && class_of[pb[row]] == c);
             word |= (uint32_t)set << b;
         }
-        img[w] = word;
+        if (low)
+            img[((size_t)c * W + w) * kWave + lane] = word;
+        else
+            img[((size_t)c * kWave + lane) * (size_t)pws + (size_t)pp * W + w] = word;
     }
     uint64_t *rp = rpeq + d.rpeq_off + (size_t)c * d.w64;
     for (int w = 0; w < d.w64; ++w) {

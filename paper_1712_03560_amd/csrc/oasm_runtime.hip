@@ -804,8 +804,10 @@ struct TileChoice {
 
 uint32_t pad_pow2_host(uint32_t x) { return x <= 1 ? 1 : x <= 2 ? 2 : x <= 4 ? 4 : 8; }
 
-uint64_t image_bytes(const oasm_ctx *c, int W, int P) {
-    return (uint64_t)c->nclass * 64 * pad_pow2_host((uint32_t)(P * W)) * 4;
+// Bytes of one tile's match-mask image: lane-major rows padded to a power of
+// two (full columns), or word-major with W words per lane (cutoff tiles).
+uint64_t image_bytes(const oasm_ctx *c, int W, int P, bool cut = false) {
+    return (uint64_t)c->nclass * 64 * (cut ? (uint32_t)W : pad_pow2_host((uint32_t)(P * W))) * 4;
 }
 
 // The patterns of one word count, shortest first: neighbouring lanes then
@@ -832,7 +834,7 @@ std::vector<TileChoice> default_choices(const oasm_ctx *c) {
         ch[W].cut = cut_ok && W >= 2;
         if (W == 2 && !ch[W].cut) P = n > 64 ? 2 : 1;
         ch[W].P = P;
-        ch[W].lds = image_bytes(c, W, P) <= 64 * 1024;
+        ch[W].lds = image_bytes(c, W, P, ch[W].cut) <= 64 * 1024;
     }
     return ch;
 }
@@ -854,8 +856,8 @@ void build_tiles(oasm_ctx *c, const std::vector<TileChoice> &choice) {
         ci.W = W;
         ci.P = P;
         ci.tile_first = (uint32_t)tiles.size();
-        ci.lds = choice[W].lds && image_bytes(c, W, P) <= c->max_lds;
         ci.cut = choice[W].cut && P == 1 && W >= 2;
+        ci.lds = choice[W].lds && image_bytes(c, W, P, ci.cut) <= c->max_lds;
         ci.waves = 4;
         const uint32_t per = 64u * P;
         for (size_t t0 = 0; t0 < ids.size(); t0 += per) {
@@ -871,8 +873,8 @@ void build_tiles(oasm_ctx *c, const std::vector<TileChoice> &choice) {
                 pat_slot[pid] = s;
             }
             tiles.push_back(td);
-            tile_wp.push_back((uint32_t)W | ((uint32_t)P << 8));
-            img_words += image_bytes(c, W, P) / 4;
+            tile_wp.push_back((uint32_t)W | ((uint32_t)P << 8) | (ci.cut ? 1u << 16 : 0u));  // bit 16: low placement
+            img_words += image_bytes(c, W, P, ci.cut) / 4;
         }
         ci.ntiles = (uint32_t)tiles.size() - ci.tile_first;
         c->classes.push_back(ci);
@@ -975,7 +977,7 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
                 if (cut && !cut_ok) continue;
                 if (!scan_variant_exists(W, P, cut) || (P > 1 && nW <= (size_t)64 * (P / 2))) continue;
                 for (bool lds : {false, true}) {
-                    if (lds && image_bytes(c, W, P) > c->max_lds) continue;
+                    if (lds && image_bytes(c, W, P, cut) > c->max_lds) continue;
                     if (P == choice[W].P && lds == choice[W].lds && cut == choice[W].cut) continue;
                     cands.push_back(TileChoice{P, lds, cut});
                 }

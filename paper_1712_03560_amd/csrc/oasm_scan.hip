@@ -148,6 +148,22 @@ __device__ __forceinline__ int32_t le_bound(const uint32_t (&pv)[W], const uint3
     return (int32_t)d;
 }
 
+// The same with the last word read through `mask` (low placement: the rows
+// above the last pattern row are excluded); `bias` then holds
+// -32(W-1) - popcount(mask) - bound - 1.
+template <int W>
+__device__ __forceinline__ int32_t le_bound_masked(const uint32_t (&pv)[W], const uint32_t (&cm)[W], uint32_t bias,
+                                                   uint32_t mask) {
+    uint32_t d = bias;
+#pragma unroll
+    for (int w = 0; w < W - 1; ++w) d = bcnt_acc(cm[w], d);
+#pragma unroll
+    for (int w = 0; w < W - 1; ++w) d = bcnt_acc(pv[w], d);
+    d = bcnt_acc(cm[W - 1] & mask, d);
+    d = bcnt_acc(pv[W - 1] & mask, d);
+    return (int32_t)d;
+}
+
 // Per-lane row of a tile image: P*W words padded to a power of two so that
 // one aligned LDS (or global) vector read fetches it.
 template <int N>
@@ -182,14 +198,31 @@ constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
 // value <= K.  The screen and exact test then read the last row only while
 // every word is active.
 //
+// The cutoff columns use low placement (row j at bit j; the last word holds
+// r = m - 32(W-1) pattern rows, and the rows above them, which influence no
+// pattern row, are ignored): the first word then holds 32 pattern rows, and
+// its bottom value is large unless the text really matches the pattern's
+// first 32 symbols.  For the last word the "stay" rule uses D, the last
+// pattern row's value, with the r - 1 pattern rows above it in that word:
+// D <= K + r - 1.
+//
 // `kc` = -(K + 5) per lane: acc = kc + popcount of the vertical deltas of
 // words 0..b (counted as popc(pv) + popc(~mv)) makes s_b <= K + 4 exactly
-// acc < 32(b+1), and s_b <= K + 31 exactly acc < 32(b+1) + 27.
+// acc < 32(b+1), and s_b <= K + 31 exactly acc < 32(b+1) + 27; for the last
+// word (rows read through `mask`), D <= K + r - 1 is acc < `kl` with
+// kl = 32(W-1) + 2r - 5 per lane.
 template <int W, int N>
-__device__ __forceinline__ uint32_t cut_decide(const uint32_t (&pv)[W], const uint32_t (&cm)[W], uint32_t kc) {
+__device__ __forceinline__ uint32_t cut_decide(const uint32_t (&pv)[W], const uint32_t (&cm)[W], uint32_t kc,
+                                               uint32_t mask, uint32_t kl) {
     uint32_t acc = kc, ynew = 0;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
+        if (b == W - 1) {
+            acc = bcnt_acc(cm[b] & mask, acc);
+            acc = bcnt_acc(pv[b] & mask, acc);
+            if (__ballot((int32_t)acc < (int32_t)kl)) ynew = W - 1;
+            break;
+        }
         acc = bcnt_acc(cm[b], acc);
         acc = bcnt_acc(pv[b], acc);
         if (__ballot((int32_t)acc < 32 * (b + 1))) {
@@ -203,19 +236,25 @@ __device__ __forceinline__ uint32_t cut_decide(const uint32_t (&pv)[W], const ui
 
 // One group of 4 symbols with only words 0..N-1 active (N < W): partial
 // mask reads, N-word column steps, then the cutoff decision.
+//
+// The cutoff tiles' images are word-major, [class][word][lane]: the masks of
+// word w for the 64 lanes are 256 contiguous bytes, so reading only the
+// active words stays one coalesced access per word (a lane-major row of
+// 8 words would make every partial read touch 16 cache lines).
 template <int W, int N>
 __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img,
-                                              uint32_t lane_off, uint32_t cur, uint32_t kc) {
-    constexpr int PWS = pad_pow2(W), NS = pad_pow2(N);
-    Words<NS> e[kScanGroup];
+                                              uint32_t lane, uint32_t cur, uint32_t kc, uint32_t mask,
+                                              uint32_t kl) {
+    uint32_t e[kScanGroup][N];
 #pragma unroll
     for (int s = 0; s < kScanGroup; ++s) {
         const uint32_t c = (cur >> (8 * s)) & 0xFFu;
-        e[s] = *reinterpret_cast<const Words<NS> *>(img + c * (kWave * PWS) + lane_off);
+#pragma unroll
+        for (int w = 0; w < N; ++w) e[s][w] = img[(c * W + w) * kWave + lane];
     }
 #pragma unroll
-    for (int s = 0; s < kScanGroup; ++s) column_step_n<N, W>(pv, cm, e[s].v);
-    return cut_decide<W, N>(pv, cm, kc);
+    for (int s = 0; s < kScanGroup; ++s) column_step_n<N, W>(pv, cm, e[s]);
+    return cut_decide<W, N>(pv, cm, kc, mask, kl);
 }
 
 // K1.  Block = `waves` wavefronts sharing one tile (its match-mask image in
@@ -248,7 +287,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
     const TileDesc td = a.tiles[a.tile_first + tile_local];
     const uint32_t *gimg = a.peq_img + td.peq_off;
     if (LDSPEQ) {
-        const uint32_t words = a.nclass * kWave * PWS;  // multiple of 64
+        const uint32_t words = a.nclass * kWave * (CUT ? W : PWS);  // multiple of 64
         const uint4 *src = reinterpret_cast<const uint4 *>(gimg);
         uint4 *dst = reinterpret_cast<uint4 *>(lds_img);
         for (uint32_t i = threadIdx.x; i < words / 4; i += blockDim.x) dst[i] = src[i];
@@ -265,7 +304,11 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
     // Inactive slots hold all-ones +1 deltas (D = 32W) and bounds of 0, so
     // they never pass the screen or the exact test.  kk / k2 hold the biases
     // of le_bound for the exact test (D <= K) and the screen (D <= K + 2).
-    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P], kc = 0;
+    //
+    // CUT (low placement): the last word's pattern rows are read through
+    // `lmask` (r = m - 32(W-1) rows); kk / k2 then count popcount(lmask) in
+    // place of 32 for that word, and kc / kl are cut_decide's biases.
+    uint32_t pv[P][W], mv[P][W], kk[P], k2[P], pat[P], kc = 0, kl = 0, lmask = ~0u;
     bool act[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -273,9 +316,23 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
         act[p] = slot < td.n_active;
         pat[p] = act[p] ? a.slot_pat[td.slot_off + slot] : 0u;
         const PatDesc d = a.pats[pat[p]];
+        if (CUT) {
+            const uint32_t r = act[p] ? (uint32_t)d.m - 32u * (W - 1) : 32u;  // 1..32
+            lmask = r == 32 ? ~0u : (1u << r) - 1u;
+            const uint32_t base = (uint32_t)(-32 * (W - 1) - 1) - r;
+            kk[p] = base - (act[p] ? (uint32_t)d.k : 0u);
+            k2[p] = base - (act[p] ? (uint32_t)d.k + 2 : 2u);
+            kc = (uint32_t)(-5) - (act[p] ? (uint32_t)d.k : 0u);
+            kl = 32u * (W - 1) + 2u * r - 5u;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                pv[p][w] = ~0u;  // the first column: row r holds r (+1 deltas)
+                mv[p][w] = ~0u;  // complemented: no -1 deltas
+            }
+            continue;
+        }
         kk[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k : 0u);
         k2[p] = (uint32_t)(-32 * W - 1) - (act[p] ? (uint32_t)d.k + 2 : 0u);
-        if (CUT) kc = (uint32_t)(-5) - (act[p] ? (uint32_t)d.k : 0u);
         const int g = 32 * W - (int)d.m;  // wildcard rows below the pattern
 #pragma unroll
         for (int w = 0; w < W; ++w) {
@@ -285,6 +342,11 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
             mv[p][w] = ~0u;  // complemented: no -1 deltas
         }
     }
+    // last-row test: D <= bound (bias holds the bound)
+    auto le = [&](const uint32_t (&v)[W], const uint32_t (&c)[W], uint32_t bias) -> int32_t {
+        if constexpr (CUT) return le_bound_masked<W>(v, c, bias, lmask);
+        else return le_bound<W>(v, c, bias);
+    };
     uint32_t cnt = 0;
     // active pattern slots of this wavefront, and the pattern words it
     // advances over the symbols whose ends it reports (a scalar tally)
@@ -312,7 +374,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
             switch (y) {  // wave-uniform
 #define OASM_CUT_CASE(n) \
     case n:              \
-        if constexpr (n + 1 < W) ynew = cut_group<W, n + 1>(pv[0], mv[0], img, lane_off, cur, kc); \
+        if constexpr (n + 1 < W) ynew = cut_group<W, n + 1>(pv[0], mv[0], img, lane, cur, kc, lmask, kl); \
         break;
                 OASM_CUT_CASE(0)
                 OASM_CUT_CASE(1)
@@ -339,7 +401,12 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 #pragma unroll
         for (int s = 0; s < kScanGroup; ++s) {
             const uint32_t c = (cur >> (8 * s)) & 0xFFu;
-            e[s] = *reinterpret_cast<const Words<PWS> *>(img + c * (kWave * PWS) + lane_off);
+            if constexpr (CUT) {  // word-major image
+#pragma unroll
+                for (int w = 0; w < W; ++w) e[s].v[w] = img[(c * W + w) * kWave + lane];
+            } else {
+                e[s] = *reinterpret_cast<const Words<PWS> *>(img + c * (kWave * PWS) + lane_off);
+            }
         }
         uint32_t pv0[P][W], mv0[P][W];
 #pragma unroll
@@ -355,7 +422,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 #pragma unroll
             for (int p = 0; p < P; ++p) {
                 column_step<W>(pv[p], mv[p], &e[s].v[p * W]);
-                if (s == 1) screen[p] = le_bound<W>(pv[p], mv[p], k2[p]);
+                if (s == 1) screen[p] = le(pv[p], mv[p], k2[p]);
             }
         }
         uint64_t sb[P], any = 0;
@@ -374,7 +441,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
                 for (int s = 0; s < kScanGroup; ++s) {
                     const bool inrange = (pos + s >= lb) && (pos + s < len);
                     column_step<W>(pv0[p], mv0[p], &e[s].v[p * W]);
-                    const uint64_t b = __ballot(le_bound<W>(pv0[p], mv0[p], kk[p]) < 0);
+                    const uint64_t b = __ballot(le(pv0[p], mv0[p], kk[p]) < 0);
                     if (inrange && b) {
                         if ((b >> lane) & 1ull) {
                             const uint32_t idx = cnt + mbcnt64(b);
@@ -385,7 +452,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
                 }
             }
         }
-        if (CUT) y = cut_decide<W, W>(pv[0], mv[0], kc);
+        if (CUT) y = cut_decide<W, W>(pv[0], mv[0], kc, lmask, kl);
     }
     if (lane == 0) {
         a.item_cnt[item] = cnt;
@@ -400,7 +467,7 @@ static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStrea
     if (gx == 0 || a.ntiles == 0) return hipSuccess;
     const uint64_t blocks = (uint64_t)((gx + kXcds - 1) / kXcds) * kXcds * a.ntiles;
     if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
-    const size_t shmem = lds ? (size_t)a.nclass * kWave * pad_pow2(P * W) * 4 : 0;
+    const size_t shmem = lds ? (size_t)a.nclass * kWave * (CUT ? W : pad_pow2(P * W)) * 4 : 0;
     if (lds) {
         // raise the instance's dynamic-LDS limit once (never inside a graph
         // capture: the first launch of a shape is always an eager one)
