@@ -257,6 +257,29 @@ __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[
     return cut_decide<W, N>(pv, cm, kc, mask, kl);
 }
 
+// Consecutive groups with exactly N words active, in a loop of its own (so
+// that the column state stays in the same registers from group to group):
+// runs from `pos` until the decision asks for another word count or the
+// chunk ends, and returns that decision.  `next` holds the text word of the
+// group at `pos` and is advanced with it; `wsteps` tallies the word-steps
+// over the symbols whose ends are reported.
+template <int W, int N>
+__device__ __forceinline__ uint32_t cut_run(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img, uint32_t lane,
+                                            const const_u32 *text, uint32_t &next, uint32_t &pos, uint32_t len,
+                                            uint32_t lb, uint32_t kc, uint32_t mask, uint32_t kl, uint64_t &wsteps,
+                                            uint32_t nact) {
+    uint32_t ynew;
+    do {
+        const uint32_t cur = next;
+        next = text[(pos >> 2) + 1];
+        const uint32_t s0 = pos > lb ? pos : lb, s1 = pos + kScanGroup < len ? pos + kScanGroup : len;
+        if (s1 > s0) wsteps += (uint64_t)(s1 - s0) * (N * nact);
+        ynew = cut_group<W, N>(pv, cm, img, lane, cur, kc, mask, kl);
+        pos += kScanGroup;
+    } while (ynew == N - 1 && pos < len);
+    return ynew;
+}
+
 // K1.  Block = `waves` wavefronts sharing one tile (its match-mask image in
 // LDS, or read through the L1 when it does not fit); each wavefront scans
 // one chunk.  Lane l holds P patterns of W words (slots l, l+64, ...).
@@ -362,19 +385,18 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 
     uint32_t y = W - 1;  // last active word (CUT); every word starts active
     uint32_t next = text[0];
-    for (uint32_t pos = 0; pos < len; pos += kScanGroup) {
-        const uint32_t cur = next;
-        next = text[(pos >> 2) + 1];
-        {
-            const uint32_t s0 = pos > lb ? pos : lb, s1 = pos + kScanGroup < len ? pos + kScanGroup : len;
-            if (s1 > s0) wsteps += (uint64_t)(s1 - s0) * (CUT ? y + 1 : W) * nact;
-        }
+    uint32_t pos = 0;
+    while (pos < len) {
         if (CUT && y < W - 1) {
+            // groups with the last word inactive (each word count in a loop
+            // of its own, left when the count changes)
             uint32_t ynew = y;
             switch (y) {  // wave-uniform
-#define OASM_CUT_CASE(n) \
-    case n:              \
-        if constexpr (n + 1 < W) ynew = cut_group<W, n + 1>(pv[0], mv[0], img, lane, cur, kc, lmask, kl); \
+#define OASM_CUT_CASE(n)                                                                                         \
+    case n:                                                                                                      \
+        if constexpr (n + 1 < W)                                                                                 \
+            ynew = cut_run<W, n + 1>(pv[0], mv[0], img, lane, text, next, pos, len, lb, kc, lmask, kl, wsteps, \
+                                     nact);                                                                      \
         break;
                 OASM_CUT_CASE(0)
                 OASM_CUT_CASE(1)
@@ -396,6 +418,12 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
             }
             y = ynew;
             continue;
+        }
+        const uint32_t cur = next;
+        next = text[(pos >> 2) + 1];
+        {
+            const uint32_t s0 = pos > lb ? pos : lb, s1 = pos + kScanGroup < len ? pos + kScanGroup : len;
+            if (s1 > s0) wsteps += (uint64_t)(s1 - s0) * W * nact;
         }
         Words<PWS> e[kScanGroup];
 #pragma unroll
@@ -453,6 +481,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
             }
         }
         if (CUT) y = cut_decide<W, W>(pv[0], mv[0], kc, lmask, kl);
+        pos += kScanGroup;
     }
     if (lane == 0) {
         a.item_cnt[item] = cnt;
