@@ -173,6 +173,21 @@ struct alignas(N * 4 < 16 ? N * 4 : 16) Words {
 
 constexpr int kScanGroup = 4;  // text symbols per scalar load and per hit check
 
+// Byte offset of symbol s's row in an image of `bytes` bytes per class, kept
+// opaque so that it stays a scalar: the per-lane address is then one
+// full-rate v_add_u32 (left to itself the compiler folds the scaling into a
+// half-rate shift-add on the vector side).
+__device__ __forceinline__ uint32_t row_off(uint32_t cur, int s, uint32_t bytes) {
+    uint32_t off = ((cur >> (8 * s)) & 0xFFu) * bytes;
+    asm("" : "+s"(off));
+    return off;
+}
+
+// p + byte offset
+__device__ __forceinline__ const uint32_t *at_bytes(const uint32_t *p, uint32_t off) {
+    return reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + off);
+}
+
 // ------------------------------------------------------------------ cutoff
 // Word cutoff for multi-word columns (Ukkonen's cutoff, kept per 32-row word
 // as in Myers' block-based algorithm, but decided once per group of 4
@@ -246,11 +261,12 @@ __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[
                                               uint32_t lane, uint32_t cur, uint32_t kc, uint32_t mask,
                                               uint32_t kl) {
     uint32_t e[kScanGroup][N];
+    const uint32_t *row = img + lane;
 #pragma unroll
     for (int s = 0; s < kScanGroup; ++s) {
-        const uint32_t c = (cur >> (8 * s)) & 0xFFu;
+        const uint32_t *r = at_bytes(row, row_off(cur, s, W * kWave * 4));
 #pragma unroll
-        for (int w = 0; w < N; ++w) e[s][w] = img[(c * W + w) * kWave + lane];
+        for (int w = 0; w < N; ++w) e[s][w] = r[w * kWave];
     }
 #pragma unroll
     for (int s = 0; s < kScanGroup; ++s) column_step_n<N, W>(pv, cm, e[s]);
@@ -261,22 +277,24 @@ __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[
 // that the column state stays in the same registers from group to group):
 // runs from `pos` until the decision asks for another word count or the
 // chunk ends, and returns that decision.  `next` holds the text word of the
-// group at `pos` and is advanced with it; `wsteps` tallies the word-steps
-// over the symbols whose ends are reported.
+// group at `pos` and is advanced with it; `wsteps` (which starts from every
+// word stepped over every reported symbol) loses the W - N inactive words
+// over the run's reported symbols.
 template <int W, int N>
 __device__ __forceinline__ uint32_t cut_run(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img, uint32_t lane,
                                             const const_u32 *text, uint32_t &next, uint32_t &pos, uint32_t len,
                                             uint32_t lb, uint32_t kc, uint32_t mask, uint32_t kl, uint64_t &wsteps,
                                             uint32_t nact) {
     uint32_t ynew;
+    const uint32_t first = pos;
     do {
         const uint32_t cur = next;
         next = text[(pos >> 2) + 1];
-        const uint32_t s0 = pos > lb ? pos : lb, s1 = pos + kScanGroup < len ? pos + kScanGroup : len;
-        if (s1 > s0) wsteps += (uint64_t)(s1 - s0) * (N * nact);
         ynew = cut_group<W, N>(pv, cm, img, lane, cur, kc, mask, kl);
         pos += kScanGroup;
     } while (ynew == N - 1 && pos < len);
+    const uint32_t s0 = first > lb ? first : lb, s1 = pos < len ? pos : len;
+    if (s1 > s0) wsteps -= (uint64_t)(s1 - s0) * ((W - N) * nact);
     return ynew;
 }
 
@@ -376,11 +394,12 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
     uint32_t nact = 0;
 #pragma unroll
     for (int p = 0; p < P; ++p) nact += (uint32_t)__popcll(__ballot(act[p]));
-    uint64_t wsteps = 0;
+    uint64_t wsteps = 0;  // set below, once the chunk's extent is known
 
     const const_u32 *text = (const const_u32 *)(cd.sym);
     const uint32_t len = cd.scan_len, lb = cd.lookback;
     const uint32_t lane_off = lane * PWS;
+    if (len > lb) wsteps = (uint64_t)(len - lb) * (W * nact);
     const uint32_t *img = LDSPEQ ? lds_img : gimg;
 
     uint32_t y = W - 1;  // last active word (CUT); every word starts active
@@ -421,19 +440,15 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
         }
         const uint32_t cur = next;
         next = text[(pos >> 2) + 1];
-        {
-            const uint32_t s0 = pos > lb ? pos : lb, s1 = pos + kScanGroup < len ? pos + kScanGroup : len;
-            if (s1 > s0) wsteps += (uint64_t)(s1 - s0) * W * nact;
-        }
         Words<PWS> e[kScanGroup];
 #pragma unroll
         for (int s = 0; s < kScanGroup; ++s) {
-            const uint32_t c = (cur >> (8 * s)) & 0xFFu;
             if constexpr (CUT) {  // word-major image
+                const uint32_t *r = at_bytes(img + lane, row_off(cur, s, W * kWave * 4));
 #pragma unroll
-                for (int w = 0; w < W; ++w) e[s].v[w] = img[(c * W + w) * kWave + lane];
+                for (int w = 0; w < W; ++w) e[s].v[w] = r[w * kWave];
             } else {
-                e[s] = *reinterpret_cast<const Words<PWS> *>(img + c * (kWave * PWS) + lane_off);
+                e[s] = *reinterpret_cast<const Words<PWS> *>(at_bytes(img + lane_off, row_off(cur, s, kWave * PWS * 4)));
             }
         }
         uint32_t pv0[P][W], mv0[P][W];
