@@ -7,6 +7,8 @@ from .oracle import (  # noqa: F401
     hset_all,
     hset_at_ends,
     lev,
+    levcalc,
+    levcalc_many,
     raw_hits,
     run_pair,
     run_pairs,

@@ -16,6 +16,9 @@
  *   oracle_hset_all      Section 3, Eq. 2: every substring t[i,l] with
  *                        l in [l_p-K, l_p+K] and lev <= K (the full hit set)
  *   oracle_hset_at_ends  Eq. 2 restricted to a given list of end positions
+ *   oracle_levcalc       the output of LEV CALC (Section 6, the LEV CORE
+ *                        description; Section 6.2): for every start i the
+ *                        distances to t[i,l], l in [l_p-K, l_p+K], by Eq. 1
  *   oracle_filter        Section 4, Alg. 1 with the rules R1-R3 (Section 4.1)
  *                        and the validation test Eq. 3 (Section 4.2)
  *
@@ -183,6 +186,35 @@ int64_t oracle_hset_at_ends(const uint8_t *p, int32_t m, const uint8_t *t,
         }
     }
     return count;
+}
+
+/*
+ * LEV CALC's output for every stream index (Section 6: at each new index it
+ * yields the distances between p and the 2K+1 substrings t[i, l_p-K] ..
+ * t[i, l_p+K]; Section 6.2).  out[i*(2K+1) + j] for start i in [0, n) and
+ * j in [0, 2K] describes l = l_p - K + j:
+ *   min(lev(p, t[i,l]), K+1)  when i + l <= n (one Eq. 1 evaluation),
+ *   255                        when the substring runs past the text end.
+ * Requires 0 <= K < l_p (so l >= 1).  Returns 0, or -1 on bad arguments.
+ */
+int64_t oracle_levcalc(const uint8_t *p, int32_t m, const uint8_t *t, int64_t n,
+                       int32_t K, uint8_t *out)
+{
+    if (m < 1 || K < 0 || K >= m)
+        return -1;
+    int32_t width = 2 * K + 1;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t j = 0; j < width; ++j) {
+            int32_t l = m - K + j;
+            uint8_t v = 255;
+            if (i + l <= n) {
+                int32_t k = oracle_lev(p, m, t + i, l);
+                v = (uint8_t)(k <= K ? k : K + 1);
+            }
+            out[i * width + j] = v;
+        }
+    }
+    return 0;
 }
 
 /* One row of mem (Section 4.2): position i, length l, validation counter r.

@@ -13,6 +13,9 @@ What each function computes (sections of arXiv 1712.03560):
                             l in [l_p-K, l_p+K] and k = lev(p, t[i,l]) <= K.
 * :func:`hset_at_ends`   -- Eq. 2 restricted to substrings ending at given
                             positions.
+* :func:`levcalc`        -- the output of LEV CALC (Section 6.2): for every
+                            start i the distances to t[i,l] for the 2K+1
+                            lengths l in [l_p-K, l_p+K], capped at K+1.
 * :func:`filter_hits`    -- Alg. 1 with R1-R3 (Section 4.1) and Eq. 3
                             (Section 4.2), as read in ``oasm_oracle.c``.
 * :func:`run_pair`       -- the whole path for one (pattern, text) pair:
@@ -67,6 +70,8 @@ def _load():
             lib.oracle_hset_all.restype = i64
             lib.oracle_hset_at_ends.argtypes = [P, i32, P, i64, i32, P, i64, P, P, P, i64]
             lib.oracle_hset_at_ends.restype = i64
+            lib.oracle_levcalc.argtypes = [P, i32, P, i64, i32, P]
+            lib.oracle_levcalc.restype = i64
             lib.oracle_filter.argtypes = [P, P, P, i64, i32, i64, i32] + [P] * 7 + [i64]
             lib.oracle_filter.restype = i64
             _lib = lib
@@ -145,6 +150,25 @@ def hset_at_ends(p, t, K: int, ends):
     E = np.ascontiguousarray(ends, dtype=np.int64)
     hs, hl, hk = _hset_call(_load().oracle_hset_at_ends, _ptr(P), P.size, _ptr(T), T.size, K, _ptr(E), E.size)
     return _sorted_h(hs, hl, hk)
+
+
+def levcalc(p, t, K: int) -> np.ndarray:
+    """LEV CALC for every start: uint8 array [n, 2K+1]; entry j is
+    min(lev(p, t[i, l_p-K+j]), K+1), or 255 where the substring runs past the end."""
+    P, T = _u8(p), _u8(t)
+    out = np.empty((T.size, 2 * K + 1), dtype=np.uint8)
+    if _load().oracle_levcalc(_ptr(P), P.size, _ptr(T), T.size, K, _ptr(out)) != 0:
+        raise ValueError("levcalc needs 0 <= K < len(p)")
+    return out
+
+
+def levcalc_many(patterns, ks, text, threads: int | None = None):
+    """levcalc for every pattern of a dictionary on one text (a thread per pattern)."""
+    T = _u8(text)
+    threads = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        futs = [ex.submit(levcalc, p, T, int(k)) for p, k in zip(patterns, ks)]
+        return [f.result() for f in futs]
 
 
 @dataclass
