@@ -14,7 +14,8 @@ The headline workload is the many-stream one (4096 streams of 1 KiB - 1 MiB,
 launch sequence per stream on the same kernels (`vs_plain`).  The same line
 carries the single 64 MiB stream (`long_stream`), the serving loop's p50/p99
 segment latency (`serving`, `p99_chunk_latency_ms`) and the oracle timed on a
-sample of the headline workload (`cpu_baseline`).
+sample of the headline workload (`cpu_baseline`), and LEV CALC for every
+start of 8 MiB of the long stream (`levcalc`).
 
     python bench.py [--steps K] [--warmup W] [--workload batched|long|multiword|tiny]
 """
@@ -45,6 +46,10 @@ VALU_PEAK_OPS = 256 * 128 * 2.4e9
 # addressing, the cutoff's decisions and replays are overhead and show up as
 # a lower roofline fraction.
 OPS_PER_WORD_STEP = 10
+# The anchored column step of the LEV CALC kernel (every start's distances):
+# the same ten plus one v_or that enters the first DP row's +1 horizontal
+# delta, for the first word of a column (the words above it use the ten).
+OPS_PER_ANCHORED_WORD_STEP = 11
 
 
 def parse():
@@ -71,6 +76,9 @@ def parse():
     ap.add_argument("--serving-budget", type=int, default=64 << 20, help="unmatched-byte budget")
     ap.add_argument("--serving-pool", type=int, default=1 << 26)
     ap.add_argument("--no-valu-probe", action="store_true", help="skip the VALU throughput probe")
+    ap.add_argument("--no-levcalc", action="store_true", help="skip the LEV CALC (every start) leg")
+    ap.add_argument("--levcalc-only", action="store_true", help="run only the LEV CALC leg")
+    ap.add_argument("--levcalc-bytes", type=int, default=1 << 23, help="text bytes of the LEV CALC leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times and a one-tile scan of the "
                          "workload's text (PMC traffic calibration)")
@@ -354,6 +362,61 @@ def serving_measure(oasm, torch, args):
     return out
 
 
+def levcalc_measure(oasm, torch, args, reps: int = 5):
+    """LEV CALC for every start (the distances between each pattern and the
+    2K+1 substrings starting at every text position): the first
+    `levcalc_bytes` of the long stream against its 256 patterns (K = 3),
+    timed with HIP events on the stream the kernel runs on; beside it the
+    oracle on a short prefix (16 threads over the patterns)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from paper_1712_03560_amd import workloads as W
+
+    w = W.long_stream()
+    n = int(args.levcalc_bytes)
+    text = np.ascontiguousarray(w.streams[0][:n])
+    dev = torch.from_numpy(text).cuda()
+    ms = np.array([len(p) for p in w.patterns], dtype=np.int64)
+    ks = np.asarray(w.ks, dtype=np.int64)
+    with oasm.Matcher(w.patterns, w.ks) as mt:
+        out = mt.levcalc(dev)  # warm-up (and the output buffer)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            mt.levcalc(dev, out=out)
+        e1.record(st)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps * 1e-3
+        h = int((out.view(-1) <= 3).sum().item())
+    word_steps = n * int(np.sum(((ms + 31) // 32) * (ms + ks)))
+    first_words = n * int(np.sum(ms + ks))  # the first word of every column step
+    ops = word_steps * 10 + first_words * (OPS_PER_ANCHORED_WORD_STEP - 10)
+    dists = n * int(np.sum(2 * ks + 1))
+    cells = n * int(np.sum(ms * (ms + ks)))
+    peak = VALU_PEAK_OPS / 1e12
+    achieved = ops / t / 1e12
+    # the oracle on a short prefix
+    nb = 2048
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda j: oracle.levcalc(w.patterns[j], text[:nb], int(ks[j])), range(len(w.patterns))))
+    dt = time.perf_counter() - t0
+    return {"workload": f"LEV CALC for every start: first {n} bytes of the long stream (ACGT) x its "
+                        f"{len(w.patterns)} patterns m~U[16,32], K=3",
+            "ms_per_call": round(t * 1e3, 3), "distances_per_s": round(dists / t, 1),
+            "anchored_gcups": round(cells / t / 1e9, 1), "hit_set_entries": h,
+            "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2), "unit": "TOP/s",
+                         "frac": round(achieved / peak, 4), "kernel": "k_levcalc", "word_steps": word_steps,
+                         "ops_per_word_step": f"{OPS_PER_ANCHORED_WORD_STEP} (first word), 10 (others)",
+                         "output_bytes": dists, "output_GBps": round(dists / t / 1e9, 1)},
+            "oracle_sample": {"distances_per_s": round(nb * int(np.sum(2 * ks + 1)) / dt, 1),
+                              "cores": min(16, os.cpu_count() or 1),
+                              "sample": f"first {nb} bytes x all {len(w.patterns)} patterns, {dt:.2f} s"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -372,6 +435,9 @@ def main():
         B.build()
     from paper_1712_03560_amd import oasm
 
+    if args.levcalc_only:
+        print(json.dumps({"levcalc": levcalc_measure(oasm, torch, args)}), flush=True)
+        return
     if args.calibrate_copy:
         copy_calibration()
     w, desc = make_workload(args.workload, args)
@@ -419,6 +485,8 @@ def main():
                                "ms_per_step": round(ml["ms_per_step"], 3), "roofline": ml["roofline"],
                                "step_breakdown_ms": ml["step_breakdown_ms"], "hits": ml["hits"]}
         del rl, wl
+    if not args.no_levcalc:
+        line["levcalc"] = levcalc_measure(oasm, torch, args)
     if not args.no_serving:
         line["serving"] = serving_measure(oasm, torch, args)
         line["p99_chunk_latency_ms"] = line["serving"]["at_0p8_capacity"]["latency_p99_ms"]

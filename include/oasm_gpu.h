@@ -294,6 +294,33 @@ oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_
 oasm_status oasm_serve(oasm_ctx *ctx, const oasm_segment *segs, size_t n, const void *dev_pool, uint64_t pool_bytes,
                        double *latency_s, oasm_serve_report *report);
 
+/*
+ * LEV CALC for every start (Section 6, the LEV CORE description: at each new
+ * stream index i the distances between p and the 2K+1 substrings
+ * t[i, l_p-K] .. t[i, l_p+K]; Section 6.2 computes them by Eq. 1).  For every
+ * pattern p of the context's dictionary and every start i of the `n` bytes at
+ * `dev_text` (device memory), writes 2K_p + 1 bytes to `dev_out` (device
+ * memory), for l = m_p - K_p + j, j = 0 .. 2K_p:
+ *     min(lev(p, t[i, l]), K_p + 1)   when i + l <= n,
+ *     255                             when t[i, l] runs past the text end.
+ * Layout: pattern-major; pattern p's block starts at byte
+ * n * sum over q < p of (2K_q + 1), and inside it start i's bytes are at
+ * i * (2K_p + 1).  The entries <= K_p are exactly the hit set H of Eq. 2.
+ * The text is one independent string (no stream state, no filter); the
+ * context's streams are not touched.  The work is queued on `hip_stream`
+ * (a hipStream_t, NULL = the null stream) and the call returns without
+ * waiting; the caller keeps both buffers alive until that stream has passed
+ * this point.  The first call uploads two small tables (synchronously).
+ * Errors: OASM_E_INVAL (NULL pointers with n > 0, out_bytes below the size
+ * that oasm_levcalc_size gives), OASM_E_DEVICE (the context is poisoned).
+ */
+oasm_status oasm_levcalc(oasm_ctx *ctx, const void *dev_text, size_t n, void *dev_out, size_t out_bytes,
+                         void *hip_stream);
+
+/* Bytes oasm_levcalc writes for a text of n bytes: n * sum over patterns of
+ * (2K + 1).  OASM_E_INVAL for NULL arguments or a size that overflows. */
+oasm_status oasm_levcalc_size(const oasm_ctx *ctx, size_t n, size_t *bytes);
+
 /* Number of records of `kind` queued for draining (OASM_E_INVAL for an
  * unknown kind, or OASM_H without OASM_CFG_KEEP_H). */
 oasm_status oasm_queued(const oasm_ctx *ctx, uint32_t kind, size_t *n);

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboasm_gpu.so")
 PROBE = os.path.join(HERE, "valu_probe")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["oasm_scan.hip", "oasm_kernels.hip", "oasm_runtime.hip"]
+SOURCES = ["oasm_scan.hip", "oasm_kernels.hip", "oasm_levcalc.hip", "oasm_runtime.hip"]
 ARCH = os.environ.get("OASM_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every HIP compile of this project.

@@ -1,0 +1,29 @@
+// Internal declarations of the dense per-start kernel (K4, LEV CALC).
+// Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "oasm_internal.h"
+
+namespace oasm {
+
+// One launch covers the patterns pat_ids[0 .. npat) of one word count W
+// (W = ceil(m / 32) for each of them).  For pattern q = pat_ids[x] the output
+// block starts at byte n * out_unit[q] of `out`; inside it, start i's
+// 2K_q + 1 distances are at i * (2K_q + 1).
+struct LevcalcArgs {
+    const uint8_t *text;      // raw stream bytes (device)
+    uint64_t n;               // bytes = starts
+    const uint32_t *pat_ids;  // patterns of this launch
+    uint32_t npat;
+    const PatDesc *pats;
+    const uint8_t *pat_bytes;
+    const uint64_t *out_unit; // per pattern: sum over earlier patterns of (2K + 1)
+    uint8_t *out;
+};
+
+hipError_t launch_levcalc(int W, const LevcalcArgs &a, hipStream_t st);
+
+}  // namespace oasm

@@ -1,0 +1,223 @@
+// K4: the per-start distances of LEV CALC (Section 6, the LEV CORE
+// description: at every stream index i, the distances between p and the
+// 2K+1 substrings t[i, l_p-K] .. t[i, l_p+K]; Section 6.2), for every start
+// of a device-resident text and every pattern of the dictionary.
+//
+// The FPGA fills the matrix of Eq. 1 anti-diagonal by anti-diagonal with one
+// processing element per pattern row.  Here a thread owns one start i and
+// advances the anchored DP column (first row C[0][l] = l, first column
+// C[r][0] = r) over t[i], t[i+1], ... as a bit-vector column recurrence,
+// 32 pattern rows per 32-bit VALU word; after l symbols the last row holds
+// lev(p, t[i,l]).  The 256 threads of a block take 256 consecutive starts
+// of one pattern: the pattern's match masks (indexed by byte value) and the
+// text window the block's starts read sit in LDS, and the output of a wave
+// (64 starts x (2K+1) bytes) is one contiguous run.
+//
+// Integer bit-vector work only; no matrix cores.
+#include "oasm_device.h"
+#include "oasm_levcalc.h"
+
+namespace oasm {
+
+// Truth-table operands of v_bitop3_b32: the result bit for inputs (a, b, c)
+// is bit (a*4 + b*2 + c) of the immediate.
+constexpr uint32_t LA = 0xF0, LB = 0xCC, LC = 0xAA;
+#define LC_BITOP3(a, b, c, expr) __builtin_amdgcn_bitop3_b32((a), (b), (c), (uint32_t)((expr) & 0xFF))
+
+// x + x as v_add_u32 (a full-rate op; the compiler would emit a shift)
+static __device__ __forceinline__ uint32_t lc_add_self(uint32_t x) {
+    uint32_t r;
+    asm("v_add_u32 %0, %1, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// popcount(x) + acc
+static __device__ __forceinline__ uint32_t lc_bcnt(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
+constexpr int kLcThreads = 256;                   // starts per block pass
+constexpr int kLcWin = kLcThreads + 256 + 64;     // + m_max + K_max - 1 symbols, rounded up
+constexpr int kLcUnroll = 4;                      // symbols per unrolled group
+constexpr int kLcStage = (kLcWin + kLcThreads - 1) / kLcThreads;  // window symbols per thread
+
+// One column of the anchored recurrence (Myers 1999 in Hyyro's form, with
+// the +1 horizontal delta of the first DP row entering the first pattern
+// row).  Row r (1-based) of the pattern is bit r-1 of the W-word column;
+// pv: rows with vertical delta +1; cm: complement of the rows with vertical
+// delta -1; eq: rows whose pattern byte equals the text byte.  With
+// u = (eq & pv) + pv (carry across words):
+//   ph = mv | ~(u | pv | eq),  mh = pv & (eq | ~u),
+//   ph2 = (ph << 1) | 1,       mh2 = mh << 1   (one row down, across words),
+//   pv' = mh2 | ~(eq | mv | ph2),  mv' = ph2 & (eq | mv).
+// Rows above the last pattern row (the unused top of the last word) receive
+// deltas from below but never feed back into a pattern row.
+template <int W>
+__device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t (&eq)[W]) {
+    uint32_t ph[W], mh[W];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t x = eq[w] & pv[w];
+        uint32_t u;
+        if (W == 1) {
+            u = x + pv[w];
+        } else {
+            const uint64_t s = (uint64_t)x + pv[w] + carry;
+            u = (uint32_t)s;
+            carry = (uint32_t)(s >> 32);
+        }
+        const uint32_t o = LC_BITOP3(u, pv[w], eq[w], LA | LB | LC);
+        ph[w] = LC_BITOP3(cm[w], o, 0u, ~(LA & LB));          // ~cm | ~o
+        mh[w] = LC_BITOP3(pv[w], eq[w], u, LA & (LB | ~LC));  // pv & (eq | ~u)
+    }
+    uint32_t npv[W], ncm[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const uint32_t ph2 = w == 0 ? (lc_add_self(ph[0]) | 1u) : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
+        const uint32_t mh2 = w == 0 ? lc_add_self(mh[0]) : __builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31);
+        const uint32_t t = LC_BITOP3(eq[w], cm[w], ph2, ~(LA | ~LB | LC));  // ~(eq | ~cm | ph2)
+        npv[w] = mh2 | t;
+        ncm[w] = LC_BITOP3(ph2, eq[w], cm[w], ~(LA & (LB | ~LC)));        // ~(ph2 & (eq | ~cm))
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        pv[w] = npv[w];
+        cm[w] = ncm[w];
+    }
+}
+
+// Block (x, y): pattern pat_ids[y] (strided by gridDim.y), starts in passes
+// of 256 (strided by gridDim.x).  The window holds, per text symbol, the
+// byte offset of its row in the mask table (byte * W * 4), so a mask read
+// needs no address arithmetic.  Every index is bounded: the window holds
+// 256 + m + K - 1 <= kLcWin symbols, a mask row is byte * W + word.
+template <int W>
+__global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
+    __shared__ uint32_t peq[256 * W];
+    __shared__ uint32_t win[kLcWin];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t passes = (a.n + kLcThreads - 1) / kLcThreads;
+    for (uint32_t x = blockIdx.y; x < a.npat; x += gridDim.y) {
+        const uint32_t q = a.pat_ids[x];
+        const PatDesc d = a.pats[q];
+        const uint32_t m = d.m, K = d.k;
+        const uint32_t width = 2 * K + 1;        // lengths m-K .. m+K
+        const uint32_t steps = m + K;            // symbols read per start
+        const uint32_t quiet = m - K - 1;        // leading steps without output (l < m - K)
+        const uint32_t rlast = m - 32u * (W - 1);  // pattern rows in the last word, 1..32
+        const uint32_t lmask = rlast >= 32 ? ~0u : (1u << rlast) - 1u;
+        uint8_t *const out = a.out + a.n * a.out_unit[q];
+        const uint8_t *const pb = a.pat_bytes + d.off;
+
+        __syncthreads();  // the previous pattern's masks and window are no longer read
+        for (uint32_t i = tid; i < 256u * W; i += kLcThreads) peq[i] = 0u;
+        __syncthreads();
+        for (uint32_t r = tid; r < m; r += kLcThreads) atomicOr(&peq[pb[r] * W + (r >> 5)], 1u << (r & 31));
+
+        // the window of the next pass is loaded into registers while the
+        // current one is matched (software pipelining of the text reads)
+        const uint32_t wlen = kLcThreads + steps - 1;
+        uint32_t nxt[kLcStage];
+        auto fetch = [&](uint64_t pass) {
+            const uint64_t base = pass * kLcThreads;
+#pragma unroll
+            for (int k = 0; k < kLcStage; ++k) {
+                const uint32_t i = tid + k * kLcThreads;
+                nxt[k] = (i < wlen && pass < passes && base + i < a.n) ? a.text[base + i] : 0u;
+            }
+        };
+        fetch(blockIdx.x);
+        for (uint64_t pass = blockIdx.x; pass < passes; pass += gridDim.x) {
+            const uint64_t base = pass * kLcThreads;
+            __syncthreads();  // masks complete; the previous window is no longer read
+#pragma unroll
+            for (int k = 0; k < kLcStage; ++k) {
+                const uint32_t i = tid + k * kLcThreads;
+                if (i < wlen) win[i] = nxt[k] * (W * 4u);
+            }
+            __syncthreads();
+            fetch(pass + gridDim.x);
+            const uint64_t s = base + tid;
+            if (s >= a.n) continue;
+
+            uint32_t pv[W], cm[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                pv[w] = ~0u;  // C[r][0] = r: every vertical delta is +1
+                cm[w] = ~0u;  // no -1 deltas (complemented)
+            }
+            const uint32_t *wp = win + tid;
+            const char *const tab = reinterpret_cast<const char *>(peq);
+            auto masks = [&](uint32_t off, uint32_t (&eq)[W]) {
+                const uint32_t *r = reinterpret_cast<const uint32_t *>(tab + off);
+#pragma unroll
+                for (int w = 0; w < W; ++w) eq[w] = r[w];
+            };
+            // l = j + 1 below m - K: no output yet
+            uint32_t j = 0;
+            for (; j + kLcUnroll <= quiet; j += kLcUnroll, wp += kLcUnroll) {
+                uint32_t eq[kLcUnroll][W];
+#pragma unroll
+                for (int u = 0; u < kLcUnroll; ++u) masks(wp[u], eq[u]);
+#pragma unroll
+                for (int u = 0; u < kLcUnroll; ++u) anchored_step<W>(pv, cm, eq[u]);
+            }
+            for (; j < quiet; ++j, ++wp) {
+                uint32_t eq[W];
+                masks(wp[0], eq);
+                anchored_step<W>(pv, cm, eq);
+            }
+            // l = m - K .. m + K: C[m][l] = l + (sum of the vertical deltas of
+            // rows 1..m) = l - m + popcount(pv) + popcount(cm) over those rows
+            uint8_t *const o = out + s * width;
+            const uint64_t room64 = a.n - s;  // symbols from s to the end
+            const uint32_t room = room64 < 0xFFFFFFFFull ? (uint32_t)room64 : 0xFFFFFFFFu;
+            for (uint32_t i = 0; i < width; ++i) {
+                uint32_t eq[W];
+                masks(wp[i], eq);
+                anchored_step<W>(pv, cm, eq);
+                const uint32_t l = m - K + i;
+                uint32_t dsum = l - m;  // wraps; the total is >= 0
+#pragma unroll
+                for (int w = 0; w < W - 1; ++w) dsum = lc_bcnt(cm[w], lc_bcnt(pv[w], dsum));
+                dsum = lc_bcnt(cm[W - 1] & lmask, lc_bcnt(pv[W - 1] & lmask, dsum));
+                uint32_t v = dsum < K + 1 ? dsum : K + 1;
+                if (l > room) v = 255u;  // t[s, l] runs past the end
+                o[i] = (uint8_t)v;
+            }
+        }
+    }
+}
+
+template <int W>
+hipError_t launch_levcalc_t(const LevcalcArgs &a, hipStream_t st) {
+    if (a.n == 0 || a.npat == 0) return hipSuccess;
+    const uint64_t passes = (a.n + kLcThreads - 1) / kLcThreads;
+    const uint32_t gy = a.npat < 65535u ? a.npat : 65535u;
+    // about 32k blocks in all: enough to fill 256 CUs many times over, few
+    // enough that each block builds its mask table once for many passes
+    uint64_t gx = (32768u + gy - 1) / gy;
+    if (gx > passes) gx = passes;
+    if (gx > 0x7FFFFFFFull) gx = 0x7FFFFFFFull;
+    hipLaunchKernelGGL((k_levcalc<W>), dim3((uint32_t)gx, gy), dim3(kLcThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_levcalc(int W, const LevcalcArgs &a, hipStream_t st) {
+    switch (W) {
+        case 1: return launch_levcalc_t<1>(a, st);
+        case 2: return launch_levcalc_t<2>(a, st);
+        case 3: return launch_levcalc_t<3>(a, st);
+        case 4: return launch_levcalc_t<4>(a, st);
+        case 5: return launch_levcalc_t<5>(a, st);
+        case 6: return launch_levcalc_t<6>(a, st);
+        case 7: return launch_levcalc_t<7>(a, st);
+        case 8: return launch_levcalc_t<8>(a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace oasm

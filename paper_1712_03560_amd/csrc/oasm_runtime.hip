@@ -31,6 +31,7 @@
 
 #include "../../include/oasm_gpu.h"
 #include "oasm_internal.h"
+#include "oasm_levcalc.h"
 
 using namespace oasm;
 
@@ -189,6 +190,16 @@ struct oasm_ctx {
     uint64_t pending_bytes = 0;  // fed, not yet matched
     PinBuf pin_seg;
     DevBuf d_seg;
+
+    // LEV CALC (K4) tables, built on first use: pattern ids grouped by word
+    // count, and per pattern the sum of (2K + 1) over the patterns before it.
+    DevBuf d_lc_ids, d_lc_unit;
+    struct LcGroup {
+        int W;
+        uint32_t first, count;
+    };
+    std::vector<LcGroup> lc_groups;
+    uint64_t lc_unit_total = 0;
 
     // Staging buffers of closed streams, kept for reuse.  Every byte of them
     // was written by this context (cleared at allocation, then mapped
@@ -1507,6 +1518,69 @@ oasm_status oasm_get_stats(const oasm_ctx *c, oasm_stats *out) {
     return OASM_OK;
 }
 
+oasm_status oasm_levcalc_size(const oasm_ctx *c, size_t n, size_t *bytes) {
+    if (!c || !bytes) return OASM_E_INVAL;
+    uint64_t unit = 0;
+    for (uint32_t p = 0; p < c->npat; ++p) unit += 2u * c->k[p] + 1u;
+    if (n && unit > SIZE_MAX / n) return OASM_E_INVAL;
+    *bytes = n * unit;
+    return OASM_OK;
+}
+
+oasm_status oasm_levcalc(oasm_ctx *c, const void *dev_text, size_t n, void *dev_out, size_t out_bytes,
+                         void *hip_stream) {
+    if (!c) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (n > 0 && (!dev_text || !dev_out)) return fail(c, OASM_E_INVAL, "NULL text or output with n > 0");
+    size_t need = 0;
+    if (oasm_levcalc_size(c, n, &need) != OASM_OK) return fail(c, OASM_E_INVAL, "output size overflows size_t");
+    if (out_bytes < need) return fail(c, OASM_E_INVAL, "output buffer too small for n * sum(2K + 1) bytes");
+    if (n == 0) return OASM_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        if (c->lc_groups.empty()) {
+            std::vector<uint32_t> ids;
+            std::vector<uint64_t> unit(c->npat);
+            uint64_t acc = 0;
+            for (uint32_t p = 0; p < c->npat; ++p) {
+                unit[p] = acc;
+                acc += 2u * c->k[p] + 1u;
+            }
+            for (int W = 1; W <= kMaxW32; ++W) {
+                oasm_ctx::LcGroup gr{W, (uint32_t)ids.size(), 0};
+                for (uint32_t p = 0; p < c->npat; ++p)
+                    if ((int)((c->m[p] + 31u) / 32u) == W) ids.push_back(p);
+                gr.count = (uint32_t)ids.size() - gr.first;
+                if (gr.count) c->lc_groups.push_back(gr);
+            }
+            c->d_lc_ids.ensure(ids.size() * 4, c->st);
+            c->d_lc_unit.ensure(unit.size() * 8, c->st);
+            ck(hipMemcpy(c->d_lc_ids.p, ids.data(), ids.size() * 4, hipMemcpyHostToDevice), "levcalc table upload");
+            ck(hipMemcpy(c->d_lc_unit.p, unit.data(), unit.size() * 8, hipMemcpyHostToDevice), "levcalc table upload");
+            c->lc_unit_total = acc;
+        }
+        for (const auto &gr : c->lc_groups) {
+            LevcalcArgs a;
+            a.text = reinterpret_cast<const uint8_t *>(dev_text);
+            a.n = n;
+            a.pat_ids = c->d_lc_ids.as<uint32_t>() + gr.first;
+            a.npat = gr.count;
+            a.pats = c->d_pats.as<PatDesc>();
+            a.pat_bytes = c->d_patbytes.as<uint8_t>();
+            a.out_unit = c->d_lc_unit.as<uint64_t>();
+            a.out = reinterpret_cast<uint8_t *>(dev_out);
+            ck(launch_levcalc(gr.W, a, st), "levcalc launch");
+        }
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
+    } catch (const std::bad_alloc &) {
+        return fail(c, OASM_E_NOMEM, "host allocation failed");
+    }
+    return OASM_OK;
+}
+
 void oasm_destroy(oasm_ctx *c) {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
@@ -1518,7 +1592,7 @@ void oasm_destroy(oasm_ctx *c) {
                       &c->item_cnt, &c->ctl, &c->scan_tmp, &c->sort_key, &c->sort_val, &c->sort_end, &c->sort_tmp,
                       &c->r_pat, &c->r_sl, &c->r_end, &c->r_flag, &c->r_dist, &c->r_hk, &c->seg_cnt, &c->seg_off,
                       &c->carry_flag, &c->carry_off, &c->seg_out, &c->occ_out, &c->carry_buf[0], &c->carry_buf[1],
-                      &c->carry_hk_buf[0], &c->carry_hk_buf[1], &c->raw_in};
+                      &c->carry_hk_buf[0], &c->carry_hk_buf[1], &c->raw_in, &c->d_lc_ids, &c->d_lc_unit};
     for (DevBuf *b : bufs) b->release();
     c->pin_plan.release();
     c->pin_ctl.release();

@@ -62,6 +62,8 @@ EXPORTED = [
     "oasm_last_error",
     "oasm_status_str",
     "oasm_tune_report",
+    "oasm_levcalc",
+    "oasm_levcalc_size",
 ]
 
 
@@ -145,6 +147,10 @@ def _load():
     lib.oasm_last_error.restype = ctypes.c_char_p
     lib.oasm_tune_report.argtypes = [P]
     lib.oasm_tune_report.restype = ctypes.c_char_p
+    lib.oasm_levcalc.argtypes = [P, P, sz, P, sz, P]
+    lib.oasm_levcalc.restype = i32
+    lib.oasm_levcalc_size.argtypes = [P, sz, ctypes.POINTER(sz)]
+    lib.oasm_levcalc_size.restype = i32
     lib.oasm_status_str.argtypes = [i32]
     lib.oasm_status_str.restype = ctypes.c_char_p
     return lib
@@ -247,6 +253,16 @@ def oasm_serve(ctx, segs: np.ndarray, pool_ptr: int, pool_bytes: int, want_laten
                                lat.ctypes.data_as(ctypes.c_void_p) if lat is not None and lat.size else None,
                                ctypes.byref(rep)))
     return {name: getattr(rep, name) for name, _ in oasm_serve_report._fields_}, lat
+
+
+def oasm_levcalc_size(ctx, n: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(ctx, lib.oasm_levcalc_size(ctx, n, ctypes.byref(out)))
+    return out.value
+
+
+def oasm_levcalc(ctx, text_ptr: int, n: int, out_ptr: int, out_bytes: int, hip_stream: int | None):
+    _check(ctx, lib.oasm_levcalc(ctx, text_ptr, n, out_ptr, out_bytes, hip_stream))
 
 
 def oasm_get_stats(ctx) -> dict:
@@ -360,6 +376,26 @@ class Matcher:
             raise ValueError("the pool must be a CUDA uint8 tensor")
         torch.cuda.current_stream(pool.device).synchronize()
         return oasm_serve(self.ctx, segs, pool.data_ptr(), pool.numel(), want_latency)
+
+    def levcalc(self, text, out=None):
+        """LEV CALC for every start of `text` (a contiguous uint8 CUDA tensor):
+        a uint8 CUDA tensor of oasm_levcalc_size bytes (pattern-major, start i
+        of pattern p at offset n * unit[p] + i * (2K_p + 1)), queued on the
+        current stream.  `out` may supply the output tensor."""
+        import torch  # only for device buffers and streams
+
+        if not isinstance(text, torch.Tensor) or not text.is_cuda or text.dtype != torch.uint8 or \
+                not text.is_contiguous():
+            raise ValueError("levcalc takes a contiguous uint8 CUDA tensor")
+        n = text.numel()
+        need = oasm_levcalc_size(self.ctx, n)
+        if out is None:
+            out = torch.empty(max(need, 1), dtype=torch.uint8, device=text.device)
+        elif not out.is_cuda or out.dtype != torch.uint8 or not out.is_contiguous() or out.numel() < need:
+            raise ValueError("out must be a contiguous uint8 CUDA tensor of at least oasm_levcalc_size bytes")
+        hs = torch.cuda.current_stream(text.device).cuda_stream
+        oasm_levcalc(self.ctx, text.data_ptr() if n else None, n, out.data_ptr(), out.numel(), hs)
+        return out[:need]
 
     def stats(self) -> dict:
         return oasm_get_stats(self.ctx)
