@@ -228,8 +228,26 @@ def cpu_baseline(w, target_s: float):
         nbytes = tot
         what = (f"{len(chosen)} of the {len(w.streams)} streams (seeded choice, {nbytes} bytes) x all "
                 f"{len(w.patterns)} patterns")
+    # the same oracle on one thread, over a smaller prefix of the sample
+    if len(w.streams) == 1:
+        one = [w.streams[0][:max(1, nbytes // (2 * threads))]]
+    else:
+        one, tot1 = [], 0
+        for t in chosen:
+            if tot1 >= nbytes // (2 * threads):
+                break
+            one.append(t)
+            tot1 += t.size
+    n1 = sum(t.size for t in one)
+    t0 = time.perf_counter()
+    for t in one:
+        for i in range(len(w.patterns)):
+            oracle.run_pair(w.patterns[i], t, int(w.ks[i]))
+    dt1 = time.perf_counter() - t0
     return {"value": round(msum * nbytes / dt / 1e9, 3), "unit": "GCUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{what} (hit ends, hit set and filter), {dt:.1f} s"}
+            "sample": f"{what} (hit ends, hit set and filter), {dt:.1f} s",
+            "one_thread": {"value": round(msum * n1 / dt1 / 1e9, 3), "unit": "GCUPS",
+                           "sample": f"{len(one)} of those streams ({n1} bytes) x all patterns, {dt1:.1f} s"}}
 
 
 def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True, graphs=True):
@@ -270,6 +288,32 @@ def run_steps(oasm, torch, w, steps, warmup, chunk=0, plain=False, autotune=True
     mt.destroy()
     del dev_streams
     return {"s0": s0, "s1": s1, "elapsed": elapsed, "res": res, "tune": tune, "steps": steps}
+
+
+def host_fed(oasm, torch, w, steps: int = 5, warmup: int = 1):
+    """The long stream fed from host memory (numpy): each step copies the
+    bytes into the library's pinned staging and over PCIe before matching, so
+    the rate includes the host-to-device transfer."""
+    mt = oasm.Matcher(w.patterns, w.ks, autotune=True, graphs=True)
+    text = w.streams[0]
+    sid = 0
+    for _ in range(warmup):
+        mt.feed(sid, text, last=True)
+        mt.sync()
+        mt.results()
+        sid += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mt.feed(sid, text, last=True)
+        mt.sync()
+        mt.results()
+        sid += 1
+    el = (time.perf_counter() - t0) / steps
+    mt.destroy()
+    cells = sum(len(p) for p in w.patterns) * text.size
+    return {"gcups": round(cells / el / 1e9, 1), "ms_per_step": round(el * 1e3, 3),
+            "host_GBps": round(text.size / el / 1e9, 2), "steps": steps}
 
 
 def summarize(w, r, workload):
@@ -483,7 +527,8 @@ def main():
         ml = summarize(wl, rl, "long")
         line["long_stream"] = {"workload": dl, "gcups": round(ml["gcups"], 1),
                                "ms_per_step": round(ml["ms_per_step"], 3), "roofline": ml["roofline"],
-                               "step_breakdown_ms": ml["step_breakdown_ms"], "hits": ml["hits"]}
+                               "step_breakdown_ms": ml["step_breakdown_ms"], "hits": ml["hits"],
+                               "host_fed": host_fed(oasm, torch, wl)}
         del rl, wl
     if not args.no_levcalc:
         line["levcalc"] = levcalc_measure(oasm, torch, args)
