@@ -166,3 +166,40 @@ def test_long_workload_prefix():
     say(f"levcalc long prefix: {len(mine)} hit-set entries")
     assert len(mine) > 1000
     assert np.array_equal(mine, theirs)
+
+
+def test_levcalc_between_feeds_on_a_side_stream():
+    """LEV CALC calls queued on another HIP stream between the pieces of a
+    streamed feed change neither the matcher's results nor their own."""
+    w = W.small_random(21, 30_000, 10, 8, 40, b"ACGT", 6, n_plants=40)
+    t = w.streams[0]
+    cuts = [0, 7_001, 15_000, 22_222, t.size]
+    side = torch.cuda.Stream()
+    dev = torch.from_numpy(t).cuda()
+    with oasm.Matcher(w.patterns, w.ks, keep_h=True) as mt:
+        outs = []
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            mt.feed(0, t[a:b], last=b == t.size)
+            with torch.cuda.stream(side):
+                outs.append(mt.levcalc(dev[a:b].contiguous()))
+            mt.sync()
+        side.synchronize()
+        res = mt.results()
+    # the streamed matcher against the oracle (hit ends and occurrences)
+    for p in range(len(w.patterns)):
+        want = oracle.run_pair(w.patterns[p], t, int(w.ks[p]))
+        sel = res.raw[res.raw["pattern"] == p]
+        assert np.array_equal(sel["end"].astype(np.int64), want.ends)
+        occ = res.occ[res.occ["pattern"] == p]
+        got = np.stack([occ["start"].astype(np.int64), occ["len"].astype(np.int64), occ["k"].astype(np.int64)], 1)
+        assert np.array_equal(got, want.occ.reshape(-1, 3))
+    # each LEV CALC call against the oracle on its own piece
+    for (a, b), out in zip(zip(cuts[:-1], cuts[1:]), outs):
+        flat = out.cpu().numpy()
+        off = 0
+        n = b - a
+        for p in range(len(w.patterns)):
+            K = int(w.ks[p])
+            got = flat[off:off + n * (2 * K + 1)].reshape(n, 2 * K + 1)
+            assert np.array_equal(got, oracle.levcalc(w.patterns[p], t[a:b], K)), (a, p)
+            off += n * (2 * K + 1)
