@@ -121,3 +121,9 @@ def test_null_arguments(lib):
     assert lib.oasm_feed(None, 0, None, 0, 0) == -1
     lib.oasm_destroy.argtypes = [ctypes.c_void_p]
     lib.oasm_destroy(None)  # no-op
+    lib.oasm_levcalc.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                 ctypes.c_size_t, ctypes.c_void_p]
+    assert lib.oasm_levcalc(None, None, 0, None, 0, None) == -1
+    lib.oasm_levcalc_size.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    out = ctypes.c_size_t(7)
+    assert lib.oasm_levcalc_size(None, 10, ctypes.byref(out)) == -1
