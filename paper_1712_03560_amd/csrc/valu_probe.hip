@@ -90,6 +90,67 @@ __global__ void __launch_bounds__(256) k_column(uint32_t *out, int iters, uint32
     out[blockIdx.x * blockDim.x + threadIdx.x] = r;
 }
 
+// Two one-word columns as the halves of one 64-bit pair: the carry add and
+// both one-row shifts as v_lshl_add_u64 over the pair, the logic per half;
+// the high half's bottom row is a wildcard row, which absorbs the carry out
+// of the low half, and the bit the shifts move across the halves is masked
+// (one v_and for the horizontal +1 deltas; the -1 deltas' mask is folded
+// into the bitop3 that forms the new +1 vertical deltas).  Eighteen
+// instructions per pair; 2 pairs per thread.
+__global__ void __launch_bounds__(256) k_column_pair(uint32_t *out, int iters, uint32_t seed) {
+    constexpr int C = 2;
+    uint32_t pv[C][2], cm[C][2], eq[8];
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+        for (int h = 0; h < 2; ++h) {
+            pv[j][h] = ~0u;
+            cm[j][h] = ~0u;
+        }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) eq[j] = (seed + j) * 0x9E3779B9u ^ (threadIdx.x * 0x85EBCA6Bu + blockIdx.x);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                const uint32_t e[2] = {eq[(s + j) & 7], eq[(s + j + 3) & 7]};
+                uint32_t x[2], o[2], ph[2], mh[2], t[2];
+                asm("v_and_b32 %0, %1, %2" : "=v"(x[0]) : "v"(e[0]), "v"(pv[j][0]));
+                asm("v_and_b32 %0, %1, %2" : "=v"(x[1]) : "v"(e[1]), "v"(pv[j][1]));
+                uint64_t u;
+                asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(u)
+                    : "v"(((uint64_t)x[1] << 32) | x[0]), "v"(((uint64_t)pv[j][1] << 32) | pv[j][0]));
+                const uint32_t uu[2] = {(uint32_t)u, (uint32_t)(u >> 32)};
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xfe" : "=v"(o[h]) : "v"(uu[h]), "v"(pv[j][h]), "v"(e[h]));
+                    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x3f" : "=v"(ph[h]) : "v"(cm[j][h]), "v"(o[h]), "v"(o[h]));
+                    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0xd0" : "=v"(mh[h]) : "v"(pv[j][h]), "v"(e[h]), "v"(uu[h]));
+                }
+                uint64_t ph2, mh2;
+                asm("v_lshl_add_u64 %0, %1, 1, 0" : "=v"(ph2) : "v"(((uint64_t)ph[1] << 32) | ph[0]));
+                asm("v_lshl_add_u64 %0, %1, 1, 0" : "=v"(mh2) : "v"(((uint64_t)mh[1] << 32) | mh[0]));
+                uint32_t p2[2] = {(uint32_t)ph2, (uint32_t)(ph2 >> 32)};
+                const uint32_t m2[2] = {(uint32_t)mh2, (uint32_t)(mh2 >> 32)};
+                asm("v_and_b32 %0, -2, %1" : "=v"(p2[1]) : "v"(p2[1]));
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x04" : "=v"(t[h]) : "v"(e[h]), "v"(cm[j][h]), "v"(p2[h]));
+                asm("v_or_b32 %0, %1, %2" : "=v"(pv[j][0]) : "v"(m2[0]), "v"(t[0]));
+                // (m2 & -2) | t
+                asm("v_bitop3_b32 %0, %1, -2, %2 bitop3:0xea" : "=v"(pv[j][1]) : "v"(m2[1]), "v"(t[1]));
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x2f" : "=v"(cm[j][h]) : "v"(p2[h]), "v"(e[h]), "v"(cm[j][h]));
+            }
+        }
+    }
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < C; ++j) r ^= pv[j][0] ^ cm[j][0] ^ pv[j][1] ^ cm[j][1];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = r;
+}
+
 double seconds(void (*launch)(uint32_t *, int, int), uint32_t *d, int blocks, int iters) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1;
@@ -112,6 +173,10 @@ void launch_op(uint32_t *d, int blocks, int iters) {
 
 void launch_column(uint32_t *d, int blocks, int iters) {
     hipLaunchKernelGGL(k_column, dim3(blocks), dim3(256), 0, 0, d, iters, 1u);
+}
+
+void launch_column_pair(uint32_t *d, int blocks, int iters) {
+    hipLaunchKernelGGL(k_column_pair, dim3(blocks), dim3(256), 0, 0, d, iters, 1u);
 }
 
 }  // namespace
@@ -146,8 +211,10 @@ int main() {
     const int citers = 2000;
     const double s = seconds(launch_column, d, blocks, citers);
     const double steps = (double)blocks * 256 * citers * 8 * 4;  // word-steps
-    std::printf("}, \"column_step\": {\"ops_per_word_step\": 10, \"word_steps_per_s\": %.4g, \"lane_ops\": %.2f}}\n",
-                steps / s, steps * 10 / s / 1e12);
+    const double s2 = seconds(launch_column_pair, d, blocks, citers);
+    std::printf("}, \"column_step\": {\"ops_per_word_step\": 10, \"word_steps_per_s\": %.4g, \"lane_ops\": %.2f}, "
+                "\"column_step_pair64\": {\"instructions_per_two_word_steps\": 18, \"word_steps_per_s\": %.4g}}\n",
+                steps / s, steps * 10 / s / 1e12, steps / s2);
     (void)hipFree(d);
     return hipGetLastError() == hipSuccess ? 0 : 1;
 }
