@@ -310,7 +310,9 @@ oasm_status oasm_serve(oasm_ctx *ctx, const oasm_segment *segs, size_t n, const 
  * context's streams are not touched.  The work is queued on `hip_stream`
  * (a hipStream_t, NULL = the null stream) and the call returns without
  * waiting; the caller keeps both buffers alive until that stream has passed
- * this point.  The first call uploads two small tables (synchronously).
+ * this point (oasm_destroy waits for the last such point, since the kernels
+ * read the context's dictionary).  The first call uploads two small tables
+ * (synchronously).
  * Errors: OASM_E_INVAL (NULL pointers with n > 0, out_bytes below the size
  * that oasm_levcalc_size gives), OASM_E_DEVICE (the context is poisoned).
  */
@@ -329,7 +331,7 @@ oasm_status oasm_queued(const oasm_ctx *ctx, uint32_t kind, size_t *n);
 oasm_status oasm_get_stats(const oasm_ctx *ctx, oasm_stats *out);
 
 /* Free the context and everything it owns (NULL is a no-op).  Waits for
- * the context's device work to finish. */
+ * the context's device work to finish, LEV CALC launches included. */
 void oasm_destroy(oasm_ctx *ctx);
 
 /* The scan variants in use and how they were chosen: one line per variant

@@ -200,6 +200,7 @@ struct oasm_ctx {
     };
     std::vector<LcGroup> lc_groups;
     uint64_t lc_unit_total = 0;
+    hipEvent_t ev_lc = nullptr;  // after the last LEV CALC launch (on the caller's stream)
 
     // Staging buffers of closed streams, kept for reuse.  Every byte of them
     // was written by this context (cleared at allocation, then mapped
@@ -1573,6 +1574,9 @@ oasm_status oasm_levcalc(oasm_ctx *c, const void *dev_text, size_t n, void *dev_
             a.out = reinterpret_cast<uint8_t *>(dev_out);
             ck(launch_levcalc(gr.W, a, st), "levcalc launch");
         }
+        // destroy waits for this point: the kernels read the dictionary tables
+        if (!c->ev_lc) ck(hipEventCreateWithFlags(&c->ev_lc, hipEventDisableTiming), "levcalc event");
+        ck(hipEventRecord(c->ev_lc, st), "levcalc event record");
     } catch (const HipFail &f) {
         return device_fail(c, f);
     } catch (const std::bad_alloc &) {
@@ -1584,6 +1588,10 @@ oasm_status oasm_levcalc(oasm_ctx *c, const void *dev_text, size_t n, void *dev_
 void oasm_destroy(oasm_ctx *c) {
     if (!c) return;
     if (c->st) (void)hipStreamSynchronize(c->st);
+    if (c->ev_lc) {
+        (void)hipEventSynchronize(c->ev_lc);
+        (void)hipEventDestroy(c->ev_lc);
+    }
     for (auto &s : c->streams)
         if (s.sym) (void)hipFree(s.sym);
     for (auto &b : c->pool) (void)hipFree(b.second);

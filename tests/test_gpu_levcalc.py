@@ -203,3 +203,22 @@ def test_levcalc_between_feeds_on_a_side_stream():
             got = flat[off:off + n * (2 * K + 1)].reshape(n, 2 * K + 1)
             assert np.array_equal(got, oracle.levcalc(w.patterns[p], t[a:b], K)), (a, p)
             off += n * (2 * K + 1)
+
+
+def test_destroy_waits_for_levcalc():
+    """A context destroyed right after a LEV CALC call (no synchronisation in
+    between) leaves the queued kernels their dictionary tables."""
+    w = W.long_stream(n=1 << 21, n_plants=100)
+    text = w.streams[0]
+    dev = torch.from_numpy(text).cuda()
+    mt = oasm.Matcher(w.patterns, w.ks)
+    out = mt.levcalc(dev)
+    mt.destroy()
+    torch.cuda.synchronize()
+    n, K = text.size, 3
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        p, s = int(rng.integers(0, len(w.patterns))), int(rng.integers(0, n))
+        got = out[(p * n + s) * 7:(p * n + s) * 7 + 7].cpu().numpy()
+        want = oracle.levcalc(w.patterns[p], text[s:s + len(w.patterns[p]) + K], K)[0]
+        assert np.array_equal(got, want), (p, s)
