@@ -15,7 +15,8 @@ launch sequence per stream on the same kernels (`vs_plain`).  The same line
 carries the single 64 MiB stream (`long_stream`), the serving loop's p50/p99
 segment latency (`serving`, `p99_chunk_latency_ms`) and the oracle timed on a
 sample of the headline workload (`cpu_baseline`), and LEV CALC for every
-start of 8 MiB of the long stream (`levcalc`).
+start of 8 MiB of the long stream and of 64 KiB of the multiword stream
+(`levcalc`).
 
     python bench.py [--steps K] [--warmup W] [--workload batched|long|multiword|tiny]
 """
@@ -78,6 +79,7 @@ def parse():
     ap.add_argument("--no-valu-probe", action="store_true", help="skip the VALU throughput probe")
     ap.add_argument("--no-levcalc", action="store_true", help="skip the LEV CALC (every start) leg")
     ap.add_argument("--levcalc-only", action="store_true", help="run only the LEV CALC leg")
+    ap.add_argument("--levcalc-leg", default="both", choices=["both", "long", "multiword"])
     ap.add_argument("--levcalc-bytes", type=int, default=1 << 23, help="text bytes of the LEV CALC leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times and a one-tile scan of the "
@@ -406,19 +408,27 @@ def serving_measure(oasm, torch, args):
     return out
 
 
-def levcalc_measure(oasm, torch, args, reps: int = 5):
+def levcalc_word_steps(m: int, K: int):
+    """Word-steps of one start's anchored column in the LEV CALC kernel: step
+    j (column l = j + 1) advances min(W, ceil((l + K) / 32)) words before
+    the first output and all W words from l = m - K on (the band cutoff);
+    and the same without the cutoff, (m + K) * W."""
+    W = (m + 31) // 32
+    quiet = m - K - 1
+    band = sum(min(W, -(-(j + 1 + K) // 32)) if j < quiet else W for j in range(m + K))
+    return band, (m + K) * W
+
+
+def levcalc_measure(oasm, torch, w, n: int, desc: str, reps: int = 5):
     """LEV CALC for every start (the distances between each pattern and the
-    2K+1 substrings starting at every text position): the first
-    `levcalc_bytes` of the long stream against its 256 patterns (K = 3),
-    timed with HIP events on the stream the kernel runs on; beside it the
-    oracle on a short prefix (16 threads over the patterns)."""
+    2K+1 substrings starting at every text position) over the first n bytes
+    of a workload's stream, timed with HIP events on the stream the kernel
+    runs on; beside it the oracle on a short prefix (16 threads over the
+    patterns)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
-    from paper_1712_03560_amd import workloads as W
 
-    w = W.long_stream()
-    n = int(args.levcalc_bytes)
     text = np.ascontiguousarray(w.streams[0][:n])
     dev = torch.from_numpy(text).cuda()
     ms = np.array([len(p) for p in w.patterns], dtype=np.int64)
@@ -434,8 +444,9 @@ def levcalc_measure(oasm, torch, args, reps: int = 5):
         e1.record(st)
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1) / reps * 1e-3
-        h = int((out.view(-1) <= 3).sum().item())
-    word_steps = n * int(np.sum(((ms + 31) // 32) * (ms + ks)))
+    steps = [levcalc_word_steps(int(m), int(k)) for m, k in zip(ms, ks)]
+    word_steps = n * sum(b for b, _ in steps)
+    full = n * sum(f for _, f in steps)
     first_words = n * int(np.sum(ms + ks))  # the first word of every column step
     ops = word_steps * 10 + first_words * (OPS_PER_ANCHORED_WORD_STEP - 10)
     dists = n * int(np.sum(2 * ks + 1))
@@ -443,22 +454,62 @@ def levcalc_measure(oasm, torch, args, reps: int = 5):
     peak = VALU_PEAK_OPS / 1e12
     achieved = ops / t / 1e12
     # the oracle on a short prefix
-    nb = 2048
+    # (sized from the Eq. 1 cells it evaluates, about 1.3e9: a second or two;
+    # for long patterns, a seeded subset of them over 4 starts)
+    cost = (2 * ks + 1) * ms * (ms + ks)
+    nb = max(4, min(2048, int(1.3e9 // max(1, int(np.sum(cost))))))
+    sub = np.arange(len(w.patterns))
+    if nb * int(np.sum(cost)) > 2.6e9:
+        sub = np.random.default_rng(7).permutation(len(w.patterns))
+        sub = np.sort(sub[:max(1, int(np.searchsorted(np.cumsum(cost[sub]) * nb, 1.3e9)))])
+    span = nb + int(np.max(ms + ks))  # every substring of the first nb starts fits
+
+    def one_pattern(q):
+        p, K, m = w.patterns[q], int(ks[q]), int(ms[q])
+        if nb >= 4 * (m + K):  # the whole prefix in one call
+            return int(np.count_nonzero(oracle.levcalc(p, text[:span], K) != 255))
+        for i in range(nb):  # short samples: one Eq. 1 evaluation per distance
+            for l in range(m - K, m + K + 1):
+                oracle.lev(p, text[i:i + l])
+        return nb * (2 * K + 1)
+
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
-        list(ex.map(lambda j: oracle.levcalc(w.patterns[j], text[:nb], int(ks[j])), range(len(w.patterns))))
+        done = sum(ex.map(one_pattern, sub.tolist()))  # distances the oracle computed
     dt = time.perf_counter() - t0
-    return {"workload": f"LEV CALC for every start: first {n} bytes of the long stream (ACGT) x its "
-                        f"{len(w.patterns)} patterns m~U[16,32], K=3",
+    return {"workload": desc,
             "ms_per_call": round(t * 1e3, 3), "distances_per_s": round(dists / t, 1),
-            "anchored_gcups": round(cells / t / 1e9, 1), "hit_set_entries": h,
+            "anchored_gcups": round(cells / t / 1e9, 1),
             "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 2), "unit": "TOP/s",
                          "frac": round(achieved / peak, 4), "kernel": "k_levcalc", "word_steps": word_steps,
+                         "word_steps_full_columns": full,
                          "ops_per_word_step": f"{OPS_PER_ANCHORED_WORD_STEP} (first word), 10 (others)",
                          "output_bytes": dists, "output_GBps": round(dists / t / 1e9, 1)},
-            "oracle_sample": {"distances_per_s": round(nb * int(np.sum(2 * ks + 1)) / dt, 1),
-                              "cores": min(16, os.cpu_count() or 1),
-                              "sample": f"first {nb} bytes x all {len(w.patterns)} patterns, {dt:.2f} s"}}
+            "oracle_sample": {"distances_per_s": round(done / dt, 1), "cores": min(16, os.cpu_count() or 1),
+                              "sample": f"the first {nb} starts (and, for short patterns, the rest of "
+                                        f"the first {span} bytes) x {sub.size} of the {len(w.patterns)} "
+                                        f"patterns ({done} distances), {dt:.2f} s"}}
+
+
+def levcalc_legs(oasm, torch, args):
+    """LEV CALC on the long stream's 256 one-word patterns (8 MiB) and on the
+    multiword dictionary's 4096 patterns of 16..256 bytes (64 KiB)."""
+    from paper_1712_03560_amd import workloads as W
+
+    out = {}
+    if args.levcalc_leg in ("both", "long"):
+        n1 = int(args.levcalc_bytes)
+        wl = W.long_stream()
+        out = levcalc_measure(oasm, torch, wl, n1, f"LEV CALC for every start: first {n1} bytes of the long "
+                                                   f"stream (ACGT) x its 256 patterns m~U[16,32], K=3")
+        del wl
+    if args.levcalc_leg in ("both", "multiword"):
+        n2 = 1 << 16
+        wm = W.multiword(n=1 << 20)
+        out["multiword"] = levcalc_measure(oasm, torch, wm, n2, f"LEV CALC for every start: first {n2} bytes of "
+                                                                f"the multiword stream x its 4096 patterns "
+                                                                f"m~U[16,256], K=floor(m/10)")
+    return out
 
 
 def main():
@@ -480,7 +531,7 @@ def main():
     from paper_1712_03560_amd import oasm
 
     if args.levcalc_only:
-        print(json.dumps({"levcalc": levcalc_measure(oasm, torch, args)}), flush=True)
+        print(json.dumps({"levcalc": levcalc_legs(oasm, torch, args)}), flush=True)
         return
     if args.calibrate_copy:
         copy_calibration()
@@ -531,7 +582,7 @@ def main():
                                "host_fed": host_fed(oasm, torch, wl)}
         del rl, wl
     if not args.no_levcalc:
-        line["levcalc"] = levcalc_measure(oasm, torch, args)
+        line["levcalc"] = levcalc_legs(oasm, torch, args)
     if not args.no_serving:
         line["serving"] = serving_measure(oasm, torch, args)
         line["p99_chunk_latency_ms"] = line["serving"]["at_0p8_capacity"]["latency_p99_ms"]

@@ -54,15 +54,18 @@ constexpr int kLcStage = (kLcWin + kLcThreads - 1) / kLcThreads;  // window symb
 //   pv' = mh2 | ~(eq | mv | ph2),  mv' = ph2 & (eq | mv).
 // Rows above the last pattern row (the unused top of the last word) receive
 // deltas from below but never feed back into a pattern row.
-template <int W>
-__device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t (&eq)[W]) {
-    uint32_t ph[W], mh[W];
+//
+// anchored_step<N, W> advances only the first N words of the column (the
+// band cutoff below); the carry and shifts out of word N-1 are dropped.
+template <int N, int W>
+__device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
+    uint32_t ph[N], mh[N];
     uint32_t carry = 0;
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
+    for (int w = 0; w < N; ++w) {
         const uint32_t x = eq[w] & pv[w];
         uint32_t u;
-        if (W == 1) {
+        if (N == 1) {
             u = x + pv[w];
         } else {
             const uint64_t s = (uint64_t)x + pv[w] + carry;
@@ -73,9 +76,9 @@ __device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[
         ph[w] = LC_BITOP3(cm[w], o, 0u, ~(LA & LB));          // ~cm | ~o
         mh[w] = LC_BITOP3(pv[w], eq[w], u, LA & (LB | ~LC));  // pv & (eq | ~u)
     }
-    uint32_t npv[W], ncm[W];
+    uint32_t npv[N], ncm[N];
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
+    for (int w = 0; w < N; ++w) {
         const uint32_t ph2 = w == 0 ? (lc_add_self(ph[0]) | 1u) : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
         const uint32_t mh2 = w == 0 ? lc_add_self(mh[0]) : __builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31);
         const uint32_t t = LC_BITOP3(eq[w], cm[w], ph2, ~(LA | ~LB | LC));  // ~(eq | ~cm | ph2)
@@ -83,9 +86,50 @@ __device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[
         ncm[w] = LC_BITOP3(ph2, eq[w], cm[w], ~(LA & (LB | ~LC)));        // ~(ph2 & (eq | ~cm))
     }
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
+    for (int w = 0; w < N; ++w) {
         pv[w] = npv[w];
         cm[w] = ncm[w];
+    }
+}
+
+// Band cutoff of the anchored column (Ukkonen's cutoff on the upper side of
+// the band): after l symbols, C[r][l] >= r - l, so rows r > l + K hold values
+// above K, and a cell above K never leads to a value <= K.  The step that
+// produces column l therefore advances only the words holding rows
+// 1 .. l + K, N(l) = ceil((l + K) / 32) of them; the words above keep their
+// initial +1 vertical deltas until they are first advanced, i.e. values
+// C[32w][l] + (r - 32w) at rows r of word w, upper bounds of the true ones
+// (a value grows by at most 1 per row).  Upper bounds of cells above K change
+// no value <= K, and every output step (l >= m - K) advances all W words.
+// quiet_band<W, 1> runs steps j .. j1-1 (column l = j + 1), word count by
+// word count.
+template <int W, int N>
+__device__ __forceinline__ void quiet_band(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *&wp, uint32_t &j,
+                                           uint32_t j1, uint32_t K, const char *tab) {
+    if constexpr (N <= W) {
+        // steps whose column l = j + 1 needs at most N words: l + K <= 32 N
+        const uint32_t lim_n = 32u * N > K ? 32u * N - K : 0u;  // j + 1 + K <= 32 N  <=>  j < 32 N - K
+        const uint32_t end = N == W ? j1 : (lim_n < j1 ? lim_n : j1);
+        constexpr int U = N <= 2 ? kLcUnroll : N <= 4 ? 2 : 1;  // mask rows read ahead (registers)
+        for (; j + U <= end; j += U, wp += U) {
+            uint32_t eq[U][N];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t *r = reinterpret_cast<const uint32_t *>(tab + wp[u]);
+#pragma unroll
+                for (int w = 0; w < N; ++w) eq[u][w] = r[w];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) anchored_step<N, W>(pv, cm, eq[u]);
+        }
+        for (; j < end; ++j, ++wp) {
+            uint32_t eq[N];
+            const uint32_t *r = reinterpret_cast<const uint32_t *>(tab + wp[0]);
+#pragma unroll
+            for (int w = 0; w < N; ++w) eq[w] = r[w];
+            anchored_step<N, W>(pv, cm, eq);
+        }
+        quiet_band<W, N + 1>(pv, cm, wp, j, j1, K, tab);
     }
 }
 
@@ -156,20 +200,9 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) eq[w] = r[w];
             };
-            // l = j + 1 below m - K: no output yet
+            // l = j + 1 below m - K: no output yet (band cutoff)
             uint32_t j = 0;
-            for (; j + kLcUnroll <= quiet; j += kLcUnroll, wp += kLcUnroll) {
-                uint32_t eq[kLcUnroll][W];
-#pragma unroll
-                for (int u = 0; u < kLcUnroll; ++u) masks(wp[u], eq[u]);
-#pragma unroll
-                for (int u = 0; u < kLcUnroll; ++u) anchored_step<W>(pv, cm, eq[u]);
-            }
-            for (; j < quiet; ++j, ++wp) {
-                uint32_t eq[W];
-                masks(wp[0], eq);
-                anchored_step<W>(pv, cm, eq);
-            }
+            quiet_band<W, 1>(pv, cm, wp, j, quiet, K, tab);
             // l = m - K .. m + K: C[m][l] = l + (sum of the vertical deltas of
             // rows 1..m) = l - m + popcount(pv) + popcount(cm) over those rows
             uint8_t *const o = out + s * width;
@@ -178,7 +211,7 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
             for (uint32_t i = 0; i < width; ++i) {
                 uint32_t eq[W];
                 masks(wp[i], eq);
-                anchored_step<W>(pv, cm, eq);
+                anchored_step<W, W>(pv, cm, eq);
                 const uint32_t l = m - K + i;
                 uint32_t dsum = l - m;  // wraps; the total is >= 0
 #pragma unroll
