@@ -14,7 +14,9 @@ The headline workload is the many-stream one (4096 streams of 1 KiB - 1 MiB,
 launch sequence per stream on the same kernels (`vs_plain`).  The same line
 carries the single 64 MiB stream (`long_stream`), the serving loop's p50/p99
 segment latency (`serving`, `p99_chunk_latency_ms`) and the oracle timed on a
-sample of the headline workload (`cpu_baseline`), and LEV CALC for every
+sample of the headline workload (`cpu_baseline`), the 1 GiB multiword stream
+with 4096 patterns of up to 256 bytes (`multiword`), the 100,000-symbol tiny
+case (`tiny`), and LEV CALC for every
 start of 8 MiB of the long stream and of 64 KiB of the multiword stream
 (`levcalc`).
 
@@ -67,6 +69,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=2, help="timed steps of the per-stream comparison")
     ap.add_argument("--no-plain", action="store_true", help="skip the per-stream launch comparison")
     ap.add_argument("--no-long", action="store_true", help="skip the single-stream leg")
+    ap.add_argument("--no-multiword", action="store_true", help="skip the multiword leg")
+    ap.add_argument("--multiword-leg-bytes", type=int, default=1 << 30, help="stream bytes of the multiword leg")
+    ap.add_argument("--no-tiny", action="store_true", help="skip the tiny leg")
     ap.add_argument("--no-autotune", action="store_true", help="heuristic scan variants instead of measured ones")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel of a step instead of graph replay")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
@@ -581,6 +586,27 @@ def main():
                                "step_breakdown_ms": ml["step_breakdown_ms"], "hits": ml["hits"],
                                "host_fed": host_fed(oasm, torch, wl)}
         del rl, wl
+    if args.workload != "multiword" and not args.no_multiword:
+        from paper_1712_03560_amd import workloads as W
+
+        nb = int(args.multiword_leg_bytes)
+        wm = W.multiword(n=nb)
+        rm = run_steps(oasm, torch, wm, 2, 1, autotune=not args.no_autotune, graphs=not args.no_graphs)
+        mm = summarize(wm, rm, "multiword")
+        line["multiword"] = {"workload": f"multiword: one {nb >> 20} MiB stream of mixture bytes (uniform / printable "
+                                         f"runs, mean 40), 4096 patterns m~U[16,256], K=floor(m/10), "
+                                         f"{len(wm.plants)} planted copies",
+                             "gcups": round(mm["gcups"], 1), "ms_per_step": round(mm["ms_per_step"], 3),
+                             "roofline": mm["roofline"], "step_breakdown_ms": mm["step_breakdown_ms"],
+                             "hits": mm["hits"], "autotune": [x for x in mm["autotune"] if x.startswith("class")]}
+        del rm, wm
+    if args.workload != "tiny" and not args.no_tiny:
+        wt, dt_ = make_workload("tiny", args)
+        rt = run_steps(oasm, torch, wt, 20, 3, autotune=not args.no_autotune, graphs=not args.no_graphs)
+        mt_ = summarize(wt, rt, "tiny")
+        line["tiny"] = {"workload": dt_, "gcups": round(mt_["gcups"], 1), "ms_per_step": round(mt_["ms_per_step"], 3),
+                        "scan_ms_per_step": mt_["roofline"]["scan_ms_per_step"], "hits": mt_["hits"]}
+        del rt, wt
     if not args.no_levcalc:
         line["levcalc"] = levcalc_legs(oasm, torch, args)
     if not args.no_serving:

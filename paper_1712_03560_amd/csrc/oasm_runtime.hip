@@ -271,10 +271,11 @@ size_t put(std::vector<uint8_t> &blob, const std::vector<T> &v) {
 
 uint32_t choose_chunk(oasm_ctx *c, uint64_t bytes) {
     if (c->cfg.chunk_bytes) return std::max<uint32_t>(64, c->cfg.chunk_bytes & ~63u);
-    // enough work items to fill 256 CUs several times over
+    // enough work items to fill 256 CUs several times over; a chunk is at
+    // least four look-backs long (so the look-back adds at most a quarter)
     const uint64_t target_items = 16384;
     uint64_t per = bytes * std::max<uint32_t>(1, c->ntiles) / target_items;
-    per = std::max<uint64_t>(per, 2048);
+    per = std::max<uint64_t>(per, std::max<uint64_t>(256, 4ull * c->lookback));
     per = std::min<uint64_t>(per, 1u << 16);
     return (uint32_t)((per + 63) & ~63ull);
 }
