@@ -74,3 +74,38 @@ def test_alone_equals_mix_equals_oracle(budget):
     # oracle on every session's concatenated bytes
     streams = {sid: session_bytes(pool, segs, sid) for sid in sids}
     compare(mix, streams, pats, ks, label=f"serving-budget{budget}")
+
+
+def test_serving_full_size_sampled_sessions():
+    """The serving workload at the benchmark's size and settings (10,000
+    sessions, 2048 patterns of 16..128 mixture bytes, K = floor(m/10), U[1,64]
+    KiB segments arriving at 20 GB/s over 50 ms, a 64 MiB budget, autotuned
+    variants), with 20,000 mutated pattern copies planted in the byte pool:
+    12 seeded sessions against the oracle on their concatenated bytes (every
+    pattern), and 2 of them alone against the mix."""
+    pats, ks = W.serving_dictionary()
+    pool = W.serving_pool(1 << 26)
+    # mutated copies of the patterns in the pool, so that the sessions hold hits
+    W.plant(np.random.default_rng(23), pool, pats, 20_000, ks, W.LETTERS_MIX)
+    sess, off, ln, t = W.serving_arrivals(10_000, 0.05, 20.0, pool.size)
+    segs = np.zeros(t.size, dtype=oasm.SEG_DTYPE)
+    segs["stream"], segs["offset"], segs["len"], segs["arrival_s"] = sess, off, ln, t
+    dpool = torch.from_numpy(pool).cuda()
+    print(f"[serving] full size: {segs.size} segments, {int(ln.sum())} bytes", file=sys.stderr, flush=True)
+    with oasm.Matcher(pats, ks, mem_budget=64 << 20, autotune=True) as mt:
+        rep, lat = mt.serve(segs, dpool)
+        mix = mt.results()
+    assert rep["segments"] == segs.size and rep["deferred"] > 0
+    sids = sorted(set(int(x) for x in segs["stream"]))
+    pick = [int(x) for x in np.random.default_rng(17).choice(sids, 12, replace=False)]
+    for sid in pick[:2]:
+        with oasm.Matcher(pats, ks, autotune=True) as mt:
+            mt.serve(segs[segs["stream"] == sid].copy(), dpool, want_latency=False)
+            alone = mt.results()
+        a_raw, a_occ = rows_of(alone, sid)
+        m_raw, m_occ = rows_of(mix, sid)
+        assert np.array_equal(a_raw, m_raw) and np.array_equal(a_occ, m_occ), f"session {sid} differs alone/mix"
+    streams = {sid: session_bytes(pool, segs, sid) for sid in pick}
+    pairs = [(sid, p) for sid in pick for p in range(len(pats))]
+    n_raw, n_occ = compare(mix, streams, pats, ks, pairs=pairs, label="serving-full-size")
+    assert n_raw > 50 and n_occ > 10
