@@ -14,6 +14,8 @@
 // (64 starts x (2K+1) bytes) is one contiguous run.
 //
 // Integer bit-vector work only; no matrix cores.
+#include <type_traits>
+
 #include "oasm_device.h"
 #include "oasm_levcalc.h"
 
@@ -38,6 +40,16 @@ static __device__ __forceinline__ uint32_t lc_bcnt(uint32_t x, uint32_t acc) {
     return r;
 }
 
+// popcount(x) + acc with acc a scalar (uniform) value
+static __device__ __forceinline__ uint32_t lc_bcnt_s(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "s"(acc));
+    return r;
+}
+
+// Fourth word of a raw (untyped, byte-addressed) buffer resource on gfx9-family
+// parts: a valid 32-bit data format, so that stores inside the size are kept.
+constexpr int kLcRsrcWord3 = 0x00020000;
 constexpr int kLcThreads = 256;                   // starts per block pass
 constexpr int kLcWin = kLcThreads + 256 + 64;     // + m_max + K_max - 1 symbols, rounded up
 constexpr int kLcUnroll = 4;                      // symbols per unrolled group
@@ -204,23 +216,42 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
             uint32_t j = 0;
             quiet_band<W, 1>(pv, cm, wp, j, quiet, K, tab);
             // l = m - K .. m + K: C[m][l] = l + (sum of the vertical deltas of
-            // rows 1..m) = l - m + popcount(pv) + popcount(cm) over those rows
-            uint8_t *const o = out + s * width;
-            const uint64_t room64 = a.n - s;  // symbols from s to the end
-            const uint32_t room = room64 < 0xFFFFFFFFull ? (uint32_t)room64 : 0xFFFFFFFFu;
-            for (uint32_t i = 0; i < width; ++i) {
-                uint32_t eq[W];
-                masks(wp[i], eq);
-                anchored_step<W, W>(pv, cm, eq);
-                const uint32_t l = m - K + i;
-                uint32_t dsum = l - m;  // wraps; the total is >= 0
+            // rows 1..m) = l - m + popcount(pv) + popcount(cm) over those rows.
+            // The pass's output (256 starts x width bytes, pattern-major
+            // layout) is one buffer: byte i of start s is at tid * width + i,
+            // the lane part in a vector register and i in a scalar one, so a
+            // store needs no vector address arithmetic; the buffer's size
+            // bounds every store.
+            const uint64_t left = a.n - base;
+            const uint32_t pass_bytes = (uint32_t)(left < (uint64_t)kLcThreads ? left : kLcThreads) * width;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(out + base * width, (short)0, pass_bytes, kLcRsrcWord3);
+            const uint32_t voff = tid * width;
+            auto outputs = [&](auto tail) {
+                constexpr bool TAIL = decltype(tail)::value;
+                const uint32_t room = TAIL ? (uint32_t)(a.n - s) : 0u;  // symbols from s to the end
+                for (uint32_t i = 0; i < width; ++i) {
+                    uint32_t eq[W];
+                    masks(wp[i], eq);
+                    anchored_step<W, W>(pv, cm, eq);
+                    const uint32_t l = m - K + i;
+                    uint32_t dsum = lc_bcnt_s(pv[0] & (W == 1 ? lmask : ~0u), l - m);  // wraps; the total is >= 0
+                    dsum = lc_bcnt(cm[0] & (W == 1 ? lmask : ~0u), dsum);
 #pragma unroll
-                for (int w = 0; w < W - 1; ++w) dsum = lc_bcnt(cm[w], lc_bcnt(pv[w], dsum));
-                dsum = lc_bcnt(cm[W - 1] & lmask, lc_bcnt(pv[W - 1] & lmask, dsum));
-                uint32_t v = dsum < K + 1 ? dsum : K + 1;
-                if (l > room) v = 255u;  // t[s, l] runs past the end
-                o[i] = (uint8_t)v;
-            }
+                    for (int w = 1; w < W; ++w) {
+                        dsum = lc_bcnt(pv[w] & (w == W - 1 ? lmask : ~0u), dsum);
+                        dsum = lc_bcnt(cm[w] & (w == W - 1 ? lmask : ~0u), dsum);
+                    }
+                    uint32_t v = dsum < K + 1 ? dsum : K + 1;
+                    if (TAIL && l > room) v = 255u;  // t[s, l] runs past the end
+                    __builtin_amdgcn_raw_buffer_store_b8((uint8_t)v, rs, voff, i, 0);
+                }
+            };
+            // a pass whose every substring ends inside the text needs no end test
+            if (base + kLcThreads + steps - 1 <= a.n)
+                outputs(std::false_type{});
+            else
+                outputs(std::true_type{});
         }
     }
 }
