@@ -188,6 +188,41 @@ __device__ __forceinline__ const uint32_t *at_bytes(const uint32_t *p, uint32_t 
     return reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(p) + off);
 }
 
+// A tile's mask image in global memory, read through a buffer resource: the
+// symbol's row offset goes in a scalar register and the lane's offset in a
+// vector one, so a read costs no vector address arithmetic (a 64-bit vector
+// address add issues at a fraction of the full rate).  Reads beyond the
+// image's size return 0.
+constexpr int kRsrcWord3 = 0x00020000;  // raw (byte-addressed) buffer, 32-bit data format
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const uint32_t *img, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t *>(img), (short)0, bytes, kRsrcWord3);
+}
+
+// n consecutive words at byte offset voff + soff of the image
+template <int N>
+__device__ __forceinline__ void gload(__amdgpu_buffer_rsrc_t rs, uint32_t voff, uint32_t soff, uint32_t *dst) {
+    if constexpr (N == 1) {
+        dst[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0);
+    } else if constexpr (N == 2) {
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+        dst[0] = v.x;
+        dst[1] = v.y;
+    } else {
+        static_assert(N % 4 == 0, "1, 2 or a multiple of 4 words");
+#pragma unroll
+        for (int q = 0; q < N / 4; ++q) {
+            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16 * q, soff, 0);
+            dst[4 * q] = v.x;
+            dst[4 * q + 1] = v.y;
+            dst[4 * q + 2] = v.z;
+            dst[4 * q + 3] = v.w;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ cutoff
 // Word cutoff for multi-word columns (Ukkonen's cutoff, kept per 32-row word
 // as in Myers' block-based algorithm, but decided once per group of 4
@@ -256,17 +291,23 @@ __device__ __forceinline__ uint32_t cut_decide(const uint32_t (&pv)[W], const ui
 // word w for the 64 lanes are 256 contiguous bytes, so reading only the
 // active words stays one coalesced access per word (a lane-major row of
 // 8 words would make every partial read touch 16 cache lines).
-template <int W, int N>
+template <int W, int N, bool LDS>
 __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img,
-                                              uint32_t lane, uint32_t cur, uint32_t kc, uint32_t mask,
-                                              uint32_t kl) {
+                                              __amdgpu_buffer_rsrc_t rs, uint32_t lane, uint32_t cur, uint32_t kc,
+                                              uint32_t mask, uint32_t kl) {
     uint32_t e[kScanGroup][N];
     const uint32_t *row = img + lane;
 #pragma unroll
     for (int s = 0; s < kScanGroup; ++s) {
-        const uint32_t *r = at_bytes(row, row_off(cur, s, W * kWave * 4));
+        if constexpr (LDS) {
+            const uint32_t *r = at_bytes(row, row_off(cur, s, W * kWave * 4));
 #pragma unroll
-        for (int w = 0; w < N; ++w) e[s][w] = r[w * kWave];
+            for (int w = 0; w < N; ++w) e[s][w] = r[w * kWave];
+        } else {
+            const uint32_t off = row_off(cur, s, W * kWave * 4);
+#pragma unroll
+            for (int w = 0; w < N; ++w) gload<1>(rs, lane * 4, off + w * kWave * 4, &e[s][w]);
+        }
     }
 #pragma unroll
     for (int s = 0; s < kScanGroup; ++s) column_step_n<N, W>(pv, cm, e[s]);
@@ -280,17 +321,17 @@ __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[
 // group at `pos` and is advanced with it; `wsteps` (which starts from every
 // word stepped over every reported symbol) loses the W - N inactive words
 // over the run's reported symbols.
-template <int W, int N>
-__device__ __forceinline__ uint32_t cut_run(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img, uint32_t lane,
-                                            const const_u32 *text, uint32_t &next, uint32_t &pos, uint32_t len,
-                                            uint32_t lb, uint32_t kc, uint32_t mask, uint32_t kl, uint64_t &wsteps,
-                                            uint32_t nact) {
+template <int W, int N, bool LDS>
+__device__ __forceinline__ uint32_t cut_run(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img,
+                                            __amdgpu_buffer_rsrc_t rs, uint32_t lane, const const_u32 *text,
+                                            uint32_t &next, uint32_t &pos, uint32_t len, uint32_t lb, uint32_t kc,
+                                            uint32_t mask, uint32_t kl, uint64_t &wsteps, uint32_t nact) {
     uint32_t ynew;
     const uint32_t first = pos;
     do {
         const uint32_t cur = next;
         next = text[(pos >> 2) + 1];
-        ynew = cut_group<W, N>(pv, cm, img, lane, cur, kc, mask, kl);
+        ynew = cut_group<W, N, LDS>(pv, cm, img, rs, lane, cur, kc, mask, kl);
         pos += kScanGroup;
     } while (ynew == N - 1 && pos < len);
     const uint32_t s0 = first > lb ? first : lb, s1 = pos < len ? pos : len;
@@ -401,6 +442,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
     const uint32_t lane_off = lane * PWS;
     if (len > lb) wsteps = (uint64_t)(len - lb) * (W * nact);
     const uint32_t *img = LDSPEQ ? lds_img : gimg;
+    const __amdgpu_buffer_rsrc_t rs = image_rsrc(gimg, a.nclass * kWave * (CUT ? W : PWS) * 4);
 
     uint32_t y = W - 1;  // last active word (CUT); every word starts active
     uint32_t next = text[0];
@@ -414,8 +456,8 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 #define OASM_CUT_CASE(n)                                                                                         \
     case n:                                                                                                      \
         if constexpr (n + 1 < W)                                                                                 \
-            ynew = cut_run<W, n + 1>(pv[0], mv[0], img, lane, text, next, pos, len, lb, kc, lmask, kl, wsteps, \
-                                     nact);                                                                      \
+            ynew = cut_run<W, n + 1, LDSPEQ>(pv[0], mv[0], img, rs, lane, text, next, pos, len, lb, kc, lmask, \
+                                             kl, wsteps, nact);                                                  \
         break;
                 OASM_CUT_CASE(0)
                 OASM_CUT_CASE(1)
@@ -444,11 +486,19 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 #pragma unroll
         for (int s = 0; s < kScanGroup; ++s) {
             if constexpr (CUT) {  // word-major image
-                const uint32_t *r = at_bytes(img + lane, row_off(cur, s, W * kWave * 4));
+                if constexpr (LDSPEQ) {
+                    const uint32_t *r = at_bytes(img + lane, row_off(cur, s, W * kWave * 4));
 #pragma unroll
-                for (int w = 0; w < W; ++w) e[s].v[w] = r[w * kWave];
-            } else {
+                    for (int w = 0; w < W; ++w) e[s].v[w] = r[w * kWave];
+                } else {
+                    const uint32_t off = row_off(cur, s, W * kWave * 4);
+#pragma unroll
+                    for (int w = 0; w < W; ++w) gload<1>(rs, lane * 4, off + w * kWave * 4, &e[s].v[w]);
+                }
+            } else if constexpr (LDSPEQ) {
                 e[s] = *reinterpret_cast<const Words<PWS> *>(at_bytes(img + lane_off, row_off(cur, s, kWave * PWS * 4)));
+            } else {
+                gload<PWS>(rs, lane_off * 4, row_off(cur, s, kWave * PWS * 4), e[s].v);
             }
         }
         uint32_t pv0[P][W], mv0[P][W];
