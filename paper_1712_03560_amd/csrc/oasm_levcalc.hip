@@ -80,9 +80,8 @@ __device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[
         if (N == 1) {
             u = x + pv[w];
         } else {
-            const uint64_t s = (uint64_t)x + pv[w] + carry;
-            u = (uint32_t)s;
-            carry = (uint32_t)(s >> 32);
+            // one add-with-carry per word (v_add_co / v_addc_co)
+            u = __builtin_addc(x, pv[w], carry, &carry);
         }
         const uint32_t o = LC_BITOP3(u, pv[w], eq[w], LA | LB | LC);
         ph[w] = LC_BITOP3(cm[w], o, 0u, ~(LA & LB));          // ~cm | ~o
