@@ -97,10 +97,10 @@ def test_fig1_strings():
 
 # ---------------------------------------------------------------- Less Naive
 def test_sellers_last_row_is_min_over_starts_exhaustive():
-    es = EditSearch("AB", 7)
-    for p in strings("AB", 1, 4):
+    es = EditSearch("AB", 10)
+    for p in strings("AB", 1, 5):
         dp = es.dist_from(p)
-        for t in strings("AB", 0, 7):
+        for t in strings("AB", 0, 10):
             D = oracle.sellers_column(p.encode(), t.encode())
             for e in range(len(t)):
                 # substrings t[s..e], including the empty one (s = e + 1)
@@ -125,9 +125,9 @@ def test_raw_hits_and_hit_set_exhaustive():
     """Raw ends, H by definition (Eq. 2) and the identity between them:
     the ends of H are exactly the raw-hit ends and D[e] is the smallest k
     among the H records ending at e."""
-    es = EditSearch("AB", 7)
-    for p in strings("AB", 1, 4):
-        for t in strings("AB", 0, 7):
+    es = EditSearch("AB", 9)
+    for p in strings("AB", 1, 5):
+        for t in strings("AB", 0, 9):
             for K in range(len(p)):
                 ends, dists = oracle.raw_hits(p.encode(), t.encode(), K)
                 H = _brute_h(es, p, t, K)
