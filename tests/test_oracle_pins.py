@@ -237,45 +237,57 @@ def _random_case(rng, mmax=9, nmax=90, sigma_max=4):
     return p, t, K
 
 
+def _check_filter_invariants(p, t, K):
+    """Invariants (i)-(v) of the filter and Table 1's ordering on one case."""
+    m = len(p)
+    r = oracle.run_pair(p, t, K)
+    Hset = {(int(a), int(b)): int(c) for a, b, c in zip(*r.H)}
+    fr = oracle.filter_hits(*r.H, K, len(t))
+    ev = fr.events
+    d_bound = m * (K + 1) + K * (K - 1) // 2
+    emissions = {}
+    for e in ev.tolist():
+        emissions.setdefault(e[0], []).append(e)
+    prev = []
+    for pos, evs in sorted(emissions.items()):
+        best = evs[0]
+        assert best[6] == 1  # (ii) the best is always accepted
+        assert best[0] == best[2] + best[3] - 1  # emitted when the best ends
+        assert [e[1] for e in evs] == sorted(e[1] for e in evs)
+        acc = 0
+        for e in evs:
+            _, lvl, s, ln, rr, a0, ok = e
+            assert a0 == acc
+            assert Hset[(s, ln)] == lvl  # (i) an H record with its own k
+            assert rr == pos - s + 1  # counter = symbols seen since its start
+            if e is not best:
+                assert ok == int(rr - acc > ln)  # Eq. 3
+                if ok:  # (iii) disjoint from the best
+                    assert s + ln - 1 < best[2] or s > best[2] + best[3] - 1
+            if ok:
+                acc += ln
+                assert pos - s + 1 <= d_bound  # (v) delay bound d of Section 4.3
+        occs = [(e[2], e[3]) for e in evs if e[6]]
+        for s, ln in occs:  # (iv) disjoint from earlier emissions
+            for s2, l2 in prev:
+                assert s > s2 + l2 - 1 or s + ln - 1 < s2
+        prev += occs
+    # the ordering Table 1 shows: |S| <= #raw ends <= |H|
+    assert len(r.occ) <= len(r.ends) <= len(Hset)
+
+
 def test_filter_invariants_random():
     rng = np.random.default_rng(7)
     for trial in range(1500):
-        p, t, K = _random_case(rng)
-        m = len(p)
-        r = oracle.run_pair(p, t, K)
-        Hset = {(int(a), int(b)): int(c) for a, b, c in zip(*r.H)}
-        fr = oracle.filter_hits(*r.H, K, len(t))
-        ev = fr.events
-        d_bound = m * (K + 1) + K * (K - 1) // 2
-        emissions = {}
-        for e in ev.tolist():
-            emissions.setdefault(e[0], []).append(e)
-        prev = []
-        for pos, evs in sorted(emissions.items()):
-            best = evs[0]
-            assert best[6] == 1  # (ii) the best is always accepted
-            assert best[0] == best[2] + best[3] - 1  # emitted when the best ends
-            assert [e[1] for e in evs] == sorted(e[1] for e in evs)
-            acc = 0
-            for e in evs:
-                _, lvl, s, ln, rr, a0, ok = e
-                assert a0 == acc
-                assert Hset[(s, ln)] == lvl  # (i) an H record with its own k
-                assert rr == pos - s + 1  # counter = symbols seen since its start
-                if e is not best:
-                    assert ok == int(rr - acc > ln)  # Eq. 3
-                    if ok:  # (iii) disjoint from the best
-                        assert s + ln - 1 < best[2] or s > best[2] + best[3] - 1
-                if ok:
-                    acc += ln
-                    assert pos - s + 1 <= d_bound  # (v) delay bound d of Section 4.3
-            occs = [(e[2], e[3]) for e in evs if e[6]]
-            for s, ln in occs:  # (iv) disjoint from earlier emissions
-                for s2, l2 in prev:
-                    assert s > s2 + l2 - 1 or s + ln - 1 < s2
-            prev += occs
-        # the ordering Table 1 shows: |S| <= #raw ends <= |H|
-        assert len(r.occ) <= len(r.ends) <= len(Hset)
+        _check_filter_invariants(*_random_case(rng))
+
+
+def test_filter_invariants_exhaustive():
+    """The same invariants for every p in {A,B}^1..4, t in {A,B}^0..9 and K < m."""
+    for p in strings("AB", 1, 4):
+        for t in strings("AB", 0, 9):
+            for K in range(len(p)):
+                _check_filter_invariants(p.encode(), t.encode(), K)
 
 
 def test_filter_segments_are_independent():
