@@ -122,3 +122,35 @@ def test_byte_by_byte_feeds():
             mt.sync()
         res = mt.results()
     check_against_oracle(res, pats, ks, t)
+
+
+def test_feeds_from_many_threads():
+    """Calls on one context are serialised inside the library: eight host
+    threads feed their own streams in pieces at the same time (ctypes lets
+    them run concurrently), then one sync; every stream equals the oracle."""
+    import threading
+
+    w = W.small_random(33, 6_000, 10, 6, 40, b"ACGT", 4, n_plants=30, n_streams=8)
+    say("8 threads feeding 8 streams concurrently")
+    errors = []
+    with oasm.Matcher(w.patterns, w.ks) as mt:
+        def worker(sid, t):
+            try:
+                cuts = list(range(0, t.size, 397)) + [t.size]
+                for a, b in zip(cuts[:-1], cuts[1:]):
+                    mt.feed(sid, t[a:b], last=b == t.size)
+                if t.size == 0:
+                    mt.feed(sid, t, last=True)
+            except Exception as e:  # reported below
+                errors.append(e)
+
+        threads = [threading.Thread(target=worker, args=(100 + i, t)) for i, t in enumerate(w.streams)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        assert not errors, errors
+        mt.sync()
+        res = mt.results()
+    for i, t in enumerate(w.streams):
+        check_against_oracle(res, w.patterns, w.ks, t, stream=100 + i)
