@@ -106,9 +106,8 @@ __device__ __forceinline__ void column_step_n(uint32_t (&pv)[W], uint32_t (&cm)[
         if (N == 1) {
             u = x + pv[w];
         } else {
-            const uint64_t s = (uint64_t)x + pv[w] + carry;
-            u = (uint32_t)s;
-            carry = (uint32_t)(s >> 32);
+            // one add-with-carry per word (v_add_co / v_addc_co)
+            u = __builtin_addc(x, pv[w], carry, &carry);
         }
         const uint32_t o = BITOP3(u, pv[w], eq[w], TA | TB | TC);
         ph[w] = BITOP3(cm[w], o, 0u, ~(TA & TB));           // ~cm | ~o
