@@ -85,6 +85,7 @@ def parse():
     ap.add_argument("--no-levcalc", action="store_true", help="skip the LEV CALC (every start) leg")
     ap.add_argument("--levcalc-only", action="store_true", help="run only the LEV CALC leg")
     ap.add_argument("--levcalc-leg", default="both", choices=["both", "long", "multiword"])
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--levcalc-bytes", type=int, default=1 << 23, help="text bytes of the LEV CALC leg")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy three times and a one-tile scan of the "
@@ -537,6 +538,9 @@ def main():
 
     if args.levcalc_only:
         print(json.dumps({"levcalc": levcalc_legs(oasm, torch, args)}), flush=True)
+        return
+    if args.serving_only:
+        print(json.dumps({"serving": serving_measure(oasm, torch, args)}), flush=True)
         return
     if args.calibrate_copy:
         copy_calibration()

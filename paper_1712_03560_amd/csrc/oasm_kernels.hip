@@ -13,6 +13,7 @@
 #include <utility>
 
 #include "oasm_device.h"
+#include "oasm_staging.h"
 
 namespace oasm {
 
@@ -161,6 +162,31 @@ hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *c
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ tail moves
+// One workgroup per stream.  The destination lies below the source, so the
+// move goes forward in chunks of 4 KiB, each read whole into LDS before any
+// of it is written: a chunk's writes land below every byte a later chunk
+// reads.
+__global__ void __launch_bounds__(256) k_tail_moves(TailMoveBatch b) {
+    __shared__ uint8_t tmp[4096];
+    const TailMove mv = b.m[blockIdx.x];
+    const uint8_t *src = mv.buf + mv.drop;
+    for (uint32_t c0 = 0; c0 < mv.keep; c0 += 4096) {
+        const uint32_t len = min(4096u, mv.keep - c0);
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) tmp[i] = src[c0 + i];
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) mv.buf[c0 + i] = tmp[i];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_tail_moves(const TailMoveBatch &b, uint32_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    if (n > kTailMovesPerLaunch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_tail_moves, dim3(n), dim3(256), 0, st, b);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ ordering
 // The hit ends of a step are put in (stream, pattern, end) order without a
 // dense count table: carried ends first, then every scan item's records in
@@ -270,7 +296,7 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t *_
     __shared__ uint32_t base[256];
     const uint32_t n = dev_n(dn);
     __shared__ uint32_t wc[4][256];
-    const uint32_t t = threadIdx.x, lane = lane_id(), wave = t >> 6;
+    const uint32_t t = threadIdx.x, wave = t >> 6;
     base[t] = offs[t * nblocks + blockIdx.x];
     wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
     __syncthreads();

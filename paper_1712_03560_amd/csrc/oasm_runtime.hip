@@ -32,6 +32,7 @@
 #include "../../include/oasm_gpu.h"
 #include "oasm_internal.h"
 #include "oasm_levcalc.h"
+#include "oasm_staging.h"
 
 using namespace oasm;
 
@@ -206,6 +207,10 @@ struct oasm_ctx {
     // was written by this context (cleared at allocation, then mapped
     // symbols), so they hold valid symbol classes only.
     std::multimap<size_t, uint8_t *> pool;  // released staging buffers by capacity
+    std::vector<uint8_t *> slabs;           // staging slabs, each cleared once when allocated
+    std::unordered_set<uint8_t *> own_alloc;  // staging buffers with an allocation of their own
+    uint8_t *slab_cur = nullptr;            // unused part of the newest slab
+    size_t slab_left = 0;
 };
 
 namespace {
@@ -663,7 +668,9 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     c->ncarry = ncarry_out;
     if (ncarry_out) c->carry_cur = cout;  // nothing carried: keep the buffers (and the step's shape) as they are
     // stream bookkeeping (matched streams only): keep a look-back tail of
-    // each stream's symbols
+    // each stream's symbols, the moves batched into few launches
+    TailMoveBatch moves;
+    uint32_t nmoves = 0;
     for (uint32_t si : which) {
         StreamState &s = c->streams[si];
         c->stats.bytes_scanned += s.valid - s.scanned;
@@ -687,18 +694,21 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         const size_t keep = std::min<size_t>(s.valid, c->lookback + 4);
         if (keep < s.valid) {
             const size_t drop = s.valid - keep;
-            // move the tail to the front (through the raw_in scratch when the ranges overlap)
-            if (drop >= keep) {
-                ck(hipMemcpyAsync(s.sym, s.sym + drop, keep, hipMemcpyDeviceToDevice, st), "tail move");
+            if (drop <= UINT32_MAX && keep <= UINT32_MAX) {
+                moves.m[nmoves++] = TailMove{s.sym, (uint32_t)drop, (uint32_t)keep};
+                if (nmoves == kTailMovesPerLaunch) {
+                    ck(launch_tail_moves(moves, nmoves, st), "tail moves");
+                    nmoves = 0;
+                }
             } else {
-                c->raw_in.ensure(keep + kPad, st);
-                ck(hipMemcpyAsync(c->raw_in.p, s.sym + drop, keep, hipMemcpyDeviceToDevice, st), "tail move");
-                ck(hipMemcpyAsync(s.sym, c->raw_in.p, keep, hipMemcpyDeviceToDevice, st), "tail move");
+                // a drop beyond 4 GiB: the ranges cannot overlap (keep is a look-back tail)
+                ck(hipMemcpyAsync(s.sym, s.sym + drop, keep, hipMemcpyDeviceToDevice, st), "tail move");
             }
             s.base_abs += drop;
             s.valid = s.scanned = keep;
         }
     }
+    ck(launch_tail_moves(moves, nmoves, st), "tail moves");
     c->stats.raw_hits += new_raw;
     c->stats.occurrences += nocc;
     c->stats.syncs++;
@@ -756,8 +766,39 @@ StreamState &get_stream(oasm_ctx *c, uint64_t id, bool create) {
 
 bool is_finished(const oasm_ctx *c, uint64_t id) { return c->closed_ids.count(id) != 0; }
 
+// Staging buffers up to a quarter slab are carved from slabs of kSlab bytes,
+// allocated and cleared once: a new stream then costs neither an allocation
+// nor a clear of its own.  Larger ones get an allocation of their own.
+constexpr size_t kSlab = size_t(16) << 20;
+
+// A device allocation cleared to class 0 (the scan's last group reads up to
+// 8 symbols past a stream's end before masking their ends out: every byte
+// must be a valid symbol class).  On failure the pooled buffers that have an
+// allocation of their own go back to the device and it tries once more.
+uint8_t *alloc_cleared(oasm_ctx *c, size_t bytes) {
+    uint8_t *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        ck(hipStreamSynchronize(c->st), "sync before pool release");
+        for (auto it = c->pool.begin(); it != c->pool.end();) {
+            if (c->own_alloc.erase(it->second)) {
+                ck(hipFree(it->second), "hipFree pool");
+                it = c->pool.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    ck(hipMemsetAsync(p, 0, bytes, c->st), "staging clear");
+    return p;
+}
+
 // A staging buffer of at least `need` bytes: the smallest pooled one that
-// fits, else a new allocation cleared to class 0.
+// fits, else a piece of a slab, else an allocation of its own.
 uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap) {
     auto it = c->pool.lower_bound(need);
     if (it != c->pool.end()) {
@@ -766,22 +807,27 @@ uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap) {
         c->pool.erase(it);
         return p;
     }
-    size_t want = (need + 255) & ~size_t(255);
-    uint8_t *p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess) {
-        (void)hipGetLastError();
-        // give the pool back to the device and try once more
-        ck(hipStreamSynchronize(c->st), "sync before pool release");
-        for (auto &b : c->pool) ck(hipFree(b.second), "hipFree pool");
-        c->pool.clear();
-        if (hipMalloc(&p, want) != hipSuccess) {
-            (void)hipGetLastError();
-            return nullptr;
+    const size_t want = (need + 255) & ~size_t(255);
+    if (want <= kSlab / 4) {
+        if (want > c->slab_left) {
+            if (uint8_t *sl = alloc_cleared(c, kSlab)) {
+                if (c->slab_left) c->pool.emplace(c->slab_left, c->slab_cur);  // the old slab's rest
+                c->slabs.push_back(sl);
+                c->slab_cur = sl;
+                c->slab_left = kSlab;
+            }
+        }
+        if (want <= c->slab_left) {
+            uint8_t *p = c->slab_cur;
+            c->slab_cur += want;
+            c->slab_left -= want;
+            cap = want;
+            return p;
         }
     }
-    // the scan's last group reads up to 8 symbols past the end before masking
-    // their ends out: every byte must be a valid symbol class
-    ck(hipMemsetAsync(p, 0, want, c->st), "staging clear");
+    uint8_t *p = alloc_cleared(c, want);
+    if (!p) return nullptr;
+    c->own_alloc.insert(p);
     cap = want;
     return p;
 }
@@ -1593,9 +1639,9 @@ void oasm_destroy(oasm_ctx *c) {
         (void)hipEventSynchronize(c->ev_lc);
         (void)hipEventDestroy(c->ev_lc);
     }
-    for (auto &s : c->streams)
-        if (s.sym) (void)hipFree(s.sym);
-    for (auto &b : c->pool) (void)hipFree(b.second);
+    // every staging buffer is a slab piece or an allocation of its own
+    for (uint8_t *p : c->own_alloc) (void)hipFree(p);
+    for (uint8_t *p : c->slabs) (void)hipFree(p);
     DevBuf *bufs[] = {&c->d_pats, &c->d_slot_pat, &c->d_tiles, &c->d_peq, &c->d_rpeq, &c->d_class, &c->d_patbytes,
                       &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->offsets, &c->item_rec,
                       &c->item_cnt, &c->ctl, &c->scan_tmp, &c->sort_key, &c->sort_val, &c->sort_end, &c->sort_tmp,
