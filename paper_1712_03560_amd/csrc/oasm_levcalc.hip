@@ -144,14 +144,22 @@ __device__ __forceinline__ void quiet_band(uint32_t (&pv)[W], uint32_t (&cm)[W],
     }
 }
 
+// Mask rows are lcStride(W) = W | 1 words apart.  The lanes of a wave each
+// read the row of their own text byte: with an odd stride the rows of
+// different bytes spread over all of the LDS banks, while a stride of
+// 2^a * b words (b odd) would fold them onto a 1/2^a share of the banks.
+constexpr int lcStride(int W) { return W | 1; }
+
 // Block (x, y): pattern pat_ids[y] (strided by gridDim.y), starts in passes
 // of 256 (strided by gridDim.x).  The window holds, per text symbol, the
-// byte offset of its row in the mask table (byte * W * 4), so a mask read
-// needs no address arithmetic.  Every index is bounded: the window holds
-// 256 + m + K - 1 <= kLcWin symbols, a mask row is byte * W + word.
+// byte offset of its row in the mask table (byte * lcStride(W) * 4), so a
+// mask read needs no address arithmetic.  Every index is bounded: the window
+// holds 256 + m + K - 1 <= kLcWin symbols, a mask row is
+// byte * lcStride(W) + word with word < W.
 template <int W>
 __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
-    __shared__ uint32_t peq[256 * W];
+    constexpr int S = lcStride(W);
+    __shared__ uint32_t peq[256 * S];
     __shared__ uint32_t win[kLcWin];
     const uint32_t tid = threadIdx.x;
     const uint64_t passes = (a.n + kLcThreads - 1) / kLcThreads;
@@ -168,9 +176,9 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
         const uint8_t *const pb = a.pat_bytes + d.off;
 
         __syncthreads();  // the previous pattern's masks and window are no longer read
-        for (uint32_t i = tid; i < 256u * W; i += kLcThreads) peq[i] = 0u;
+        for (uint32_t i = tid; i < 256u * S; i += kLcThreads) peq[i] = 0u;
         __syncthreads();
-        for (uint32_t r = tid; r < m; r += kLcThreads) atomicOr(&peq[pb[r] * W + (r >> 5)], 1u << (r & 31));
+        for (uint32_t r = tid; r < m; r += kLcThreads) atomicOr(&peq[pb[r] * S + (r >> 5)], 1u << (r & 31));
 
         // the window of the next pass is loaded into registers while the
         // current one is matched (software pipelining of the text reads)
@@ -191,7 +199,7 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
 #pragma unroll
             for (int k = 0; k < kLcStage; ++k) {
                 const uint32_t i = tid + k * kLcThreads;
-                if (i < wlen) win[i] = nxt[k] * (W * 4u);
+                if (i < wlen) win[i] = nxt[k] * (S * 4u);
             }
             __syncthreads();
             fetch(pass + gridDim.x);
