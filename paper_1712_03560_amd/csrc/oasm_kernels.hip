@@ -162,28 +162,27 @@ hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *c
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ tail moves
-// One workgroup per stream.  The destination lies below the source, so the
-// move goes forward in chunks of 4 KiB, each read whole into LDS before any
-// of it is written: a chunk's writes land below every byte a later chunk
-// reads.
-__global__ void __launch_bounds__(256) k_tail_moves(TailMoveBatch b) {
+// ------------------------------------------------------------------ staging moves
+// One workgroup per move.  The move goes forward in chunks of 4 KiB, each
+// read whole into LDS before any of it is written; when the ranges overlap
+// the destination lies below the source, so a chunk's writes land below
+// every byte a later chunk reads.
+__global__ void __launch_bounds__(256) k_staging_moves(StagingMoveBatch b) {
     __shared__ uint8_t tmp[4096];
-    const TailMove mv = b.m[blockIdx.x];
-    const uint8_t *src = mv.buf + mv.drop;
-    for (uint32_t c0 = 0; c0 < mv.keep; c0 += 4096) {
-        const uint32_t len = min(4096u, mv.keep - c0);
-        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) tmp[i] = src[c0 + i];
+    const StagingMove mv = b.m[blockIdx.x];
+    for (uint32_t c0 = 0; c0 < mv.len; c0 += 4096) {
+        const uint32_t len = min(4096u, mv.len - c0);
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) tmp[i] = mv.src[c0 + i];
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) mv.buf[c0 + i] = tmp[i];
+        for (uint32_t i = threadIdx.x; i < len; i += blockDim.x) mv.dst[c0 + i] = tmp[i];
         __syncthreads();
     }
 }
 
-hipError_t launch_tail_moves(const TailMoveBatch &b, uint32_t n, hipStream_t st) {
+hipError_t launch_staging_moves(const StagingMoveBatch &b, uint32_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    if (n > kTailMovesPerLaunch) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tail_moves, dim3(n), dim3(256), 0, st, b);
+    if (n > kStagingMovesPerLaunch) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_staging_moves, dim3(n), dim3(256), 0, st, b);
     return hipGetLastError();
 }
 

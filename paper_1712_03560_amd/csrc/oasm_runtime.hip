@@ -211,6 +211,8 @@ struct oasm_ctx {
     std::unordered_set<uint8_t *> own_alloc;  // staging buffers with an allocation of their own
     uint8_t *slab_cur = nullptr;            // unused part of the newest slab
     size_t slab_left = 0;
+    std::vector<StagingMove> moves;         // queued staging moves (launched by flush_moves)
+    std::vector<std::pair<uint8_t *, size_t>> move_release;  // buffers the queued moves read
 };
 
 namespace {
@@ -236,6 +238,7 @@ double now_ms() {
 void wait_stream(oasm_ctx *c, const char *what);
 
 uint8_t *acquire_staging(oasm_ctx *c, size_t need, size_t &cap);
+void flush_moves(oasm_ctx *c, hipStream_t st);
 void release_staging(oasm_ctx *c, uint8_t *p, size_t cap);
 
 void wait_stream(oasm_ctx *c, const char *what) {
@@ -669,8 +672,6 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     if (ncarry_out) c->carry_cur = cout;  // nothing carried: keep the buffers (and the step's shape) as they are
     // stream bookkeeping (matched streams only): keep a look-back tail of
     // each stream's symbols, the moves batched into few launches
-    TailMoveBatch moves;
-    uint32_t nmoves = 0;
     for (uint32_t si : which) {
         StreamState &s = c->streams[si];
         c->stats.bytes_scanned += s.valid - s.scanned;
@@ -694,21 +695,17 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
         const size_t keep = std::min<size_t>(s.valid, c->lookback + 4);
         if (keep < s.valid) {
             const size_t drop = s.valid - keep;
-            if (drop <= UINT32_MAX && keep <= UINT32_MAX) {
-                moves.m[nmoves++] = TailMove{s.sym, (uint32_t)drop, (uint32_t)keep};
-                if (nmoves == kTailMovesPerLaunch) {
-                    ck(launch_tail_moves(moves, nmoves, st), "tail moves");
-                    nmoves = 0;
-                }
+            if (keep <= UINT32_MAX) {
+                c->moves.push_back(StagingMove{s.sym + drop, s.sym, (uint32_t)keep, 0});
             } else {
-                // a drop beyond 4 GiB: the ranges cannot overlap (keep is a look-back tail)
+                // never for a look-back tail (at most m_max + K_max + 3 symbols)
                 ck(hipMemcpyAsync(s.sym, s.sym + drop, keep, hipMemcpyDeviceToDevice, st), "tail move");
             }
             s.base_abs += drop;
             s.valid = s.scanned = keep;
         }
     }
-    ck(launch_tail_moves(moves, nmoves, st), "tail moves");
+    flush_moves(c, st);
     c->stats.raw_hits += new_raw;
     c->stats.occurrences += nocc;
     c->stats.syncs++;
@@ -836,8 +833,26 @@ void release_staging(oasm_ctx *c, uint8_t *p, size_t cap) {
     if (p) c->pool.emplace(cap, p);
 }
 
-// Make room for `n` more symbols in a stream's staging buffer.
-oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n) {
+// Launch the queued staging moves, 128 per launch, then give the buffers
+// they read back to the pool (their next users are ordered after the moves
+// on the stream `st`).
+void flush_moves(oasm_ctx *c, hipStream_t st) {
+    StagingMoveBatch b;
+    for (size_t i = 0; i < c->moves.size(); i += kStagingMovesPerLaunch) {
+        const uint32_t n = (uint32_t)std::min<size_t>(kStagingMovesPerLaunch, c->moves.size() - i);
+        std::copy(c->moves.begin() + (ptrdiff_t)i, c->moves.begin() + (ptrdiff_t)(i + n), b.m);
+        ck(launch_staging_moves(b, n, st), "staging moves");
+    }
+    c->moves.clear();
+    for (auto &r : c->move_release) release_staging(c, r.first, r.second);
+    c->move_release.clear();
+}
+
+// Make room for `n` more symbols in a stream's staging buffer.  With
+// `queue`, the copy of the stream's symbols into a new buffer joins the
+// queued staging moves (the caller runs flush_moves before anything reads
+// the new buffer); otherwise it is a copy of its own.
+oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n, bool queue = false) {
     const size_t need = s.valid + n + kPad;
     if (need <= s.cap) return OASM_OK;
     const size_t want = std::max(need, s.cap + s.cap / 2);
@@ -845,8 +860,13 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n) {
     uint8_t *p = acquire_staging(c, want, cap);
     if (!p) return fail(c, OASM_E_NOMEM, "hipMalloc for stream staging failed");
     if (s.sym) {
-        if (s.valid) ck(hipMemcpyAsync(p, s.sym, s.valid, hipMemcpyDeviceToDevice, c->st), "staging grow");
-        release_staging(c, s.sym, s.cap);
+        if (queue && s.valid && s.valid <= UINT32_MAX) {
+            c->moves.push_back(StagingMove{s.sym, p, (uint32_t)s.valid, 0});
+            c->move_release.emplace_back(s.sym, s.cap);  // not reused before the move
+        } else {
+            if (s.valid) ck(hipMemcpyAsync(p, s.sym, s.valid, hipMemcpyDeviceToDevice, c->st), "staging grow");
+            release_staging(c, s.sym, s.cap);
+        }
     }
     c->staged_bytes += cap - s.cap;
     s.sym = p;
@@ -1358,10 +1378,14 @@ oasm_status oasm_feed_device_many(oasm_ctx *c, const oasm_feed_seg *segs, size_t
         for (auto &kv : add) {
             StreamState &s = get_stream(c, kv.first, true);
             if (kv.second) {
-                oasm_status r = reserve_stream(c, s, kv.second);
-                if (r != OASM_OK) return r;
+                oasm_status r = reserve_stream(c, s, kv.second, true);
+                if (r != OASM_OK) {
+                    flush_moves(c, c->st);  // the streams grown so far keep their symbols
+                    return r;
+                }
             }
         }
+        flush_moves(c, c->st);
         std::vector<SegCopy> copies;
         copies.reserve(n);
         for (size_t i = 0; i < n; ++i) {
@@ -1471,9 +1495,13 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
             }
             // one staging reservation per stream, then the copies
             for (auto &kv : add) {
-                oasm_status r = reserve_stream(c, c->streams[kv.first], kv.second);
-                if (r != OASM_OK) return r;
+                oasm_status r = reserve_stream(c, c->streams[kv.first], kv.second, true);
+                if (r != OASM_OK) {
+                    flush_moves(c, c->st);  // the streams grown so far keep their symbols
+                    return r;
+                }
             }
+            flush_moves(c, c->st);
             copies.clear();
             for (size_t i : batch) {
                 const oasm_segment &sg = segs[i];

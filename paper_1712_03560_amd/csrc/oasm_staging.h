@@ -7,18 +7,22 @@
 
 namespace oasm {
 
-// After a step a stream keeps its last `keep` symbols, moved `drop` bytes
-// down to the front of its staging buffer (the ranges may overlap).  Up to
-// kTailMovesPerLaunch moves travel in the kernel arguments.
-struct TailMove {
-    uint8_t *buf;
-    uint32_t drop;
-    uint32_t keep;
+// A move of len symbols from src to dst inside the staging memory: the
+// look-back tail of a stream moved to the front of its buffer after a step
+// (dst below src, the ranges may overlap), or a stream's symbols copied into
+// its new, larger buffer (disjoint ranges).  dst above an overlapping src is
+// not allowed.  Up to kStagingMovesPerLaunch moves travel in the kernel
+// arguments.
+struct StagingMove {
+    const uint8_t *src;
+    uint8_t *dst;
+    uint32_t len;
+    uint32_t pad;
 };
-constexpr uint32_t kTailMovesPerLaunch = 128;
-struct TailMoveBatch {
-    TailMove m[kTailMovesPerLaunch];
+constexpr uint32_t kStagingMovesPerLaunch = 128;
+struct StagingMoveBatch {
+    StagingMove m[kStagingMovesPerLaunch];
 };
-hipError_t launch_tail_moves(const TailMoveBatch &b, uint32_t n, hipStream_t st);
+hipError_t launch_staging_moves(const StagingMoveBatch &b, uint32_t n, hipStream_t st);
 
 }  // namespace oasm
