@@ -154,3 +154,46 @@ def test_feeds_from_many_threads():
         res = mt.results()
     for i, t in enumerate(w.streams):
         check_against_oracle(res, w.patterns, w.ks, t, stream=100 + i)
+
+
+def test_small_pieces_long_patterns():
+    """Long patterns (m up to 256: the multi-word and cutoff scan variants)
+    fed in pieces shorter than their look-back at first, then longer ones,
+    with a sync after each round: every step moves an overlapping tail (up to
+    m_max + K_max + 3 symbols, more than a workgroup's 256 threads) to the
+    front of its staging buffer, and the growing pieces outgrow the buffers,
+    through the batched device feed (copies queued with the tail moves) on
+    two streams and the single host feed (a copy of its own) on a third.
+    Every stream equals the oracle."""
+    w = W.small_random(34, 12_000, 12, 150, 256, b"ACGT", 25, n_plants=40, n_streams=3)
+    texts = [np.ascontiguousarray(t) for t in w.streams]
+    devs = [torch.from_numpy(t).cuda() for t in texts]
+    torch.cuda.synchronize()
+    pos = [0, 0, 0]
+    size = 37.0
+    rounds = 0
+    say(f"stream lengths {[t.size for t in texts]}, m up to {max(len(p) for p in w.patterns)}")
+    with oasm.Matcher(w.patterns, w.ks) as mt:
+        while any(pos[i] < texts[i].size for i in range(3)) or rounds == 0:
+            n = int(size)
+            items = []
+            for i in (0, 1):
+                a, b = pos[i], min(pos[i] + n, texts[i].size)
+                if a < texts[i].size or (a == 0 and texts[i].size == 0 and rounds == 0):
+                    items.append((10 + i, devs[i][a:b], b == texts[i].size))
+                pos[i] = b
+            if items:
+                mt.feed_many(items)
+            a, b = pos[2], min(pos[2] + n, texts[2].size)
+            if a < texts[2].size or (texts[2].size == 0 and rounds == 0):
+                mt.feed(12, texts[2][a:b], last=b == texts[2].size)
+            pos[2] = b
+            mt.sync()
+            size = min(size * 1.35, 1500.0)
+            rounds += 1
+        res = mt.results()
+    say(f"{rounds} rounds, {res.raw.size} hit ends, {res.occ.size} occurrences")
+    assert rounds >= 8
+    assert res.raw.size > 0 and res.occ.size > 0  # the planted copies are found
+    for i, t in enumerate(texts):
+        check_against_oracle(res, w.patterns, w.ks, t, stream=10 + i)
