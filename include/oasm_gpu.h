@@ -67,7 +67,8 @@ extern "C" {
 typedef int32_t oasm_status;
 #define OASM_OK 0
 #define OASM_E_INVAL (-1)  /* bad argument: NULL pointer, len 0, K >= len ... */
-#define OASM_E_NOMEM (-2)  /* host or device allocation failed */
+#define OASM_E_NOMEM (-2)  /* host or device allocation failed (from oasm_sync or oasm_serve after a
+                            * host allocation failed inside a matching step, the context is poisoned) */
 #define OASM_E_AGAIN (-3)  /* device-memory budget exhausted: drain / sync, retry */
 #define OASM_E_CLOSED (-4) /* feed to a stream that was closed */
 #define OASM_E_DEVICE (-5) /* HIP error; the context is poisoned, only destroy is valid */
@@ -260,6 +261,9 @@ oasm_status oasm_close_stream(oasm_ctx *ctx, uint64_t stream_id);
  * launch sequence, or one per stream with OASM_CFG_PLAIN), wait for it and
  * queue the results for draining.  Occurrences whose fate still depends on
  * bytes not yet fed stay pending until a later sync (or the stream's close).
+ * Errors: OASM_E_INVAL (ctx NULL), OASM_E_NOMEM (a host allocation failed
+ * inside the step: the context is poisoned, only destroy is valid),
+ * OASM_E_DEVICE.
  */
 oasm_status oasm_sync(oasm_ctx *ctx);
 
@@ -289,7 +293,8 @@ oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_
  * then drainable and its filter has advanced as far as the bytes allow).
  * Results are queued as by oasm_sync.  Errors: OASM_E_INVAL (NULL pointers,
  * unsorted arrivals, a segment outside the pool, a closed stream),
- * OASM_E_NOMEM, OASM_E_DEVICE.
+ * OASM_E_NOMEM (device staging memory: the context stays usable; a host
+ * allocation: the context is poisoned), OASM_E_DEVICE.
  */
 oasm_status oasm_serve(oasm_ctx *ctx, const oasm_segment *segs, size_t n, const void *dev_pool, uint64_t pool_bytes,
                        double *latency_s, oasm_serve_report *report);

@@ -230,6 +230,15 @@ oasm_status device_fail(oasm_ctx *c, const HipFail &f) {
     return OASM_E_DEVICE;
 }
 
+// A host allocation that fails inside a matching step leaves the step half
+// applied (stream bookkeeping, queued moves, result queues): the context is
+// poisoned as after a device error.
+oasm_status step_alloc_fail(oasm_ctx *c) {
+    c->poisoned = true;
+    c->err = "host allocation failed during a matching step; the context is poisoned";
+    return OASM_E_NOMEM;
+}
+
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -1286,7 +1295,7 @@ static oasm_status feed_common(oasm_ctx *c, uint64_t stream_id, const void *src,
                                void *user_stream, uint32_t flags) {
     if (!c) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
     if (n > 0 && !src) return fail(c, OASM_E_INVAL, "NULL bytes with n > 0");
     if (n > (size_t(1) << 31)) return fail(c, OASM_E_INVAL, "feed larger than 2 GiB");
     try {
@@ -1349,7 +1358,7 @@ oasm_status oasm_feed_device(oasm_ctx *c, uint64_t stream_id, const void *dev, s
 oasm_status oasm_feed_device_many(oasm_ctx *c, const oasm_feed_seg *segs, size_t n, void *hip_stream) {
     if (!c) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
     if (n > 0 && !segs) return fail(c, OASM_E_INVAL, "NULL segs with n > 0");
     // validate everything before touching any stream (all or nothing)
     uint64_t total = 0;
@@ -1430,7 +1439,7 @@ oasm_status oasm_close_stream(oasm_ctx *c, uint64_t stream_id) {
 oasm_status oasm_sync(oasm_ctx *c) {
     if (!c) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
     const double t0 = now_ms();
     try {
         ck(hipSetDevice(c->device), "hipSetDevice");
@@ -1439,7 +1448,7 @@ oasm_status oasm_sync(oasm_ctx *c) {
         c->stats.sync_wall_ms += now_ms() - t0;
         return device_fail(c, f);
     } catch (const std::bad_alloc &) {
-        return fail(c, OASM_E_NOMEM, "host allocation failed");
+        return step_alloc_fail(c);
     }
     c->stats.sync_wall_ms += now_ms() - t0;
     return OASM_OK;
@@ -1449,7 +1458,7 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
                        double *latency_s, oasm_serve_report *report) {
     if (!c || (n > 0 && (!segs || !dev_pool))) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
     for (size_t i = 0; i < n; ++i) {
         if (segs[i].offset + segs[i].len > pool_bytes) return fail(c, OASM_E_INVAL, "segment outside the pool");
         if (i && segs[i].arrival_s < segs[i - 1].arrival_s)
@@ -1528,7 +1537,7 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
     } catch (const HipFail &f) {
         return device_fail(c, f);
     } catch (const std::bad_alloc &) {
-        return fail(c, OASM_E_NOMEM, "host allocation failed");
+        return step_alloc_fail(c);
     }
     rep.wall_s = (now_ms() - t0) * 1e-3;
     if (report) *report = rep;
@@ -1607,7 +1616,7 @@ oasm_status oasm_levcalc(oasm_ctx *c, const void *dev_text, size_t n, void *dev_
                          void *hip_stream) {
     if (!c) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
-    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier device error");
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
     if (n > 0 && (!dev_text || !dev_out)) return fail(c, OASM_E_INVAL, "NULL text or output with n > 0");
     size_t need = 0;
     if (oasm_levcalc_size(c, n, &need) != OASM_OK) return fail(c, OASM_E_INVAL, "output size overflows size_t");
