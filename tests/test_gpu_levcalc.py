@@ -71,6 +71,7 @@ def test_tiny_config_full():
     (4, 300, 60, 140, b"ACGT", 20),
     (5, 257, 120, 256, bytes([0, 255, 7]), 40),
     (6, 600, 200, 256, b"ACGT", 63),
+    (7, 700, 100, 256, bytes(range(256)), 30),  # every byte row of the even-W mask tables
 ])
 def test_random_dictionaries(seed, n, mlo, mhi, alphabet, kmax):
     w = W.small_random(seed, n, 12, mlo, mhi, alphabet, kmax, n_plants=6)
