@@ -57,20 +57,28 @@ constexpr int kLcStage = (kLcWin + kLcThreads - 1) / kLcThreads;  // window symb
 
 // One column of the anchored recurrence (Myers 1999 in Hyyro's form, with
 // the +1 horizontal delta of the first DP row entering the first pattern
-// row).  Row r (1-based) of the pattern is bit r-1 of the W-word column;
+// row).  Row r (1-based) of the pattern is bit b0 + r - 1 of the W-word
+// column.  One-word columns use high placement, b0 = 32 - m: row m is the
+// top bit, and the b0 bits below row 1 are rows that match every byte and
+// start with no vertical delta; with eq = 1 and pv = mv = 0 they produce
+// ph = mh = 0 and keep pv = mv = 0, so they never feed a pattern row, and
+// the +1 of the first DP row is put in at bit b0 (`inj` = 1 << b0).  Wider
+// columns use low placement, b0 = 0 (row r at bit r - 1, which keeps the
+// band cutoff below as tight as possible): the rows above row m at the top
+// of the last word take deltas from below but never feed a pattern row, and
+// are masked out of the last-row sum.
 // pv: rows with vertical delta +1; cm: complement of the rows with vertical
 // delta -1; eq: rows whose pattern byte equals the text byte.  With
 // u = (eq & pv) + pv (carry across words):
 //   ph = mv | ~(u | pv | eq),  mh = pv & (eq | ~u),
-//   ph2 = (ph << 1) | 1,       mh2 = mh << 1   (one row down, across words),
+//   ph2 = (ph << 1) | inj,     mh2 = mh << 1   (one row down, across words),
 //   pv' = mh2 | ~(eq | mv | ph2),  mv' = ph2 & (eq | mv).
-// Rows above the last pattern row (the unused top of the last word) receive
-// deltas from below but never feed back into a pattern row.
 //
 // anchored_step<N, W> advances only the first N words of the column (the
 // band cutoff below); the carry and shifts out of word N-1 are dropped.
 template <int N, int W>
-__device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq) {
+__device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *eq,
+                                              uint32_t inj) {
     uint32_t ph[N], mh[N];
     uint32_t carry = 0;
 #pragma unroll
@@ -90,7 +98,7 @@ __device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[
     uint32_t npv[N], ncm[N];
 #pragma unroll
     for (int w = 0; w < N; ++w) {
-        const uint32_t ph2 = w == 0 ? (lc_add_self(ph[0]) | 1u) : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
+        const uint32_t ph2 = w == 0 ? (lc_add_self(ph[0]) | inj) : __builtin_amdgcn_alignbit(ph[w], ph[w - 1], 31);
         const uint32_t mh2 = w == 0 ? lc_add_self(mh[0]) : __builtin_amdgcn_alignbit(mh[w], mh[w - 1], 31);
         const uint32_t t = LC_BITOP3(eq[w], cm[w], ph2, ~(LA | ~LB | LC));  // ~(eq | ~cm | ph2)
         npv[w] = mh2 | t;
@@ -107,19 +115,20 @@ __device__ __forceinline__ void anchored_step(uint32_t (&pv)[W], uint32_t (&cm)[
 // the band): after l symbols, C[r][l] >= r - l, so rows r > l + K hold values
 // above K, and a cell above K never leads to a value <= K.  The step that
 // produces column l therefore advances only the words holding rows
-// 1 .. l + K, N(l) = ceil((l + K) / 32) of them; the words above keep their
-// initial +1 vertical deltas until they are first advanced, i.e. values
-// C[32w][l] + (r - 32w) at rows r of word w, upper bounds of the true ones
-// (a value grows by at most 1 per row).  Upper bounds of cells above K change
-// no value <= K, and every output step (l >= m - K) advances all W words.
-// quiet_band<W, 1> runs steps j .. j1-1 (column l = j + 1), word count by
-// word count.
+// 1 .. l + K (bits up to b0 + l + K - 1), N(l) = ceil((b0 + l + K) / 32) of
+// them; the words above keep their initial +1 vertical deltas until they are
+// first advanced, i.e. values C[r0][l] + (r - r0) at the rows r of a word
+// whose lowest row is r0, upper bounds of the true ones (a value grows by at
+// most 1 per row).  Upper bounds of cells above K change no value <= K, and
+// every output step (l >= m - K) advances all W words.  quiet_band<W, 1>
+// runs steps j .. j1-1 (column l = j + 1), word count by word count; kb =
+// K + b0.
 template <int W, int N>
 __device__ __forceinline__ void quiet_band(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *&wp, uint32_t &j,
-                                           uint32_t j1, uint32_t K, const char *tab) {
+                                           uint32_t j1, uint32_t kb, uint32_t inj, const char *tab) {
     if constexpr (N <= W) {
-        // steps whose column l = j + 1 needs at most N words: l + K <= 32 N
-        const uint32_t lim_n = 32u * N > K ? 32u * N - K : 0u;  // j + 1 + K <= 32 N  <=>  j < 32 N - K
+        // steps whose column l = j + 1 needs at most N words: b0 + l + K <= 32 N
+        const uint32_t lim_n = 32u * N > kb ? 32u * N - kb : 0u;  // j + 1 + kb <= 32 N  <=>  j < 32 N - kb
         const uint32_t end = N == W ? j1 : (lim_n < j1 ? lim_n : j1);
         constexpr int U = N <= 2 ? kLcUnroll : N <= 4 ? 2 : 1;  // mask rows read ahead (registers)
         for (; j + U <= end; j += U, wp += U) {
@@ -131,16 +140,16 @@ __device__ __forceinline__ void quiet_band(uint32_t (&pv)[W], uint32_t (&cm)[W],
                 for (int w = 0; w < N; ++w) eq[u][w] = r[w];
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u) anchored_step<N, W>(pv, cm, eq[u]);
+            for (int u = 0; u < U; ++u) anchored_step<N, W>(pv, cm, eq[u], inj);
         }
         for (; j < end; ++j, ++wp) {
             uint32_t eq[N];
             const uint32_t *r = reinterpret_cast<const uint32_t *>(tab + wp[0]);
 #pragma unroll
             for (int w = 0; w < N; ++w) eq[w] = r[w];
-            anchored_step<N, W>(pv, cm, eq);
+            anchored_step<N, W>(pv, cm, eq, inj);
         }
-        quiet_band<W, N + 1>(pv, cm, wp, j, j1, K, tab);
+        quiet_band<W, N + 1>(pv, cm, wp, j, j1, kb, inj, tab);
     }
 }
 
@@ -170,15 +179,23 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
         const uint32_t width = 2 * K + 1;        // lengths m-K .. m+K
         const uint32_t steps = m + K;            // symbols read per start
         const uint32_t quiet = m - K - 1;        // leading steps without output (l < m - K)
-        const uint32_t rlast = m - 32u * (W - 1);  // pattern rows in the last word, 1..32
-        const uint32_t lmask = rlast >= 32 ? ~0u : (1u << rlast) - 1u;
+        const uint32_t b0 = W == 1 ? 32u - m : 0u;  // match-all rows below row 1, 0..31
+        const uint32_t inj = 1u << b0;              // the first DP row's +1 enters at row 1
+        const uint32_t low = inj - 1u;              // the match-all rows
+        const uint32_t rlast = m - 32u * (W - 1);   // pattern rows in the last word (W > 1), 1..32
+        const uint32_t lmask = W == 1 || rlast >= 32 ? ~0u : (1u << rlast) - 1u;
         uint8_t *const out = a.out + a.n * a.out_unit[q];
         const uint8_t *const pb = a.pat_bytes + d.off;
 
         __syncthreads();  // the previous pattern's masks and window are no longer read
-        for (uint32_t i = tid; i < 256u * S; i += kLcThreads) peq[i] = 0u;
+        // every byte's row: the match-all rows set, then pattern row r + 1
+        // (0-based r) at bit b0 + r where the byte equals p[r]
+        for (uint32_t i = tid; i < 256u * S; i += kLcThreads) peq[i] = i % S == 0 ? low : 0u;
         __syncthreads();
-        for (uint32_t r = tid; r < m; r += kLcThreads) atomicOr(&peq[pb[r] * S + (r >> 5)], 1u << (r & 31));
+        for (uint32_t r = tid; r < m; r += kLcThreads) {
+            const uint32_t q = b0 + r;
+            atomicOr(&peq[pb[r] * S + (q >> 5)], 1u << (q & 31));
+        }
 
         // the window of the next pass is loaded into registers while the
         // current one is matched (software pipelining of the text reads)
@@ -209,7 +226,7 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
             uint32_t pv[W], cm[W];
 #pragma unroll
             for (int w = 0; w < W; ++w) {
-                pv[w] = ~0u;  // C[r][0] = r: every vertical delta is +1
+                pv[w] = w == 0 ? ~low : ~0u;  // C[r][0] = r: every vertical delta is +1 (0 below row 1)
                 cm[w] = ~0u;  // no -1 deltas (complemented)
             }
             const uint32_t *wp = win + tid;
@@ -221,9 +238,11 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
             };
             // l = j + 1 below m - K: no output yet (band cutoff)
             uint32_t j = 0;
-            quiet_band<W, 1>(pv, cm, wp, j, quiet, K, tab);
+            quiet_band<W, 1>(pv, cm, wp, j, quiet, K + b0, inj, tab);
             // l = m - K .. m + K: C[m][l] = l + (sum of the vertical deltas of
-            // rows 1..m) = l - m + popcount(pv) + popcount(cm) over those rows.
+            // rows 1..m) = l - m + popcount(pv) + popcount(cm) over those
+            // rows = l - m - b0 + popcount(pv) + popcount(cm) over the column
+            // below the last word's mask (below row 1, pv = 0 and cm = 1).
             // The pass's output (256 starts x width bytes, pattern-major
             // layout) is one buffer: byte i of start s is at tid * width + i,
             // the lane part in a vector register and i in a scalar one, so a
@@ -240,10 +259,10 @@ __global__ void __launch_bounds__(kLcThreads) k_levcalc(LevcalcArgs a) {
                 for (uint32_t i = 0; i < width; ++i) {
                     uint32_t eq[W];
                     masks(wp[i], eq);
-                    anchored_step<W, W>(pv, cm, eq);
+                    anchored_step<W, W>(pv, cm, eq, inj);
                     const uint32_t l = m - K + i;
-                    uint32_t dsum = lc_bcnt_s(pv[0] & (W == 1 ? lmask : ~0u), l - m);  // wraps; the total is >= 0
-                    dsum = lc_bcnt(cm[0] & (W == 1 ? lmask : ~0u), dsum);
+                    uint32_t dsum = lc_bcnt_s(pv[0], l - m - b0);  // wraps; the total is >= 0
+                    dsum = lc_bcnt(cm[0], dsum);
 #pragma unroll
                     for (int w = 1; w < W; ++w) {
                         dsum = lc_bcnt(pv[w] & (w == W - 1 ? lmask : ~0u), dsum);
