@@ -521,8 +521,8 @@ def levcalc_legs(oasm, torch, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path has no multi-GPU mode "
-              f"in this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library runs on one GPU "
+              f"and has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
     probe = None if args.no_valu_probe else valu_probe()
     import torch
