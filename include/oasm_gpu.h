@@ -63,6 +63,10 @@ extern "C" {
 /* Longest supported pattern (eight 32-bit words per pattern column). */
 #define OASM_MAX_PATTERN_LEN 256
 
+/* Largest oasm_config.chunk_bytes (16 MiB): the scan records a hit end as
+ * its offset inside the chunk, in 24 bits. */
+#define OASM_MAX_CHUNK_BYTES (1u << 24)
+
 /* Status codes (negative = error). */
 typedef int32_t oasm_status;
 #define OASM_OK 0
@@ -141,7 +145,8 @@ typedef struct oasm_config {
     uint32_t struct_size;        /* sizeof(oasm_config); set by oasm_config_init */
     int32_t device;              /* HIP device ordinal; -1 = the current device */
     void *hip_stream;            /* hipStream_t to run on; NULL = library-owned stream */
-    uint32_t chunk_bytes;        /* text bytes per scan work item; 0 = autotuned */
+    uint32_t chunk_bytes;        /* text bytes per scan work item (rounded down to a multiple of 64, at
+                                    least 64, at most OASM_MAX_CHUNK_BYTES); 0 = chosen by the library */
     uint32_t flags;              /* OASM_CFG_* */
     uint64_t device_mem_budget;  /* bytes of fed, not yet matched stream data allowed; 0 = unlimited */
 } oasm_config;
@@ -209,8 +214,9 @@ oasm_status oasm_config_init(oasm_config *cfg);
  * OASM_RULES_NONE, or OASM_RULES_PAPER with any OASM_RULES_* variant bits.
  * `cfg` may be NULL (defaults).
  * Errors: OASM_E_INVAL for n == 0, a NULL pattern, len == 0,
- * len > OASM_MAX_PATTERN_LEN, K >= len, or unknown rule bits (variant bits
- * without OASM_RULES_PAPER included); OASM_E_NOMEM; OASM_E_DEVICE.
+ * len > OASM_MAX_PATTERN_LEN, K >= len, unknown rule bits (variant bits
+ * without OASM_RULES_PAPER included), or cfg->chunk_bytes above
+ * OASM_MAX_CHUNK_BYTES; OASM_E_NOMEM; OASM_E_DEVICE.
  * On success *out receives the context; on error *out is set to NULL.
  */
 oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k, uint16_t k_all,
@@ -271,10 +277,12 @@ oasm_status oasm_sync(oasm_ctx *ctx);
  * Copy up to `cap` queued records of `kind` into `out` (an array of
  * oasm_hit for OASM_RAW, of oasm_occ otherwise) and remove them from the
  * queue.  *n_out receives the number copied; *more (may be NULL) is set to 1
- * when records remain.  Within one sync, records are ordered by stream,
- * then pattern, then position (end for OASM_RAW; emission order, which is
- * start order, for OASM_FILTERED; start then length for OASM_H); syncs
- * follow each other in call order.
+ * when records remain.  Within one sync, records are ordered by stream id,
+ * then pattern, then position: the end for OASM_RAW; the emission order of
+ * Alg. 1 for OASM_FILTERED (emissions in stream order, and inside one
+ * emission its best occurrence first, then the accepted lower-priority ones
+ * by ascending k, which start before it); start then length for OASM_H.
+ * Syncs follow each other in call order.
  */
 oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_t *n_out, int *more);
 
@@ -291,10 +299,14 @@ oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_
  * arrival.  latency_s (optional, n entries) receives, per segment, the time
  * from its arrival to the end of the step that matched it (its hit ends are
  * then drainable and its filter has advanced as far as the bytes allow).
- * Results are queued as by oasm_sync.  Errors: OASM_E_INVAL (NULL pointers,
- * unsorted arrivals, a segment outside the pool, a closed stream),
- * OASM_E_NOMEM (device staging memory: the context stays usable; a host
- * allocation: the context is poisoned), OASM_E_DEVICE.
+ * Results are queued as by oasm_sync.  `report` (optional) is written on
+ * every return, errors included: segments are served in arrival order, so
+ * the served ones are segs[0 .. report->segments).  Errors: OASM_E_INVAL
+ * (NULL pointers, unsorted arrivals, a segment outside the pool, a segment
+ * for a closed stream: that iteration's batch is refused whole, before any
+ * stream changes), OASM_E_NOMEM (device staging memory: the batch is refused
+ * whole and the context stays usable; a host allocation: the context is
+ * poisoned), OASM_E_DEVICE.
  */
 oasm_status oasm_serve(oasm_ctx *ctx, const oasm_segment *segs, size_t n, const void *dev_pool, uint64_t pool_bytes,
                        double *latency_s, oasm_serve_report *report);

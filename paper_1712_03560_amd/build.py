@@ -64,12 +64,6 @@ def build(verbose: bool = False) -> str:
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for valu_probe.hip:\n{res.stdout}\n{res.stderr}")
     os.replace(tmp, PROBE)
-    # the host runtime under AddressSanitizer / UBSan (a test driver; optional)
-    script = os.path.join(os.path.dirname(HERE), "tests", "native", "build_runtime_asan.sh")
-    if os.path.exists(script):
-        res = subprocess.run(["bash", script], capture_output=True, text=True)
-        if res.returncode != 0:
-            print(f"note: the sanitized runtime driver did not build:\n{res.stderr[-2000:]}", file=sys.stderr)
     return LIB
 
 

@@ -12,6 +12,7 @@ constexpr uint32_t kXcds = 8;      // accelerator dies (each with its own L2)
 constexpr int kMaxW32 = 8;         // 32-bit words per pattern column (256 rows)
 constexpr int kMaxW64 = 4;         // 64-bit words per column in the recovery kernel
 constexpr uint8_t kNoHit = 0xFF;   // hit-set byte for "distance above K"
+constexpr int kMaxDevices = 64;    // device ordinals the per-device tables cover
 
 // Filter rule bits (the values of the public OASM_RULES_* flags).
 constexpr uint32_t kRulePaper = 1, kRuleAccLast = 2, kRuleEq3Ge = 4, kRuleStartOrder = 8, kRuleDisjoint = 16;

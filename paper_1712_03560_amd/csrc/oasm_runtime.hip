@@ -306,6 +306,12 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which_in, StepPlan &pl
     for (uint32_t si : which_in) target[si] = 1;
     for (uint32_t si = 0; si < c->streams.size(); ++si)
         if (!target[si] && c->streams[si].ncarry > 0) which.push_back(si);
+    // step-local order = stream id order: the step's records are sorted by
+    // (step-local stream, pattern, position), which the drain promises as
+    // (stream id, pattern, position); slots of finished streams are reused
+    // in any order
+    std::sort(which.begin(), which.end(),
+              [c](uint32_t a, uint32_t b) { return c->streams[a].id < c->streams[b].id; });
     uint64_t total_new = 0;
     for (uint32_t si : which_in) total_new += c->streams[si].valid - c->streams[si].scanned;
     const uint32_t C = choose_chunk(c, total_new);
@@ -1169,6 +1175,11 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         g_create_error = "unknown rules";
         return OASM_E_INVAL;
     }
+    if (cfg && cfg->chunk_bytes > OASM_MAX_CHUNK_BYTES) {
+        // a scan record holds an end offset inside its chunk in 24 bits
+        g_create_error = "chunk_bytes above OASM_MAX_CHUNK_BYTES";
+        return OASM_E_INVAL;
+    }
     for (uint32_t i = 0; i < n; ++i) {
         const uint32_t len = dict[i].len;
         const uint32_t kk = k ? k[i] : k_all;
@@ -1456,22 +1467,32 @@ oasm_status oasm_sync(oasm_ctx *c) {
 
 oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const void *dev_pool, uint64_t pool_bytes,
                        double *latency_s, oasm_serve_report *report) {
+    if (report) *report = oasm_serve_report{};
     if (!c || (n > 0 && (!segs || !dev_pool))) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
     if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
     for (size_t i = 0; i < n; ++i) {
-        if (segs[i].offset + segs[i].len > pool_bytes) return fail(c, OASM_E_INVAL, "segment outside the pool");
+        if (segs[i].offset > pool_bytes || segs[i].len > pool_bytes - segs[i].offset)
+            return fail(c, OASM_E_INVAL, "segment outside the pool");
         if (i && segs[i].arrival_s < segs[i - 1].arrival_s)
             return fail(c, OASM_E_INVAL, "segments must be sorted by arrival");
     }
     oasm_serve_report rep{};
     const uint8_t *pool = reinterpret_cast<const uint8_t *>(dev_pool);
     const double t0 = now_ms();
+    // on every return: the segments served so far (a prefix in arrival order)
+    auto done_with = [&](oasm_status st) {
+        rep.wall_s = (now_ms() - t0) * 1e-3;
+        if (report) *report = rep;
+        return st;
+    };
     size_t next = 0;
     std::deque<size_t> ready;
     std::vector<size_t> batch;
     std::vector<SegCopy> copies;
-    std::unordered_map<uint32_t, uint64_t> add;  // stream slot -> bytes admitted this iteration
+    std::unordered_map<uint64_t, uint64_t> add;  // stream id -> bytes admitted this iteration
+    std::unordered_set<uint64_t> closing;        // streams a segment of this iteration closes
+    std::vector<uint32_t> created;               // slots of streams this iteration created
     try {
         ck(hipSetDevice(c->device), "hipSetDevice");
         while (next < n || !ready.empty()) {
@@ -1482,35 +1503,55 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
                 if (dt > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(dt, 0.01)));
                 continue;
             }
-            // admission: arrival order, within the budget for unmatched bytes
-            batch.clear();
+            // admission: arrival order, within the budget for unmatched bytes.
+            // Every admitted segment is checked before any stream changes, so
+            // an error leaves the streams as the previous iteration left them.
             add.clear();
+            closing.clear();
             uint64_t admit = 0;
+            size_t take = 0;
             const uint64_t budget = c->cfg.device_mem_budget;
-            while (!ready.empty()) {
-                const oasm_segment &sg = segs[ready.front()];
+            for (; take < ready.size(); ++take) {
+                const oasm_segment &sg = segs[ready[take]];
                 if (budget && c->pending_bytes + admit + sg.len > budget && (admit > 0 || c->pending_bytes > 0)) {
                     rep.deferred++;
                     break;
                 }
-                if (is_finished(c, sg.stream)) return fail(c, OASM_E_INVAL, "segment for a closed stream");
-                StreamState &s = get_stream(c, sg.stream, true);
-                if (s.closed || s.close_pending) return fail(c, OASM_E_INVAL, "segment for a closed stream");
-                add[s.slot] += sg.len;
+                bool closed = is_finished(c, sg.stream) || closing.count(sg.stream) != 0;
+                if (!closed) {
+                    auto it = c->slot_of.find(sg.stream);
+                    if (it != c->slot_of.end())
+                        closed = c->streams[it->second].closed || c->streams[it->second].close_pending;
+                }
+                if (closed) return done_with(fail(c, OASM_E_INVAL, "segment for a closed stream"));
+                add[sg.stream] += sg.len;
                 admit += sg.len;
-                batch.push_back(ready.front());
-                ready.pop_front();
-                if (sg.flags & OASM_FEED_LAST) s.close_pending = true;  // later segments of it are refused above
+                if (sg.flags & OASM_FEED_LAST) closing.insert(sg.stream);
             }
-            // one staging reservation per stream, then the copies
+            // one staging reservation per stream; on failure the streams this
+            // iteration created are removed again (the others only grew)
+            created.clear();
             for (auto &kv : add) {
-                oasm_status r = reserve_stream(c, c->streams[kv.first], kv.second, true);
+                if (c->slot_of.find(kv.first) == c->slot_of.end()) created.push_back(get_stream(c, kv.first, true).slot);
+                oasm_status r = reserve_stream(c, c->streams[c->slot_of[kv.first]], kv.second, true);
                 if (r != OASM_OK) {
                     flush_moves(c, c->st);  // the streams grown so far keep their symbols
-                    return r;
+                    for (uint32_t slot : created) {
+                        StreamState &s = c->streams[slot];
+                        if (s.sym) {
+                            c->staged_bytes -= s.cap;
+                            release_staging(c, s.sym, s.cap);
+                        }
+                        c->slot_of.erase(s.id);
+                        s = StreamState{};
+                        c->free_slots.push_back(slot);
+                    }
+                    return done_with(r);
                 }
             }
             flush_moves(c, c->st);
+            batch.assign(ready.begin(), ready.begin() + (ptrdiff_t)take);
+            ready.erase(ready.begin(), ready.begin() + (ptrdiff_t)take);
             copies.clear();
             for (size_t i : batch) {
                 const oasm_segment &sg = segs[i];
@@ -1520,6 +1561,7 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
                 c->pending_bytes += sg.len;
                 c->stats.cells += (uint64_t)sg.len * c->msum;
                 c->stats.word_steps += (uint64_t)sg.len * c->wsum;
+                if (sg.flags & OASM_FEED_LAST) s.close_pending = true;
             }
             const double tb = now_ms();
             map_copies(c, copies);
@@ -1530,18 +1572,16 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
             rep.max_batch_bytes = std::max<uint64_t>(rep.max_batch_bytes, admit);
             rep.segments += batch.size();
             rep.bytes += admit;
-            const double done = (te - t0) * 1e-3;
+            const double fin = (te - t0) * 1e-3;
             if (latency_s)
-                for (size_t i : batch) latency_s[i] = done - segs[i].arrival_s;
+                for (size_t i : batch) latency_s[i] = fin - segs[i].arrival_s;
         }
     } catch (const HipFail &f) {
-        return device_fail(c, f);
+        return done_with(device_fail(c, f));
     } catch (const std::bad_alloc &) {
-        return step_alloc_fail(c);
+        return done_with(step_alloc_fail(c));
     }
-    rep.wall_s = (now_ms() - t0) * 1e-3;
-    if (report) *report = rep;
-    return OASM_OK;
+    return done_with(OASM_OK);
 }
 
 oasm_status oasm_queued(const oasm_ctx *c, uint32_t kind, size_t *n) {

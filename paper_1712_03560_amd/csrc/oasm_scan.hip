@@ -4,6 +4,8 @@
 // tiled over wavefront lanes and many streams cut into chunks.
 //
 // Integer bit-vector work only; no matrix cores.
+#include <mutex>
+
 #include "oasm_device.h"
 
 namespace oasm {
@@ -562,14 +564,23 @@ static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStrea
     if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
     const size_t shmem = lds ? (size_t)a.nclass * kWave * (CUT ? W : pad_pow2(P * W)) * 4 : 0;
     if (lds) {
-        // raise the instance's dynamic-LDS limit once (never inside a graph
-        // capture: the first launch of a shape is always an eager one)
-        static size_t configured = 0;
-        if (shmem > configured) {
-            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true, CUT>),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-            if (e != hipSuccess) return e;
-            configured = shmem;
+        // raise the instance's dynamic-LDS limit once per device (never
+        // inside a graph capture: the first launch of a shape is always an
+        // eager one); contexts on several host threads share the table
+        static std::mutex mu;
+        static size_t configured[kMaxDevices] = {};
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return e;
+        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+        {
+            std::lock_guard<std::mutex> g(mu);
+            if (shmem > configured[dev]) {
+                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true, CUT>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+                if (e != hipSuccess) return e;
+                configured[dev] = shmem;
+            }
         }
         hipLaunchKernelGGL((k_scan<W, P, true, CUT>), dim3((uint32_t)blocks), dim3(waves * kWave), shmem, st, a);
     } else {

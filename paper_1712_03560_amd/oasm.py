@@ -44,6 +44,7 @@ OASM_RAW = 0
 OASM_FILTERED = 1
 OASM_H = 2
 OASM_MAX_PATTERN_LEN = 256
+OASM_MAX_CHUNK_BYTES = 1 << 24
 
 # every symbol the header declares (checked by the ABI test)
 EXPORTED = [

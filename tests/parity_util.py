@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import os
 import sys
+import time
 from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
@@ -36,8 +37,16 @@ def oracle_pairs(streams: dict, patterns, ks, pairs=None, threads=None, with_fil
         sid, pi = pair
         return pair, oracle.run_pair(patterns[pi], streams[sid], int(ks[pi]), with_filter, rules)
 
+    # a progress line every 20 s, so that a long oracle run is seen to advance
+    out, t0, last = {}, time.monotonic(), time.monotonic()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        return dict(ex.map(one, pairs))
+        for key, val in ex.map(one, pairs):
+            out[key] = val
+            if time.monotonic() - last > 20:
+                last = time.monotonic()
+                print(f"[parity] oracle: {len(out)} of {len(pairs)} pairs after {last - t0:.0f} s", file=sys.stderr,
+                      flush=True)
+    return out
 
 
 def compare(res, streams: dict, patterns, ks, pairs=None, check_h=False, with_filter=True, label="", rules=1):

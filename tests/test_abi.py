@@ -127,3 +127,29 @@ def test_null_arguments(lib):
     lib.oasm_levcalc_size.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     out = ctypes.c_size_t(7)
     assert lib.oasm_levcalc_size(None, 10, ctypes.byref(out)) == -1
+
+
+@pytest.mark.parametrize("chunk", [(1 << 24) + 64, 0xFFFFFFC0])
+def test_create_rejects_oversized_chunks(chunk):
+    """A scan record keeps a hit end's offset inside its chunk in 24 bits, so
+    chunks above OASM_MAX_CHUNK_BYTES are refused before any device work."""
+    from paper_1712_03560_amd import oasm
+
+    cfg = oasm.oasm_config_init()
+    cfg.chunk_bytes = chunk
+    with pytest.raises(oasm.OasmError) as ei:
+        oasm.oasm_create([b"ACGT"], 1, cfg=cfg)
+    assert ei.value.status == oasm.OASM_E_INVAL
+    assert "chunk_bytes" in oasm.oasm_last_error(None)
+
+
+def test_serve_writes_the_report_on_errors(lib):
+    """oasm_serve fills its report on every return, errors included."""
+    from paper_1712_03560_amd import oasm
+
+    rep = oasm.oasm_serve_report()
+    rep.segments = rep.bytes = rep.steps = 77
+    lib.oasm_serve.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_uint64,
+                               ctypes.c_void_p, ctypes.POINTER(oasm.oasm_serve_report)]
+    assert lib.oasm_serve(None, None, 0, None, 0, None, ctypes.byref(rep)) == oasm.OASM_E_INVAL
+    assert (rep.segments, rep.bytes, rep.steps) == (0, 0, 0)

@@ -76,13 +76,14 @@ def test_alone_equals_mix_equals_oracle(budget):
     compare(mix, streams, pats, ks, label=f"serving-budget{budget}")
 
 
+@pytest.mark.timeout(900)
 def test_serving_full_size_sampled_sessions():
     """The serving workload at the benchmark's size and settings (10,000
     sessions, 2048 patterns of 16..128 mixture bytes, K = floor(m/10), U[1,64]
     KiB segments arriving at 20 GB/s over 50 ms, a 64 MiB budget, autotuned
     variants), with 20,000 mutated pattern copies planted in the byte pool:
-    12 seeded sessions against the oracle on their concatenated bytes (every
-    pattern), and 2 of them alone against the mix."""
+    1 % of the 10,000 sessions (100, seeded) against the oracle on their
+    concatenated bytes (every pattern), and 2 of them alone against the mix."""
     pats, ks = W.serving_dictionary()
     pool = W.serving_pool(1 << 26)
     # mutated copies of the patterns in the pool, so that the sessions hold hits
@@ -92,15 +93,24 @@ def test_serving_full_size_sampled_sessions():
     segs["stream"], segs["offset"], segs["len"], segs["arrival_s"] = sess, off, ln, t
     dpool = torch.from_numpy(pool).cuda()
     print(f"[serving] full size: {segs.size} segments, {int(ln.sum())} bytes", file=sys.stderr, flush=True)
+    sids = sorted(set(int(x) for x in segs["stream"]))
+    # the trace leaves its sessions open: each session is closed after the
+    # run, so that its last filter segment (still pending when the run ends)
+    # completes as in the oracle, which filters each session as a finished
+    # stream
     with oasm.Matcher(pats, ks, mem_budget=64 << 20, autotune=True) as mt:
         rep, lat = mt.serve(segs, dpool)
+        for sid in sids:
+            mt.close(sid)
+        mt.sync()
         mix = mt.results()
     assert rep["segments"] == segs.size and rep["deferred"] > 0
-    sids = sorted(set(int(x) for x in segs["stream"]))
-    pick = [int(x) for x in np.random.default_rng(17).choice(sids, 12, replace=False)]
+    pick = [int(x) for x in np.random.default_rng(17).choice(sids, 100, replace=False)]
     for sid in pick[:2]:
         with oasm.Matcher(pats, ks, autotune=True) as mt:
             mt.serve(segs[segs["stream"] == sid].copy(), dpool, want_latency=False)
+            mt.close(sid)
+            mt.sync()
             alone = mt.results()
         a_raw, a_occ = rows_of(alone, sid)
         m_raw, m_occ = rows_of(mix, sid)
@@ -108,4 +118,4 @@ def test_serving_full_size_sampled_sessions():
     streams = {sid: session_bytes(pool, segs, sid) for sid in pick}
     pairs = [(sid, p) for sid in pick for p in range(len(pats))]
     n_raw, n_occ = compare(mix, streams, pats, ks, pairs=pairs, label="serving-full-size")
-    assert n_raw > 50 and n_occ > 10
+    assert n_raw > 400 and n_occ > 80
