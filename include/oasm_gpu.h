@@ -336,6 +336,29 @@ oasm_status oasm_serve(oasm_ctx *ctx, const oasm_segment *segs, size_t n, const 
 oasm_status oasm_levcalc(oasm_ctx *ctx, const void *dev_text, size_t n, void *dev_out, size_t out_bytes,
                          void *hip_stream);
 
+/* Largest dictionary oasm_levcalc_noalloc accepts. */
+#define OASM_NOALLOC_MAX_PATTERNS 65536u
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * call and the same output as oasm_levcalc, but it allocates nothing and
+ * copies nothing from the host.  oasm_levcalc's two small tables (the pattern
+ * ids grouped by word count, and per pattern the sum of 2K + 1 over the
+ * patterns before it, which places its output block) are built on its first
+ * call in device memory it allocates; here they are built by a kernel, at
+ * every call, in a fixed device array that the library holds per GPU until
+ * the process ends (OASM_NOALLOC_MAX_PATTERNS x 12 bytes = 768 KiB).  Every
+ * call on a GPU, from any context, writes that GPU's array: calls that
+ * overlap in time on one GPU (on different HIP streams, or from different
+ * threads) race and may write wrong distances; calls queued on one stream
+ * are ordered.  The caller passes the text and the output, as for
+ * oasm_levcalc.  Errors: those of oasm_levcalc, and OASM_E_INVAL for a
+ * context of more than OASM_NOALLOC_MAX_PATTERNS patterns.
+ */
+oasm_status oasm_levcalc_noalloc(oasm_ctx *ctx, const void *dev_text, size_t n, void *dev_out, size_t out_bytes,
+                                 void *hip_stream);
+
 /* Bytes oasm_levcalc writes for a text of n bytes: n * sum over patterns of
  * (2K + 1).  OASM_E_INVAL for NULL arguments or a size that overflows. */
 oasm_status oasm_levcalc_size(const oasm_ctx *ctx, size_t n, size_t *bytes);

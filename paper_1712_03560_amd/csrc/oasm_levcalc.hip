@@ -14,6 +14,7 @@
 // (64 starts x (2K+1) bytes) is one contiguous run.
 //
 // Integer bit-vector work only; no matrix cores.
+#include <mutex>
 #include <type_traits>
 
 #include "oasm_device.h"
@@ -308,6 +309,95 @@ hipError_t launch_levcalc(int W, const LevcalcArgs &a, hipStream_t st) {
         case 8: return launch_levcalc_t<8>(a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+
+// ------------------------------------------------------------------ tables
+// The allocation-free entry point's tables live in this array (one copy per
+// GPU, held for the life of the process).  Host code never passes the
+// array's name to a kernel: it passes the address levcalc_scratch() looked
+// up on the device.
+static __device__ __align__(256) uint8_t scratch[kLcScratchBytes];
+
+hipError_t levcalc_scratch(int device, uint8_t **out) {
+    static std::mutex mu;
+    static uint8_t *addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = reinterpret_cast<uint8_t *>(p);
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+// exclusive scan of one value per thread over a 256-thread block
+__device__ __forceinline__ uint32_t lc_block_scan(uint32_t v, uint32_t *wsum, uint32_t &total) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, 64);
+        if (lane >= (uint32_t)off) incl += t;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (uint32_t w = 0; w < kLcThreads / 64; ++w) {
+        const uint32_t x = wsum[w];
+        if (w < wave) before += x;
+        all += x;
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - v;
+}
+
+// One block: thread t takes a contiguous run of patterns, counts them per
+// word count and sums their 2K + 1; block scans turn the counts into each
+// run's positions in the word-count-major id list and the sums into output
+// units.
+__global__ void __launch_bounds__(kLcThreads) k_levcalc_tables(const PatDesc *__restrict__ pats, uint32_t npat,
+                                                               uint64_t *__restrict__ unit,
+                                                               uint32_t *__restrict__ ids) {
+    __shared__ uint32_t wsum[kLcThreads / 64];
+    const uint32_t per = (npat + kLcThreads - 1) / kLcThreads;
+    const uint32_t q0 = min(npat, threadIdx.x * per), q1 = min(npat, q0 + per);
+    uint32_t cnt[kMaxW32] = {}, usum = 0, total = 0;
+    for (uint32_t q = q0; q < q1; ++q) {
+        const PatDesc d = pats[q];
+#pragma unroll
+        for (int w = 0; w < kMaxW32; ++w) cnt[w] += ((uint32_t)d.m + 31u) / 32u == (uint32_t)(w + 1) ? 1u : 0u;
+        usum += 2u * d.k + 1u;
+    }
+    uint64_t u = lc_block_scan(usum, wsum, total);
+    uint32_t pos[kMaxW32], base = 0;
+#pragma unroll
+    for (int w = 0; w < kMaxW32; ++w) {
+        pos[w] = base + lc_block_scan(cnt[w], wsum, total);
+        base += total;
+    }
+    for (uint32_t q = q0; q < q1; ++q) {
+        const PatDesc d = pats[q];
+        unit[q] = u;
+        u += 2u * d.k + 1u;
+        const uint32_t wq = ((uint32_t)d.m + 31u) / 32u;
+#pragma unroll
+        for (int w = 0; w < kMaxW32; ++w)
+            if (wq == (uint32_t)(w + 1)) ids[pos[w]++] = q;
+    }
+}
+
+hipError_t launch_levcalc_tables(const PatDesc *pats, uint32_t npat, uint8_t *scr, hipStream_t st) {
+    if (npat == 0) return hipSuccess;
+    if (npat > kLcNoallocMaxPatterns) return hipErrorInvalidValue;
+    uint64_t *unit = reinterpret_cast<uint64_t *>(scr);
+    uint32_t *ids = reinterpret_cast<uint32_t *>(scr + (size_t)kLcNoallocMaxPatterns * sizeof(uint64_t));
+    hipLaunchKernelGGL(k_levcalc_tables, dim3(1), dim3(kLcThreads), 0, st, pats, npat, unit, ids);
+    return hipGetLastError();
 }
 
 }  // namespace oasm

@@ -202,6 +202,7 @@ struct oasm_ctx {
     std::vector<LcGroup> lc_groups;
     uint64_t lc_unit_total = 0;
     hipEvent_t ev_lc = nullptr;  // after the last LEV CALC launch (on the caller's stream)
+    uint8_t *lc_scratch = nullptr;  // this device's table array of oasm_levcalc_noalloc
 
     // Staging buffers of closed streams, kept for reuse.  Every byte of them
     // was written by this context (cleared at allocation, then mapped
@@ -1171,6 +1172,7 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
                       OASM_RULES_EQ3_GE == kRuleEq3Ge && OASM_RULES_START_ORDER == kRuleStartOrder &&
                       OASM_RULES_DISJOINT == kRuleDisjoint,
                   "rule bits");
+    static_assert(OASM_NOALLOC_MAX_PATTERNS == kLcNoallocMaxPatterns, "noalloc table size");
     if ((rules & ~kRuleAll) != 0 || (rules != OASM_RULES_NONE && !(rules & OASM_RULES_PAPER))) {
         g_create_error = "unknown rules";
         return OASM_E_INVAL;
@@ -1210,6 +1212,10 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         ck(hipEventCreate(&c->ev2), "event");
         ck(hipEventCreate(&c->ev3), "event");
         ck(hipEventCreate(&c->ev_seg), "event");
+        ck(hipEventCreateWithFlags(&c->ev_lc, hipEventDisableTiming), "event");
+        // the allocation-free LEV CALC's table array on this device (looked
+        // up once per device, with the device current)
+        ck(levcalc_scratch(c->device, &c->lc_scratch), "scratch address");
         hipStream_t st = c->st;
 
         // dictionary on the host: lengths, thresholds, symbol classes
@@ -1699,12 +1705,56 @@ oasm_status oasm_levcalc(oasm_ctx *c, const void *dev_text, size_t n, void *dev_
             ck(launch_levcalc(gr.W, a, st), "levcalc launch");
         }
         // destroy waits for this point: the kernels read the dictionary tables
-        if (!c->ev_lc) ck(hipEventCreateWithFlags(&c->ev_lc, hipEventDisableTiming), "levcalc event");
         ck(hipEventRecord(c->ev_lc, st), "levcalc event record");
     } catch (const HipFail &f) {
         return device_fail(c, f);
     } catch (const std::bad_alloc &) {
         return fail(c, OASM_E_NOMEM, "host allocation failed");
+    }
+    return OASM_OK;
+}
+
+oasm_status oasm_levcalc_noalloc(oasm_ctx *c, const void *dev_text, size_t n, void *dev_out, size_t out_bytes,
+                                 void *hip_stream) {
+    if (!c) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
+    if (n > 0 && (!dev_text || !dev_out)) return fail(c, OASM_E_INVAL, "NULL text or output with n > 0");
+    if (c->npat > OASM_NOALLOC_MAX_PATTERNS)
+        return fail(c, OASM_E_INVAL, "dictionary larger than OASM_NOALLOC_MAX_PATTERNS");
+    size_t need = 0;
+    if (oasm_levcalc_size(c, n, &need) != OASM_OK) return fail(c, OASM_E_INVAL, "output size overflows size_t");
+    if (out_bytes < need) return fail(c, OASM_E_INVAL, "output buffer too small for n * sum(2K + 1) bytes");
+    if (n == 0) return OASM_OK;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        // groups of the word-count-major id list, counted on the host from
+        // the dictionary's lengths (the device builds the same list)
+        uint32_t cnt[kMaxW32 + 1] = {};
+        for (uint32_t p = 0; p < c->npat; ++p) cnt[(c->m[p] + 31u) / 32u]++;
+        ck(launch_levcalc_tables(c->d_pats.as<PatDesc>(), c->npat, c->lc_scratch, st), "levcalc tables");
+        const uint64_t *unit = reinterpret_cast<const uint64_t *>(c->lc_scratch);
+        const uint32_t *ids =
+            reinterpret_cast<const uint32_t *>(c->lc_scratch + (size_t)kLcNoallocMaxPatterns * sizeof(uint64_t));
+        uint32_t first = 0;
+        for (int W = 1; W <= kMaxW32; ++W) {
+            if (!cnt[W]) continue;
+            LevcalcArgs a;
+            a.text = reinterpret_cast<const uint8_t *>(dev_text);
+            a.n = n;
+            a.pat_ids = ids + first;
+            a.npat = cnt[W];
+            a.pats = c->d_pats.as<PatDesc>();
+            a.pat_bytes = c->d_patbytes.as<uint8_t>();
+            a.out_unit = unit;
+            a.out = reinterpret_cast<uint8_t *>(dev_out);
+            ck(launch_levcalc(W, a, st), "levcalc launch");
+            first += cnt[W];
+        }
+        ck(hipEventRecord(c->ev_lc, st), "levcalc event record");
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
     }
     return OASM_OK;
 }

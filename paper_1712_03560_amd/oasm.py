@@ -45,6 +45,7 @@ OASM_FILTERED = 1
 OASM_H = 2
 OASM_MAX_PATTERN_LEN = 256
 OASM_MAX_CHUNK_BYTES = 1 << 24
+OASM_NOALLOC_MAX_PATTERNS = 65536
 
 # every symbol the header declares (checked by the ABI test)
 EXPORTED = [
@@ -65,6 +66,7 @@ EXPORTED = [
     "oasm_tune_report",
     "oasm_levcalc",
     "oasm_levcalc_size",
+    "oasm_levcalc_noalloc",
 ]
 
 
@@ -150,6 +152,8 @@ def _load():
     lib.oasm_tune_report.restype = ctypes.c_char_p
     lib.oasm_levcalc.argtypes = [P, P, sz, P, sz, P]
     lib.oasm_levcalc.restype = i32
+    lib.oasm_levcalc_noalloc.argtypes = [P, P, sz, P, sz, P]
+    lib.oasm_levcalc_noalloc.restype = i32
     lib.oasm_levcalc_size.argtypes = [P, sz, ctypes.POINTER(sz)]
     lib.oasm_levcalc_size.restype = i32
     lib.oasm_status_str.argtypes = [i32]
@@ -264,6 +268,10 @@ def oasm_levcalc_size(ctx, n: int) -> int:
 
 def oasm_levcalc(ctx, text_ptr: int, n: int, out_ptr: int, out_bytes: int, hip_stream: int | None):
     _check(ctx, lib.oasm_levcalc(ctx, text_ptr, n, out_ptr, out_bytes, hip_stream))
+
+
+def oasm_levcalc_noalloc(ctx, text_ptr: int, n: int, out_ptr: int, out_bytes: int, hip_stream: int | None):
+    _check(ctx, lib.oasm_levcalc_noalloc(ctx, text_ptr, n, out_ptr, out_bytes, hip_stream))
 
 
 def oasm_get_stats(ctx) -> dict:
