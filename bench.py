@@ -588,7 +588,7 @@ def main():
         line["long_stream"] = {"workload": dl, "gcups": round(ml["gcups"], 1),
                                "ms_per_step": round(ml["ms_per_step"], 3), "roofline": ml["roofline"],
                                "step_breakdown_ms": ml["step_breakdown_ms"], "hits": ml["hits"],
-                               "host_fed": host_fed(oasm, torch, wl)}
+                               "autotune": ml["autotune"], "host_fed": host_fed(oasm, torch, wl)}
         del rl, wl
     if args.workload != "multiword" and not args.no_multiword:
         from paper_1712_03560_amd import workloads as W
@@ -602,7 +602,7 @@ def main():
                                          f"{len(wm.plants)} planted copies",
                              "gcups": round(mm["gcups"], 1), "ms_per_step": round(mm["ms_per_step"], 3),
                              "roofline": mm["roofline"], "step_breakdown_ms": mm["step_breakdown_ms"],
-                             "hits": mm["hits"], "autotune": [x for x in mm["autotune"] if x.startswith("class")]}
+                             "hits": mm["hits"], "autotune": mm["autotune"]}
         del rm, wm
     if args.workload != "tiny" and not args.no_tiny:
         wt, dt_ = make_workload("tiny", args)

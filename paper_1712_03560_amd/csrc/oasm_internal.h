@@ -135,9 +135,11 @@ struct ScanArgs {
     uint32_t *max_cnt;       // atomic max of per-item counts
     unsigned long long *wsteps;  // += pattern words advanced over reported symbols (may be null)
 };
-// `cut`: the word-cutoff variant (one pattern per lane, W >= 2).
-hipError_t launch_scan(int W, int P, bool cut, const ScanArgs &a, int waves_per_block, bool peq_in_lds,
-                       hipStream_t st);
+// `cut`: the word-cutoff variant (one pattern per lane, W >= 2).  `mode`:
+// where the tile's match masks are read from: 0 = the image in global memory
+// (through L1/L2), 1 = the image copied to LDS.  `waves_per_block`: 1..4
+// wavefronts, each scanning one chunk with the block's tile.
+hipError_t launch_scan(int W, int P, bool cut, const ScanArgs &a, int waves_per_block, int mode, hipStream_t st);
 bool scan_variant_exists(int W, int P, bool cut);
 
 // Ordering of the step's hit ends: carried ends first, then the scan items'
@@ -207,9 +209,10 @@ size_t scan_tmp_words(size_t cap);
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, DevN n, uint32_t *total, uint32_t *tmp,
                                  hipStream_t st);
 
-// Fill nwords uint32 with symbol classes drawn uniformly from [0, nclass)
-// by splitmix64 of the byte index (the autotuner's synthetic text).
-hipError_t launch_fill_classes(uint32_t *p, size_t nwords, uint32_t nclass, uint64_t seed, hipStream_t st);
+// Fill nwords uint32 with symbol classes: byte j is table[x >> 48] for x the
+// splitmix64 hash of j (the autotuner's synthetic text; `table` holds 65536
+// class ids, each class repeated in proportion to its wanted frequency).
+hipError_t launch_fill_classes(uint32_t *p, size_t nwords, const uint8_t *table, uint64_t seed, hipStream_t st);
 
 // Fill n uint32 with a value (graph-safe replacement for a memset).
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t st);

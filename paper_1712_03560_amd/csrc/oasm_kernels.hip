@@ -810,7 +810,8 @@ hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, DevN n, uint
     return hipGetLastError();
 }
 
-__global__ void k_fill_classes(uint32_t *__restrict__ p, size_t nwords, uint32_t nclass, uint64_t seed) {
+__global__ void k_fill_classes(uint32_t *__restrict__ p, size_t nwords, const uint8_t *__restrict__ table,
+                               uint64_t seed) {
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) {
         uint32_t w = 0;
@@ -819,17 +820,17 @@ __global__ void k_fill_classes(uint32_t *__restrict__ p, size_t nwords, uint32_t
             z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
             z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
             z ^= z >> 31;
-            w |= ((uint32_t)(z >> 32) % nclass) << (8 * b);
+            w |= (uint32_t)table[z >> 48] << (8 * b);
         }
         p[i] = w;
     }
 }
 
-hipError_t launch_fill_classes(uint32_t *p, size_t nwords, uint32_t nclass, uint64_t seed, hipStream_t st) {
-    if (nwords == 0 || nclass == 0) return nwords == 0 ? hipSuccess : hipErrorInvalidValue;
+hipError_t launch_fill_classes(uint32_t *p, size_t nwords, const uint8_t *table, uint64_t seed, hipStream_t st) {
+    if (nwords == 0) return hipSuccess;
     const size_t want = (nwords + 255) / 256;
     hipLaunchKernelGGL(k_fill_classes, dim3((uint32_t)(want < 8192 ? want : 8192)), dim3(256), 0, st, p, nwords,
-                       nclass, seed);
+                       table, seed);
     return hipGetLastError();
 }
 

@@ -117,9 +117,9 @@ struct StreamState {
 struct ClassInfo {
     int W = 1, P = 1;
     uint32_t tile_first = 0, ntiles = 0;
-    bool lds = true;
+    int lds = 1;       // match masks: 0 image through L1/L2, 1 image in LDS
     bool cut = false;  // word-cutoff scan variant
-    int waves = 4;
+    int waves = 4;     // wavefronts per block (each scans one chunk)
 };
 
 }  // namespace
@@ -147,6 +147,7 @@ struct oasm_ctx {
     std::vector<PatDesc> h_pd;
     uint64_t rpeq_words = 0;
     size_t max_lds = 64 * 1024;       // dynamic LDS a block may use on this device
+    double chunk_scale = 1.0;         // scale of the chunk-size rule (autotuned)
     std::string tune_log;             // choices made by the autotuner
     DevBuf d_pats, d_slot_pat, d_tiles, d_peq, d_rpeq, d_class, d_patbytes, d_pat_tile, d_pat_slot, d_tile_wp;
     std::vector<uint32_t> class_w32;  // per pattern: words
@@ -289,12 +290,14 @@ size_t put(std::vector<uint8_t> &blob, const std::vector<T> &v) {
 
 uint32_t choose_chunk(oasm_ctx *c, uint64_t bytes) {
     if (c->cfg.chunk_bytes) return std::max<uint32_t>(64, c->cfg.chunk_bytes & ~63u);
-    // enough work items to fill 256 CUs several times over; a chunk is at
+    // enough work items to fill 256 CUs several times over, at most 64 KiB;
+    // both scaled by the autotuned factor (0.5, 1 or 2); and a chunk is at
     // least four look-backs long (so the look-back adds at most a quarter)
     const uint64_t target_items = 16384;
-    uint64_t per = bytes * std::max<uint32_t>(1, c->ntiles) / target_items;
+    const double sc = c->chunk_scale;
+    uint64_t per = (uint64_t)((double)bytes * std::max<uint32_t>(1, c->ntiles) / target_items * sc);
+    per = std::min<uint64_t>(per, (uint64_t)(65536 * sc));
     per = std::max<uint64_t>(per, std::max<uint64_t>(256, 4ull * c->lookback));
-    per = std::min<uint64_t>(per, 1u << 16);
     return (uint32_t)((per + 63) & ~63ull);
 }
 
@@ -893,8 +896,9 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n, bool queue = f
 // ------------------------------------------------------------------ tiles
 struct TileChoice {
     int P = 1;         // patterns per lane
-    bool lds = true;   // match-mask image in LDS (else read through L1/L2)
+    int lds = 1;       // match masks: 0 image through L1/L2, 1 image in LDS
     bool cut = false;  // word cutoff (P = 1, W >= 2)
+    int waves = 4;     // wavefronts per block
 };
 
 uint32_t pad_pow2_host(uint32_t x) { return x <= 1 ? 1 : x <= 2 ? 2 : x <= 4 ? 4 : 8; }
@@ -903,6 +907,11 @@ uint32_t pad_pow2_host(uint32_t x) { return x <= 1 ? 1 : x <= 2 ? 2 : x <= 4 ? 4
 // two (full columns), or word-major with W words per lane (cutoff tiles).
 uint64_t image_bytes(const oasm_ctx *c, int W, int P, bool cut = false) {
     return (uint64_t)c->nclass * 64 * (cut ? (uint32_t)W : pad_pow2_host((uint32_t)(P * W))) * 4;
+}
+
+// LDS bytes a block of class (W, P, cut) uses with mask mode `lds`.
+uint64_t lds_bytes(const oasm_ctx *c, int W, int P, bool cut, int lds) {
+    return lds == 1 ? image_bytes(c, W, P, cut) : 0;
 }
 
 // The patterns of one word count, shortest first: neighbouring lanes then
@@ -929,7 +938,8 @@ std::vector<TileChoice> default_choices(const oasm_ctx *c) {
         ch[W].cut = cut_ok && W >= 2;
         if (W == 2 && !ch[W].cut) P = n > 64 ? 2 : 1;
         ch[W].P = P;
-        ch[W].lds = image_bytes(c, W, P, ch[W].cut) <= 64 * 1024;
+        ch[W].lds = image_bytes(c, W, P, ch[W].cut) <= 64 * 1024 ? 1 : 0;
+        ch[W].waves = 4;
     }
     return ch;
 }
@@ -952,8 +962,9 @@ void build_tiles(oasm_ctx *c, const std::vector<TileChoice> &choice) {
         ci.P = P;
         ci.tile_first = (uint32_t)tiles.size();
         ci.cut = choice[W].cut && P == 1 && W >= 2;
-        ci.lds = choice[W].lds && image_bytes(c, W, P, ci.cut) <= c->max_lds;
-        ci.waves = 4;
+        ci.lds = choice[W].lds;
+        if (lds_bytes(c, W, P, ci.cut, ci.lds) > c->max_lds) ci.lds = 0;
+        ci.waves = std::max(1, std::min(choice[W].waves, 4));
         const uint32_t per = 64u * P;
         for (size_t t0 = 0; t0 < ids.size(); t0 += per) {
             TileDesc td;
@@ -1035,27 +1046,95 @@ double time_class(oasm_ctx *c, const ClassInfo &ci, const ChunkDesc *d_chunks, u
     return best;
 }
 
-// Process-wide memory of tuning results, keyed by the class's shape.
+// Process-wide memory of tuning results, keyed by the class's shape, and of
+// the chunk-size scale, keyed by the dictionary's shape.
 std::mutex g_tune_mu;
 std::map<std::tuple<uint32_t, int, size_t, int>, TileChoice> g_tune_cache;
+std::map<std::vector<uint64_t>, double> g_scale_cache;
 
-// Measure every (patterns per lane, LDS or not) variant of every word-count
-// class on a synthetic stream of uniformly drawn symbol classes, and keep
-// the fastest per class.  Each trial is planned the way a large step is
-// (the chunk size from the same rule, so about as many work items), with
-// text enough for at least 16,384 of them: variants with fewer tiles are
-// then not starved of wavefronts.
+// The synthetic trial of class W under the tiles last built: a stream of
+// `nbytes` symbols cut into chunks by the rule of a real step of that size
+// (at the context's current chunk scale).  Returns the device time of one
+// launch (min of `reps`).
+double time_trial(oasm_ctx *c, int W, const uint8_t *text, size_t nbytes, DevBuf &d_chunks, int reps) {
+    hipStream_t st = c->st;
+    const ClassInfo *ci = nullptr;
+    for (const ClassInfo &k : c->classes)
+        if (k.W == W) ci = &k;
+    const uint32_t C = choose_chunk(c, nbytes);  // the rule of a real step of nbytes
+    std::vector<ChunkDesc> ch;
+    for (uint64_t e0 = 0; e0 < nbytes; e0 += C) {
+        const uint64_t e1 = std::min<uint64_t>(nbytes, e0 + C);
+        uint64_t s0 = e0 >= c->lookback ? e0 - c->lookback : 0;
+        s0 &= ~uint64_t(3);
+        ch.push_back(ChunkDesc{text + s0, e0, (uint32_t)(e1 - s0), (uint32_t)(e0 - s0), 0, 0});
+    }
+    d_chunks.ensure(ch.size() * sizeof(ChunkDesc), st);
+    ck(hipMemcpyAsync(d_chunks.p, ch.data(), ch.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st),
+       "tune chunks");
+    return time_class(c, *ci, d_chunks.as<ChunkDesc>(), (uint32_t)ch.size(), reps);
+}
+
+// Measure the scan variants of every word-count class on a synthetic stream
+// of uniformly drawn symbol classes, and keep the fastest per class: patterns
+// per lane (1, 2, 4), the word cutoff or full columns, where the match masks
+// are read from (the image in LDS or through L1/L2) and wavefronts per block
+// (2 or 4).  A trial is a large step of one class: text for
+// 16,384 chunks of 64 KiB over the class's tiles, between 4 and 128 MiB, cut
+// by the real chunk rule, so that it fills the chip with about as many work
+// items, and spreads a block's image copy over about as much text, as a
+// large step.  Three interleaved rounds; after the first, only candidates
+// within 25 % of the best are timed again.  Then the chunk-size rule's scale
+// (0.5, 1, 2): the sum over the classes of their time per byte with their
+// chosen variants.
 void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
     hipStream_t st = c->st;
-    const size_t max_bytes = size_t(32) << 20, min_bytes = size_t(4) << 20;
-    DevBuf d_text, d_chunks;
-    d_text.ensure(max_bytes + kPad, st);
-    ck(launch_fill_classes(d_text.as<uint32_t>(), (max_bytes + kPad) / 4, c->nclass, 0x9E3779B97F4A7C15ull, st),
-       "tune text");
+    const size_t max_bytes = size_t(128) << 20, min_bytes = size_t(4) << 20;
+    DevBuf d_text, d_chunks, d_tab;
+    // the trial text draws symbol classes with the frequencies they have in
+    // the dictionary's patterns (text and patterns usually share an
+    // alphabet's skew; how often a pattern's prefix matches decides how far
+    // the word cutoff reaches and how often a group is replayed), through a
+    // table of 65536 entries; bytes no pattern uses are left out
+    {
+        std::vector<double> freq(c->nclass, 0.0);
+        for (uint8_t b : c->h_patbytes) freq[c->class_of[b]] += 1.0;
+        double total = 0;
+        for (double f : freq) total += f;
+        std::vector<uint8_t> tab;
+        tab.reserve(65536);
+        for (uint32_t k = 0; k < c->nclass; ++k) {
+            const size_t want = (size_t)(freq[k] / total * 65536.0 + 0.5);
+            tab.insert(tab.end(), std::min(want, 65536 - tab.size()), (uint8_t)k);
+        }
+        uint32_t most = 0;
+        for (uint32_t k = 1; k < c->nclass; ++k)
+            if (freq[k] > freq[most]) most = k;
+        tab.resize(65536, (uint8_t)most);  // rounding leftovers to the most frequent class
+        d_tab.ensure(65536, st);
+        ck(hipMemcpyAsync(d_tab.p, tab.data(), 65536, hipMemcpyHostToDevice, st), "tune table");
+        d_text.ensure(max_bytes + kPad, st);
+        ck(launch_fill_classes(d_text.as<uint32_t>(), (max_bytes + kPad) / 4, d_tab.as<uint8_t>(),
+                               0x9E3779B97F4A7C15ull, st),
+           "tune text");
+        wait_stream(c, "tune text");
+    }
+    const bool cut_ok = !(c->cfg.flags & OASM_CFG_NO_CUTOFF);
+    // trial text per class: 16,384 chunks of 64 KiB over its tiles
+    auto trial_bytes = [&](int W) {
+        const ClassInfo *ci = nullptr;
+        for (const ClassInfo &k : c->classes)
+            if (k.W == W) ci = &k;
+        const size_t nbytes = (size_t)16384 * 65536 / std::max<uint32_t>(1, ci->ntiles);
+        return std::min(max_bytes, std::max(min_bytes, nbytes)) & ~size_t(0xFFFF);
+    };
+    char line[192];
+    c->chunk_scale = 1.0;
+    std::vector<uint64_t> shape{c->nclass, (uint64_t)c->max_lds, (uint64_t)cut_ok};
     for (int W = 1; W <= kMaxW32; ++W) {
         const size_t nW = class_members(c, W).size();
         if (nW == 0) continue;
-        const bool cut_ok = !(c->cfg.flags & OASM_CFG_NO_CUTOFF);
+        shape.push_back((uint64_t)W << 32 | nW);
         const auto key = std::make_tuple(c->nclass, W, nW, (int)c->max_lds * 2 + (cut_ok ? 1 : 0));
         {
             std::lock_guard<std::mutex> g(g_tune_mu);
@@ -1071,10 +1150,13 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
             for (bool cut : {false, true}) {
                 if (cut && !cut_ok) continue;
                 if (!scan_variant_exists(W, P, cut) || (P > 1 && nW <= (size_t)64 * (P / 2))) continue;
-                for (bool lds : {false, true}) {
-                    if (lds && image_bytes(c, W, P, cut) > c->max_lds) continue;
-                    if (P == choice[W].P && lds == choice[W].lds && cut == choice[W].cut) continue;
-                    cands.push_back(TileChoice{P, lds, cut});
+                for (int lds : {0, 1}) {
+                    if (lds_bytes(c, W, P, cut, lds) > c->max_lds) continue;
+                    for (int waves : {2, 4}) {
+                        const TileChoice &d = choice[W];
+                        if (P == d.P && lds == d.lds && cut == d.cut && waves == d.waves) continue;
+                        cands.push_back(TileChoice{P, lds, cut, waves});
+                    }
                 }
             }
         }
@@ -1084,41 +1166,28 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
         std::vector<double> best_ms(cands.size(), 1e30);
         std::vector<size_t> nbytes_of(cands.size(), 0);
         for (int round = 0; round < 3; ++round) {
+            double lead = 1e30;  // best time per word-step so far
+            for (size_t q = 0; q < cands.size(); ++q)
+                if (nbytes_of[q]) lead = std::min(lead, best_ms[q] / ((double)nW * W * (double)nbytes_of[q]));
             for (size_t q = 0; q < cands.size(); ++q) {
+                if (round && best_ms[q] / ((double)nW * W * (double)nbytes_of[q]) > 1.25 * lead) continue;
                 std::vector<TileChoice> trial = choice;
                 trial[W] = cands[q];
                 build_tiles(c, trial);
-                const ClassInfo *ci = nullptr;
-                for (const ClassInfo &k : c->classes)
-                    if (k.W == W) ci = &k;
-                size_t nbytes = max_bytes / std::max<uint32_t>(1, ci->ntiles);
-                nbytes = std::max(min_bytes, nbytes) & ~size_t(0xFFFF);
-                nbytes_of[q] = nbytes;
-                const uint32_t C = choose_chunk(c, nbytes);
-                std::vector<ChunkDesc> ch;
-                for (uint64_t e0 = 0; e0 < nbytes; e0 += C) {
-                    const uint64_t e1 = std::min<uint64_t>(nbytes, e0 + C);
-                    uint64_t s0 = e0 >= c->lookback ? e0 - c->lookback : 0;
-                    s0 &= ~uint64_t(3);
-                    ch.push_back(
-                        ChunkDesc{d_text.as<uint8_t>() + s0, e0, (uint32_t)(e1 - s0), (uint32_t)(e0 - s0), 0, 0});
-                }
-                d_chunks.ensure(ch.size() * sizeof(ChunkDesc), st);
-                ck(hipMemcpyAsync(d_chunks.p, ch.data(), ch.size() * sizeof(ChunkDesc), hipMemcpyHostToDevice, st),
-                   "tune chunks");
-                const double ms = time_class(c, *ci, d_chunks.as<ChunkDesc>(), (uint32_t)ch.size(), round ? 1 : 2);
+                nbytes_of[q] = trial_bytes(W);
+                const double ms = time_trial(c, W, d_text.as<uint8_t>(), nbytes_of[q], d_chunks, round ? 1 : 2);
                 best_ms[q] = std::min(best_ms[q], ms);
             }
         }
         double best = 1e30;
         TileChoice pick = choice[W];
-        char line[160];
         for (size_t q = 0; q < cands.size(); ++q) {
             const TileChoice &cd = cands[q];
             // time per pattern word per text byte: trials differ in tiles and text
             const double per = best_ms[q] / ((double)nW * W * (double)nbytes_of[q]);
-            std::snprintf(line, sizeof line, "W=%d P=%d lds=%d cut=%d: %.3f ms for %.0f MiB (%.3f ps per word-step)\n",
-                          W, cd.P, (int)cd.lds, (int)cd.cut, best_ms[q], nbytes_of[q] / 1048576.0, per * 1e9);
+            std::snprintf(line, sizeof line,
+                          "W=%d P=%d lds=%d cut=%d waves=%d: %.3f ms for %.0f MiB (%.3f ps per word-step)\n", W, cd.P,
+                          cd.lds, (int)cd.cut, cd.waves, best_ms[q], nbytes_of[q] / 1048576.0, per * 1e9);
             c->tune_log += line;
             if (per < (q == 0 ? 1e30 : best * 0.97)) {
                 best = per;
@@ -1129,8 +1198,47 @@ void autotune(oasm_ctx *c, std::vector<TileChoice> &choice) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         g_tune_cache[key] = pick;
     }
+    // the chunk-size scale, with every class's chosen variant
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_scale_cache.find(shape);
+        if (it != g_scale_cache.end()) {
+            c->chunk_scale = it->second;
+            d_text.release();
+            d_chunks.release();
+            d_tab.release();
+            return;
+        }
+    }
+    build_tiles(c, choice);
+    const double scales[3] = {1.0, 0.5, 2.0};
+    double per_byte[3] = {1e30, 1e30, 1e30};
+    for (int round = 0; round < 3; ++round) {
+        for (int q = 0; q < 3; ++q) {
+            c->chunk_scale = scales[q];
+            double sum = 0;
+            for (const ClassInfo &ci : std::vector<ClassInfo>(c->classes)) {
+                const size_t nbytes = trial_bytes(ci.W);
+                sum += time_trial(c, ci.W, d_text.as<uint8_t>(), nbytes, d_chunks, round ? 1 : 2) / (double)nbytes;
+            }
+            per_byte[q] = std::min(per_byte[q], sum);
+        }
+    }
+    int pick = 0;
+    for (int q = 0; q < 3; ++q) {
+        std::snprintf(line, sizeof line, "chunk scale %.1f: %.4f ns per text byte over all classes\n", scales[q],
+                      per_byte[q] * 1e6);
+        c->tune_log += line;
+        if (q > 0 && per_byte[q] < per_byte[pick] * 0.97) pick = q;
+    }
+    c->chunk_scale = scales[pick];
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_scale_cache[shape] = c->chunk_scale;
+    }
     d_text.release();
     d_chunks.release();
+    d_tab.release();
 }
 
 }  // namespace
@@ -1265,8 +1373,13 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         build_tiles(c, choice);
         for (const ClassInfo &ci : c->classes) {
             char line[128];
-            std::snprintf(line, sizeof line, "class W=%d: P=%d lds=%d cut=%d tiles=%u\n", ci.W, ci.P, (int)ci.lds,
-                          (int)ci.cut, ci.ntiles);
+            std::snprintf(line, sizeof line, "class W=%d: P=%d lds=%d cut=%d waves=%d tiles=%u\n", ci.W, ci.P,
+                          ci.lds, (int)ci.cut, ci.waves, ci.ntiles);
+            c->tune_log += line;
+        }
+        {
+            char line[96];
+            std::snprintf(line, sizeof line, "chunk scale: %.1f\n", c->chunk_scale);
             c->tune_log += line;
         }
         ck(hipStreamSynchronize(st), "create sync");

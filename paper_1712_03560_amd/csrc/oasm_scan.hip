@@ -285,6 +285,27 @@ __device__ __forceinline__ uint32_t cut_decide(const uint32_t (&pv)[W], const ui
     return ynew < (uint32_t)(W - 1) ? ynew : (uint32_t)(W - 1);
 }
 
+// Where a tile's match masks are read from (the MODE template argument):
+constexpr int kImgGlobal = 0;  // the image through L1/L2 (buffer resource)
+constexpr int kImgLds = 1;     // the image copied to LDS
+
+// Masks of words 0..N-1 of a cutoff tile's lane for symbol s of the group
+// `cur`.  The image is word-major ([class][word][lane]: the 64 lanes' masks
+// of one word are 256 contiguous bytes).
+template <int W, int N, int MODE>
+__device__ __forceinline__ void cut_masks(const uint32_t *img, __amdgpu_buffer_rsrc_t rs, uint32_t lane,
+                                          uint32_t cur, int s, uint32_t *e) {
+    if constexpr (MODE == kImgLds) {
+        const uint32_t *r = at_bytes(img + lane, row_off(cur, s, W * kWave * 4));
+#pragma unroll
+        for (int w = 0; w < N; ++w) e[w] = r[w * kWave];
+    } else {
+        const uint32_t off = row_off(cur, s, W * kWave * 4);
+#pragma unroll
+        for (int w = 0; w < N; ++w) gload<1>(rs, lane * 4, off + w * kWave * 4, &e[w]);
+    }
+}
+
 // One group of 4 symbols with only words 0..N-1 active (N < W): partial
 // mask reads, N-word column steps, then the cutoff decision.
 //
@@ -292,24 +313,13 @@ __device__ __forceinline__ uint32_t cut_decide(const uint32_t (&pv)[W], const ui
 // word w for the 64 lanes are 256 contiguous bytes, so reading only the
 // active words stays one coalesced access per word (a lane-major row of
 // 8 words would make every partial read touch 16 cache lines).
-template <int W, int N, bool LDS>
+template <int W, int N, int MODE>
 __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img,
                                               __amdgpu_buffer_rsrc_t rs, uint32_t lane, uint32_t cur, uint32_t kc,
                                               uint32_t mask, uint32_t kl) {
     uint32_t e[kScanGroup][N];
-    const uint32_t *row = img + lane;
 #pragma unroll
-    for (int s = 0; s < kScanGroup; ++s) {
-        if constexpr (LDS) {
-            const uint32_t *r = at_bytes(row, row_off(cur, s, W * kWave * 4));
-#pragma unroll
-            for (int w = 0; w < N; ++w) e[s][w] = r[w * kWave];
-        } else {
-            const uint32_t off = row_off(cur, s, W * kWave * 4);
-#pragma unroll
-            for (int w = 0; w < N; ++w) gload<1>(rs, lane * 4, off + w * kWave * 4, &e[s][w]);
-        }
-    }
+    for (int s = 0; s < kScanGroup; ++s) cut_masks<W, N, MODE>(img, rs, lane, cur, s, e[s]);
 #pragma unroll
     for (int s = 0; s < kScanGroup; ++s) column_step_n<N, W>(pv, cm, e[s]);
     return cut_decide<W, N>(pv, cm, kc, mask, kl);
@@ -322,7 +332,7 @@ __device__ __forceinline__ uint32_t cut_group(uint32_t (&pv)[W], uint32_t (&cm)[
 // group at `pos` and is advanced with it; `wsteps` (which starts from every
 // word stepped over every reported symbol) loses the W - N inactive words
 // over the run's reported symbols.
-template <int W, int N, bool LDS>
+template <int W, int N, int MODE>
 __device__ __forceinline__ uint32_t cut_run(uint32_t (&pv)[W], uint32_t (&cm)[W], const uint32_t *img,
                                             __amdgpu_buffer_rsrc_t rs, uint32_t lane, const const_u32 *text,
                                             uint32_t &next, uint32_t &pos, uint32_t len, uint32_t lb, uint32_t kc,
@@ -332,7 +342,7 @@ __device__ __forceinline__ uint32_t cut_run(uint32_t (&pv)[W], uint32_t (&cm)[W]
     do {
         const uint32_t cur = next;
         next = text[(pos >> 2) + 1];
-        ynew = cut_group<W, N, LDS>(pv, cm, img, rs, lane, cur, kc, mask, kl);
+        ynew = cut_group<W, N, MODE>(pv, cm, img, rs, lane, cur, kc, mask, kl);
         pos += kScanGroup;
     } while (ynew == N - 1 && pos < len);
     const uint32_t s0 = first > lb ? first : lb, s1 = pos < len ? pos : len;
@@ -357,9 +367,10 @@ __device__ __forceinline__ uint32_t cut_run(uint32_t (&pv)[W], uint32_t (&cm)[W]
 // hit in that XCD's L2.
 //
 // CUT: the word cutoff described above (one pattern per lane, W >= 2).
-template <int W, int P, bool LDSPEQ, bool CUT>
+template <int W, int P, int MODE, bool CUT>
 __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 : 1)) k_scan(ScanArgs a) {
     static_assert(!CUT || (P == 1 && W >= 2), "the cutoff is for one multi-word pattern per lane");
+    constexpr bool LDSPEQ = MODE == kImgLds;
     extern __shared__ uint32_t lds_img[];
     constexpr int PW = P * W;
     constexpr int PWS = pad_pow2(PW);
@@ -442,7 +453,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
     const uint32_t len = cd.scan_len, lb = cd.lookback;
     const uint32_t lane_off = lane * PWS;
     if (len > lb) wsteps = (uint64_t)(len - lb) * (W * nact);
-    const uint32_t *img = LDSPEQ ? lds_img : gimg;
+    const uint32_t *img = MODE == kImgGlobal ? gimg : lds_img;
     const __amdgpu_buffer_rsrc_t rs = image_rsrc(gimg, a.nclass * kWave * (CUT ? W : PWS) * 4);
 
     uint32_t y = W - 1;  // last active word (CUT); every word starts active
@@ -457,8 +468,8 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 #define OASM_CUT_CASE(n)                                                                                         \
     case n:                                                                                                      \
         if constexpr (n + 1 < W)                                                                                 \
-            ynew = cut_run<W, n + 1, LDSPEQ>(pv[0], mv[0], img, rs, lane, text, next, pos, len, lb, kc, lmask, \
-                                             kl, wsteps, nact);                                                  \
+            ynew = cut_run<W, n + 1, MODE>(pv[0], mv[0], img, rs, lane, text, next, pos, len, lb, kc, lmask, \
+                                           kl, wsteps, nact);                                                  \
         break;
                 OASM_CUT_CASE(0)
                 OASM_CUT_CASE(1)
@@ -487,15 +498,7 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 #pragma unroll
         for (int s = 0; s < kScanGroup; ++s) {
             if constexpr (CUT) {  // word-major image
-                if constexpr (LDSPEQ) {
-                    const uint32_t *r = at_bytes(img + lane, row_off(cur, s, W * kWave * 4));
-#pragma unroll
-                    for (int w = 0; w < W; ++w) e[s].v[w] = r[w * kWave];
-                } else {
-                    const uint32_t off = row_off(cur, s, W * kWave * 4);
-#pragma unroll
-                    for (int w = 0; w < W; ++w) gload<1>(rs, lane * 4, off + w * kWave * 4, &e[s].v[w]);
-                }
+                cut_masks<W, W, MODE>(img, rs, lane, cur, s, e[s].v);
             } else if constexpr (LDSPEQ) {
                 e[s] = *reinterpret_cast<const Words<PWS> *>(at_bytes(img + lane_off, row_off(cur, s, kWave * PWS * 4)));
             } else {
@@ -557,35 +560,36 @@ __global__ void __launch_bounds__(256, CUT ? (W <= 4 ? 6 : 1) : (P * W <= 4 ? 8 
 }
 
 template <int W, int P, bool CUT>
-static hipError_t launch_scan_t(const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+static hipError_t launch_scan_t(const ScanArgs &a, int waves, int mode, hipStream_t st) {
+    if (waves < 1 || waves > 4) return hipErrorInvalidValue;
     const uint32_t gx = (a.nchunks + waves - 1) / waves;
     if (gx == 0 || a.ntiles == 0) return hipSuccess;
     const uint64_t blocks = (uint64_t)((gx + kXcds - 1) / kXcds) * kXcds * a.ntiles;
     if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
-    const size_t shmem = lds ? (size_t)a.nclass * kWave * (CUT ? W : pad_pow2(P * W)) * 4 : 0;
-    if (lds) {
-        // raise the instance's dynamic-LDS limit once per device (never
-        // inside a graph capture: the first launch of a shape is always an
-        // eager one); contexts on several host threads share the table
-        static std::mutex mu;
-        static size_t configured[kMaxDevices] = {};
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e != hipSuccess) return e;
-        if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-        {
-            std::lock_guard<std::mutex> g(mu);
-            if (shmem > configured[dev]) {
-                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, true, CUT>),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
-                if (e != hipSuccess) return e;
-                configured[dev] = shmem;
-            }
-        }
-        hipLaunchKernelGGL((k_scan<W, P, true, CUT>), dim3((uint32_t)blocks), dim3(waves * kWave), shmem, st, a);
-    } else {
-        hipLaunchKernelGGL((k_scan<W, P, false, CUT>), dim3((uint32_t)blocks), dim3(waves * kWave), 0, st, a);
+    if (mode == kImgGlobal) {
+        hipLaunchKernelGGL((k_scan<W, P, kImgGlobal, CUT>), dim3((uint32_t)blocks), dim3(waves * kWave), 0, st, a);
+        return hipGetLastError();
     }
+    const size_t shmem = (size_t)a.nclass * kWave * (CUT ? W : pad_pow2(P * W)) * 4;
+    // raise the kernel's dynamic-LDS limit once per device (never inside a
+    // graph capture: the first launch of a shape is always an eager one);
+    // contexts on several host threads share the table
+    static std::mutex mu;
+    static size_t configured[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        if (shmem > configured[dev]) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_scan<W, P, kImgLds, CUT>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+            if (e != hipSuccess) return e;
+            configured[dev] = shmem;
+        }
+    }
+    hipLaunchKernelGGL((k_scan<W, P, kImgLds, CUT>), dim3((uint32_t)blocks), dim3(waves * kWave), shmem, st, a);
     return hipGetLastError();
 }
 
@@ -602,32 +606,33 @@ bool scan_variant_exists(int W, int P, bool cut) {
     }
 }
 
-hipError_t launch_scan(int W, int P, bool cut, const ScanArgs &a, int waves, bool lds, hipStream_t st) {
+hipError_t launch_scan(int W, int P, bool cut, const ScanArgs &a, int waves, int mode, hipStream_t st) {
+    if (mode != kImgGlobal && mode != kImgLds) return hipErrorInvalidValue;
     if (cut) {
         if (P != 1) return hipErrorInvalidValue;
         switch (W) {
-            case 2: return launch_scan_t<2, 1, true>(a, waves, lds, st);
-            case 3: return launch_scan_t<3, 1, true>(a, waves, lds, st);
-            case 4: return launch_scan_t<4, 1, true>(a, waves, lds, st);
-            case 5: return launch_scan_t<5, 1, true>(a, waves, lds, st);
-            case 6: return launch_scan_t<6, 1, true>(a, waves, lds, st);
-            case 7: return launch_scan_t<7, 1, true>(a, waves, lds, st);
-            case 8: return launch_scan_t<8, 1, true>(a, waves, lds, st);
+            case 2: return launch_scan_t<2, 1, true>(a, waves, mode, st);
+            case 3: return launch_scan_t<3, 1, true>(a, waves, mode, st);
+            case 4: return launch_scan_t<4, 1, true>(a, waves, mode, st);
+            case 5: return launch_scan_t<5, 1, true>(a, waves, mode, st);
+            case 6: return launch_scan_t<6, 1, true>(a, waves, mode, st);
+            case 7: return launch_scan_t<7, 1, true>(a, waves, mode, st);
+            case 8: return launch_scan_t<8, 1, true>(a, waves, mode, st);
             default: return hipErrorInvalidValue;
         }
     }
     switch (W * 16 + P) {
-        case 1 * 16 + 1: return launch_scan_t<1, 1, false>(a, waves, lds, st);
-        case 1 * 16 + 2: return launch_scan_t<1, 2, false>(a, waves, lds, st);
-        case 1 * 16 + 4: return launch_scan_t<1, 4, false>(a, waves, lds, st);
-        case 2 * 16 + 1: return launch_scan_t<2, 1, false>(a, waves, lds, st);
-        case 2 * 16 + 2: return launch_scan_t<2, 2, false>(a, waves, lds, st);
-        case 3 * 16 + 1: return launch_scan_t<3, 1, false>(a, waves, lds, st);
-        case 4 * 16 + 1: return launch_scan_t<4, 1, false>(a, waves, lds, st);
-        case 5 * 16 + 1: return launch_scan_t<5, 1, false>(a, waves, lds, st);
-        case 6 * 16 + 1: return launch_scan_t<6, 1, false>(a, waves, lds, st);
-        case 7 * 16 + 1: return launch_scan_t<7, 1, false>(a, waves, lds, st);
-        case 8 * 16 + 1: return launch_scan_t<8, 1, false>(a, waves, lds, st);
+        case 1 * 16 + 1: return launch_scan_t<1, 1, false>(a, waves, mode, st);
+        case 1 * 16 + 2: return launch_scan_t<1, 2, false>(a, waves, mode, st);
+        case 1 * 16 + 4: return launch_scan_t<1, 4, false>(a, waves, mode, st);
+        case 2 * 16 + 1: return launch_scan_t<2, 1, false>(a, waves, mode, st);
+        case 2 * 16 + 2: return launch_scan_t<2, 2, false>(a, waves, mode, st);
+        case 3 * 16 + 1: return launch_scan_t<3, 1, false>(a, waves, mode, st);
+        case 4 * 16 + 1: return launch_scan_t<4, 1, false>(a, waves, mode, st);
+        case 5 * 16 + 1: return launch_scan_t<5, 1, false>(a, waves, mode, st);
+        case 6 * 16 + 1: return launch_scan_t<6, 1, false>(a, waves, mode, st);
+        case 7 * 16 + 1: return launch_scan_t<7, 1, false>(a, waves, mode, st);
+        case 8 * 16 + 1: return launch_scan_t<8, 1, false>(a, waves, mode, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -8,8 +8,10 @@
 // test issues exactly the named instruction.  Output: one JSON object.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 
 namespace {
 
@@ -179,9 +181,76 @@ void launch_column_pair(uint32_t *d, int blocks, int iters) {
     hipLaunchKernelGGL(k_column_pair, dim3(blocks), dim3(256), 0, 0, d, iters, 1u);
 }
 
+// ------------------------------------------------------------------ HBM read calibration
+// Read kernels of known size, for scaling the FETCH_SIZE counter
+// (`valu_probe --read-calibration`): one reads with scalar loads, as the scan
+// reads its text (each wavefront walks its own 64 KiB run one dword at a time
+// through the scalar cache), the other with 16-byte vector loads, as a device
+// copy does.  Each dispatch reads kReadBytes once and writes one dword per
+// wavefront (16 KiB).
+constexpr size_t kReadBytes = size_t(256) << 20;
+constexpr uint32_t kRunWords = 16384;  // 64 KiB per wavefront
+constexpr uint32_t kReadWaves = (uint32_t)(kReadBytes / (kRunWords * 4));
+
+typedef __attribute__((address_space(4))) const uint32_t const_u32;
+
+__global__ void __launch_bounds__(256) k_read_scalar(const uint32_t *p, uint32_t *out) {
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
+    const const_u32 *q = (const const_u32 *)(p + (size_t)wave * kRunWords);
+    uint32_t acc = 0;
+#pragma nounroll
+    for (uint32_t i = 0; i < kRunWords; ++i) acc = acc * 31u + q[i];
+    if ((threadIdx.x & 63) == 0) out[wave] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_read_vector(const uint4 *p, uint32_t *out) {
+    const uint32_t wave = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const uint4 *q = p + (size_t)wave * (kRunWords / 4);
+    uint32_t acc = 0;
+    for (uint32_t i = lane; i < kRunWords / 4; i += 64) {
+        const uint4 v = q[i];
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, 64);
+    if (lane == 0) out[wave] = acc;
+}
+
+int read_calibration() {
+    uint32_t *buf = nullptr, *out = nullptr;
+    if (hipMalloc(&buf, kReadBytes) != hipSuccess || hipMalloc(&out, kReadWaves * 4) != hipSuccess) return 1;
+    if (hipMemset(buf, 1, kReadBytes) != hipSuccess) return 1;
+    double ms[2] = {0, 0};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return 1;
+    for (int k = 0; k < 2; ++k) {
+        for (int r = 0; r < 3; ++r) {
+            (void)hipEventRecord(e0, 0);
+            if (k == 0)
+                hipLaunchKernelGGL(k_read_scalar, dim3(kReadWaves / 4), dim3(256), 0, 0, buf, out);
+            else
+                hipLaunchKernelGGL(k_read_vector, dim3(kReadWaves / 4), dim3(256), 0, 0,
+                                   reinterpret_cast<const uint4 *>(buf), out);
+            (void)hipEventRecord(e1, 0);
+            if (hipEventSynchronize(e1) != hipSuccess) return 1;
+            float t = 0;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            ms[k] = r ? std::min(ms[k], (double)t) : (double)t;
+        }
+    }
+    std::printf("{\"read_bytes_per_dispatch\": %zu, \"write_bytes_per_dispatch\": %u, \"dispatches_each\": 3, "
+                "\"k_read_scalar_ms\": %.3f, \"k_read_vector_ms\": %.3f}\n",
+                kReadBytes, kReadWaves * 4, ms[0], ms[1]);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(buf);
+    (void)hipFree(out);
+    return hipGetLastError() == hipSuccess ? 0 : 1;
+}
+
 }  // namespace
 
-int main() {
+int main(int argc, char **argv) {
+    if (argc > 1 && std::strcmp(argv[1], "--read-calibration") == 0) return read_calibration();
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
