@@ -360,7 +360,7 @@ def summarize(w, r, workload):
             "device_step": round((s1["step_ms"] - s0["step_ms"]) / steps, 3),
             "sync_wall": round((s1["sync_wall_ms"] - s0["sync_wall_ms"]) / steps, 3),
             "sync_waiting": round((s1["wait_ms"] - s0["wait_ms"]) / steps, 3),
-            "host_plan_launch_copyback_convert": [round((b - a) / steps, 3) for a, b in
+            "host_plan_launch_convert_bookkeep": [round((b - a) / steps, 3) for a, b in
                                                   zip(s0["host_ms"], s1["host_ms"])],
             "python_feed_drain": round(elapsed / steps * 1e3 - (s1["sync_wall_ms"] - s0["sync_wall_ms"]) / steps, 3),
             "graph_replays": s1["graph_replays"] - s0["graph_replays"],
@@ -381,10 +381,15 @@ def serving_measure(oasm, torch, args):
 
     pats, ks = W.serving_dictionary()
     pool = W.serving_pool(args.serving_pool)
+    # mutated pattern copies in the pool (one per 3.3 KiB on average), so that
+    # sessions hold hit ends and the hit-set recovery and the filter have work
+    n_plants = args.serving_pool // 3355
+    W.plant(np.random.default_rng(23), pool, pats, n_plants, ks, W.LETTERS_MIX)
     dpool = torch.from_numpy(pool).cuda()
     msum = sum(len(p) for p in pats)
     out = {"workload": f"{args.serving_sessions} sessions, {len(pats)} patterns m~U[16,128] K=floor(m/10), "
-                       f"segments U[1,64] KiB of mixture bytes, Poisson arrivals",
+                       f"segments U[1,64] KiB of a {args.serving_pool >> 20} MiB pool of mixture bytes with "
+                       f"{n_plants} planted mutated pattern copies, Poisson arrivals",
            "mem_budget_bytes": args.serving_budget}
 
     def point(gbps, duration):
@@ -396,16 +401,26 @@ def serving_measure(oasm, torch, args):
             mt.serve(segs[:200].copy(), dpool, want_latency=False)
             mt.results()
         with oasm.Matcher(pats, ks, mem_budget=args.serving_budget, no_raw=True, autotune=True) as mt:
+            s0 = mt.stats()
             rep, lat = mt.serve(segs, dpool)
+            s1 = mt.stats()
             res = mt.results()
         nbytes = int(ln.sum())
+        ns = max(1, rep["steps"])
+        per_step = {"device_step_ms": round((s1["step_ms"] - s0["step_ms"]) / ns, 4),
+                    "scan_ms": round((s1["scan_ms"] - s0["scan_ms"]) / ns, 4),
+                    "sync_wall_ms": round((s1["sync_wall_ms"] - s0["sync_wall_ms"]) / ns, 4),
+                    "host_plan_launch_convert_bookkeep_ms": [round((b - a) / ns, 4) for a, b in
+                                                             zip(s0["host_ms"], s1["host_ms"])],
+                    "loop_busy_ms": round(rep["busy_s"] * 1e3 / ns, 4),
+                    "hit_ends": s1["raw_hits"] - s0["raw_hits"]}
         return {"offered_GBps": gbps, "arrival_window_s": duration, "segments": int(t.size), "bytes": nbytes,
                 "steps": rep["steps"], "deferred": rep["deferred"], "max_batch_bytes": rep["max_batch_bytes"],
                 "wall_s": round(rep["wall_s"], 3), "sustained_GBps": round(nbytes / rep["busy_s"] / 1e9, 4),
                 "gcups": round(msum * nbytes / rep["busy_s"] / 1e9, 1),
                 "latency_p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
                 "latency_p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
-                "occurrences": int(res.occ.size)}
+                "occurrences": int(res.occ.size), "per_step": per_step}
 
     hi = point(args.serving_gbps, args.serving_window)
     out["at_offered_load"] = hi

@@ -180,7 +180,7 @@ typedef struct oasm_serve_report {
     uint64_t deferred;        /* loop iterations that left ready segments waiting for memory */
     uint64_t max_batch_bytes; /* largest batch */
     double wall_s;            /* start of the run to the last completion */
-    double busy_s;            /* time spent in ingest and matching steps */
+    double busy_s;            /* wall_s less the time spent sleeping for arrivals */
 } oasm_serve_report;
 
 /* Per-context counters (cumulative since create). */
@@ -198,8 +198,9 @@ typedef struct oasm_stats {
     double sync_wall_ms;        /* host wall time spent inside oasm_sync */
     double wait_ms;             /* part of it spent waiting for the device */
     double host_ms[4];          /* host time per step phase, device waits excluded: plan and
-                                   upload; launches up to the step's end; copy-back of the
-                                   results; result conversion and stream bookkeeping */
+                                   upload; launches (and re-launches after a capacity overflow);
+                                   conversion of the results into the drain queues; stream
+                                   bookkeeping (look-back tails, closes, carried ends) */
     uint64_t graph_replays;     /* steps launched from captured graphs */
     uint64_t word_steps_done;   /* pattern-column words the scan advanced over the symbols it
                                    reported: word_steps less the words the word cutoff skipped */
@@ -290,15 +291,21 @@ oasm_status oasm_hits(oasm_ctx *ctx, uint32_t kind, void *out, size_t cap, size_
  * Continuous-batching request loop over `n` segments sorted by arrival_s.
  * Segments are admitted in arrival order as soon as they have arrived, while
  * the fed-but-unmatched bytes stay within cfg.device_mem_budget (0 = no
- * limit; one segment is always admitted when nothing is pending).  Each
- * iteration copies every admitted segment from `dev_pool` (device memory of
- * `pool_bytes` bytes, owned by the caller) into its stream with one batched
- * kernel and runs one matching step over all of them, so segments of many
- * streams share each launch while later arrivals wait for the next one.  The
- * loop runs in real time: when nothing is ready it sleeps until the next
- * arrival.  latency_s (optional, n entries) receives, per segment, the time
- * from its arrival to the end of the step that matched it (its hit ends are
- * then drainable and its filter has advanced as far as the bytes allow).
+ * limit; one segment is always admitted when nothing is pending).  Admitted
+ * segments are copied from `dev_pool` (device memory of `pool_bytes` bytes,
+ * owned by the caller) into their streams by one batched kernel per
+ * admission, and one matching step runs over every stream with new bytes, so
+ * segments of many streams share each launch.  The loop is pipelined: while
+ * a step runs on the device, the host converts the previous step's results
+ * and admits and copies the segments that arrive (queued behind the running
+ * step); when the step ends, the segments that arrived meanwhile are admitted
+ * too and the next step is launched at once.  Bytes fed before the run (not
+ * yet matched) are matched with the first step.  The loop runs in real time:
+ * when nothing is ready or running it sleeps until the next arrival.
+ * latency_s (optional, n entries) receives, per segment, the time from its
+ * arrival to the moment the results of the step that matched it are queued
+ * (its hit ends are then drainable and its filter has advanced as far as the
+ * bytes allow).
  * Results are queued as by oasm_sync.  `report` (optional) is written on
  * every return, errors included: segments are served in arrival order, so
  * the served ones are segs[0 .. report->segments).  Errors: OASM_E_INVAL

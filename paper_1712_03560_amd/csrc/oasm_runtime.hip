@@ -169,7 +169,8 @@ struct oasm_ctx {
     DevBuf carry_buf[2], carry_hk_buf[2];
     int carry_cur = 0;
     uint32_t ncarry = 0;
-    PinBuf pin_plan, pin_ctl, pin_out, pin_feed;
+    PinBuf pin_plan, pin_ctl, pin_out[2], pin_feed;  // results: two buffers, so that a step's results
+                                                     // can be read while the next step runs
     size_t pin_feed_used = 0;
     uint32_t cap = 256;         // records per scan item
     uint32_t cap_n = 1u << 16;  // hit ends per step (carried + new)
@@ -215,6 +216,11 @@ struct oasm_ctx {
     size_t slab_left = 0;
     std::vector<StagingMove> moves;         // queued staging moves (launched by flush_moves)
     std::vector<std::pair<uint8_t *, size_t>> move_release;  // buffers the queued moves read
+    // While a launched step has not been waited for (the serving loop admits
+    // segments meanwhile), buffers that it may read are held back from the
+    // pool: a re-run of the step after a capacity overflow reads them again.
+    bool hold_release = false;
+    std::vector<std::pair<uint8_t *, size_t>> held;
 };
 
 namespace {
@@ -352,27 +358,283 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which_in, StepPlan &pl
     }
 }
 
+// Room for `more` records at the end of a result queue, growing it at least
+// geometrically (an exact reserve would copy the whole queue at every step
+// when the caller drains rarely, as a serving run does).
+template <class T>
+void grow_for(std::vector<T> &q, size_t more) {
+    if (q.size() + more > q.capacity()) q.reserve(std::max(q.size() + more, 2 * q.capacity()));
+}
+
 // ------------------------------------------------------------------ step
-void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
-    hipStream_t st = c->st;
-    double tmark = now_ms(), twait0 = c->stats.wait_ms;
-    // host time since the last mark, excluding device waits, into phase ph
-    auto phase = [&](int ph) {
+// One matching step, from its launch to its results.  run_step runs the four
+// parts back to back; the serving loop launches the next step before it
+// converts this one's results (and admits new arrivals while a step runs).
+struct StepRun {
+    bool active = false;
+    StepPlan pl;
+    std::vector<uint32_t> which;     // streams with new bytes (ctx->streams indices)
+    std::vector<uint64_t> scan_to;   // per `which` entry: its symbols matched by this step
+    std::vector<char> closing;       // per `which` entry: the stream ends with this step
+    std::vector<uint64_t> ids;       // per step-local stream: the stream id
+    // fixed at launch (a re-run after a capacity overflow reuses them)
+    size_t o_chunks = 0, o_sdesc = 0, o_s2l = 0;
+    uint32_t nchunks = 0, ncarry = 0, key_bits = 0;
+    int cin = 0, cout = 1, pin = 0;
+    bool keep_raw = true, keep_h = false;
+    // from the completed step
+    PackArgs layout{};
+    uint32_t n_new = 0, nocc = 0, ncarry_out = 0;
+};
+
+// host time since the last mark, excluding device waits, into phase ph
+struct PhaseClock {
+    oasm_ctx *c;
+    double tmark, twait0;
+    explicit PhaseClock(oasm_ctx *cc) : c(cc), tmark(now_ms()), twait0(cc->stats.wait_ms) {}
+    void operator()(int ph) {
         const double t = now_ms();
         c->stats.host_ms[ph] += (t - tmark) - (c->stats.wait_ms - twait0);
         tmark = t;
         twait0 = c->stats.wait_ms;
+    }
+};
+
+// Queue one attempt of the step's launch sequence (buffers sized by the
+// context's current capacities), ending with ev2.
+void step_enqueue(oasm_ctx *c, StepRun &r) {
+    hipStream_t st = c->st;
+    uint8_t *pb = c->plan.as<uint8_t>();
+    const ChunkDesc *d_chunks = reinterpret_cast<const ChunkDesc *>(pb + r.o_chunks);
+    const StreamDesc *d_sdesc = reinterpret_cast<const StreamDesc *>(pb + r.o_sdesc);
+    const uint32_t *d_s2l = reinterpret_cast<const uint32_t *>(pb + r.o_s2l);
+    const uint32_t nchunks = r.nchunks, ncarry = r.ncarry, key_bits = r.key_bits;
+    const int cin = r.cin, cout = r.cout;
+    const CarryRec *d_carry = c->carry_buf[cin].as<CarryRec>();
+    const uint8_t *d_carry_hk = c->carry_hk_buf[cin].as<uint8_t>();
+    uint32_t *ctl = c->ctl.as<uint32_t>();
+    const uint64_t nitems = (uint64_t)nchunks * c->ntiles;
+    const uint32_t hks = c->hks;
+    const uint32_t out_stride = c->kmax + 1;
+    const uint32_t rules = c->rules;
+    const bool keep_any_raw = r.keep_raw || r.keep_h;
+    PinBuf &pin_out = c->pin_out[r.pin];
+
+    const uint32_t cap_n = c->cap_n, cap_occ = c->cap_occ, cap_carry = c->cap_carry;
+    const uint64_t n1 = cap_n;
+    c->item_rec.ensure(std::max<uint64_t>(1, nitems) * c->cap * 4, st);
+    c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint64_t>({nitems, n1, 1})) * 4, 1024), st);
+    c->sort_key.ensure(n1 * 8, st);  // two halves: ping-pong
+    c->sort_val.ensure(n1 * 8, st);
+    c->sort_end.ensure(n1 * 8, st);
+    c->sort_tmp.ensure(sort_tmp_words((uint32_t)n1) * 4, st);
+    c->r_pat.ensure(n1 * 4, st);
+    c->r_sl.ensure(n1 * 4, st);
+    c->r_end.ensure(n1 * 8, st);
+    c->r_flag.ensure(n1, st);
+    c->r_dist.ensure(n1, st);
+    c->r_hk.ensure(n1 * hks, st);
+    c->seg_cnt.ensure(n1 * 4, st);
+    c->seg_off.ensure(n1 * 4, st);
+    c->carry_flag.ensure(n1 * 4, st);
+    c->carry_off.ensure(n1 * 4, st);
+    c->seg_out.ensure(n1 * out_stride * sizeof(OccRec), st);
+    c->occ_out.ensure((uint64_t)cap_occ * sizeof(OccRec), st);
+    c->carry_buf[cout].ensure((uint64_t)cap_carry * sizeof(CarryRec), st);
+    c->carry_hk_buf[cout].ensure((uint64_t)cap_carry * hks, st);
+
+    // layout of the mapped pinned results buffer, by capacity
+    PackArgs pk{};
+    {
+        size_t off = 0;
+        auto region = [&](size_t bytes) {
+            const size_t o = (off + 255) & ~size_t(255);
+            off = o + bytes;
+            return (uint64_t)o;
+        };
+        pk.o_ctl = region(64);
+        pk.o_pat = region(keep_any_raw ? n1 * 4 : 0);
+        pk.o_sl = region(keep_any_raw ? n1 * 4 : 0);
+        pk.o_end = region(keep_any_raw ? n1 * 8 : 0);
+        pk.o_flag = region(keep_any_raw ? n1 : 0);
+        pk.o_dist = region(keep_any_raw ? n1 : 0);
+        pk.o_hk = region(r.keep_h ? n1 * hks : 0);
+        pk.o_occ = region((size_t)cap_occ * sizeof(OccRec));
+        pk.o_cr = region((size_t)cap_carry * sizeof(CarryRec));
+        pin_out.ensure(off + 256, st);
+    }
+    void *dev_host = nullptr;
+    ck(hipHostGetDevicePointer(&dev_host, pin_out.p, 0), "mapped results buffer");
+
+    // The step's launch sequence in two parts (the scan, then everything
+    // after it), with the scan-timing event between them.
+    auto part_a = [&]() {
+        ck(launch_fill_u32(ctl, 0, 16, st), "fill ctl");
+        uint32_t item_base = 0;
+        for (const ClassInfo &ci : c->classes) {
+            ScanArgs a;
+            a.chunks = d_chunks;
+            a.nchunks = nchunks;
+            a.tiles = c->d_tiles.as<TileDesc>();
+            a.tile_first = ci.tile_first;
+            a.ntiles = ci.ntiles;
+            a.peq_img = c->d_peq.as<uint32_t>();
+            a.slot_pat = c->d_slot_pat.as<uint32_t>();
+            a.pats = c->d_pats.as<PatDesc>();
+            a.nclass = c->nclass;
+            a.item_rec = c->item_rec.as<uint32_t>();
+            a.item_cnt = c->item_cnt.as<uint32_t>();
+            a.item_base = item_base;
+            a.cap = c->cap;
+            a.max_cnt = ctl + 0;
+            a.wsteps = reinterpret_cast<unsigned long long *>(ctl + 8);
+            ck(launch_scan(ci.W, ci.P, ci.cut, a, ci.waves, ci.lds, st), "scan launch");
+            item_base += nchunks * ci.ntiles;
+            c->stats.scan_launches++;
+        }
     };
-    StepPlan pl;
-    build_plan(c, which, pl);
-    if ((uint64_t)pl.locals.size() * c->npat >= (1ull << 32))
+    auto part_b = [&]() {
+        const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems, nullptr, 0u};
+        ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), items, ctl + 1,
+                                 c->scan_tmp.as<uint32_t>(), st),
+           "item count scan");
+        const DevN dn{ctl + 1, ncarry, cap_n, ctl + 0, c->cap};  // carried + new hit ends
+        uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
+        uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
+        ck(launch_place_carry(d_carry, std::min(ncarry, cap_n), d_s2l, c->npat, key0, val0, c->sort_end.as<uint64_t>(),
+                              st),
+           "place carry");
+        uint32_t item_base = 0;
+        for (const ClassInfo &ci : c->classes) {
+            ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
+                                  c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(), c->item_cnt.as<uint32_t>(),
+                                  c->offsets.as<uint32_t>(), item_base, c->cap, ncarry, cap_n, c->npat, key0, val0,
+                                  c->sort_end.as<uint64_t>(), st),
+               "compact hit ends");
+            item_base += nchunks * ci.ntiles;
+        }
+        bool second = false;
+        ck(launch_radix_sort(key0, val0, key1, val1, dn, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
+           "radix sort");
+        ck(launch_gather_raw(second ? key1 : key0, second ? val1 : val0, dn, c->npat, ncarry,
+                             c->sort_end.as<uint64_t>(), d_carry, d_carry_hk, hks, c->r_pat.as<uint32_t>(),
+                             c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(),
+                             c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), st),
+           "gather hit ends");
+        ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                          c->r_flag.as<uint8_t>(), dn, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
+                          c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
+           "recover");
+        ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                         c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, rules, out_stride,
+                         c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
+           "filter");
+        ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
+                                 c->scan_tmp.as<uint32_t>(), st),
+           "occ scan");
+        ck(launch_exclusive_scan(c->carry_flag.as<uint32_t>(), c->carry_off.as<uint32_t>(), dn, ctl + 3,
+                                 c->scan_tmp.as<uint32_t>(), st),
+           "carry scan");
+        ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn,
+                              out_stride, c->occ_out.as<OccRec>(), cap_occ, st),
+           "compact occ");
+        ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
+                                c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
+                                c->carry_off.as<uint32_t>(), d_sdesc, dn, c->carry_buf[cout].as<CarryRec>(),
+                                c->carry_hk_buf[cout].as<uint8_t>(), cap_carry, st),
+           "compact carry");
+        pk.ctl = ctl;
+        pk.n = dn;
+        pk.r_pat = c->r_pat.as<uint32_t>();
+        pk.r_sl = c->r_sl.as<uint32_t>();
+        pk.r_end = c->r_end.as<uint64_t>();
+        pk.r_flag = c->r_flag.as<uint8_t>();
+        pk.r_dist = c->r_dist.as<uint8_t>();
+        pk.r_hk = c->r_hk.as<uint8_t>();
+        pk.hks = hks;
+        pk.with_raw = keep_any_raw ? 1u : 0u;
+        pk.with_hk = r.keep_h ? 1u : 0u;
+        pk.occ = c->occ_out.as<OccRec>();
+        pk.cap_occ = cap_occ;
+        pk.carry = c->carry_buf[cout].as<CarryRec>();
+        pk.cap_carry = cap_carry;
+        pk.host = reinterpret_cast<uint8_t *>(dev_host);
+        ck(launch_pack_results(pk, st), "pack results");
+    };
+    // Replay captured graphs when this step has the same shape (every kernel
+    // argument and buffer) as the last; capture when a shape repeats.
+    std::vector<uint64_t> gkey;
+    if (c->cfg.flags & OASM_CFG_GRAPHS) {
+        gkey = {nchunks, ncarry, c->cap, cap_n, cap_occ, cap_carry, key_bits, (uint64_t)r.pl.locals.size(),
+                (uint64_t)(uintptr_t)c->plan.p, r.o_chunks, r.o_sdesc, r.o_s2l, (uint64_t)cin,
+                (uint64_t)(uintptr_t)c->item_rec.p, (uint64_t)(uintptr_t)c->scan_tmp.p,
+                (uint64_t)(uintptr_t)c->sort_key.p, (uint64_t)(uintptr_t)c->sort_tmp.p,
+                (uint64_t)(uintptr_t)c->seg_out.p, (uint64_t)(uintptr_t)c->occ_out.p,
+                (uint64_t)(uintptr_t)c->carry_buf[cin].p, (uint64_t)(uintptr_t)c->carry_buf[cout].p,
+                (uint64_t)(uintptr_t)c->r_hk.p, (uint64_t)(uintptr_t)pin_out.p, (uint64_t)keep_any_raw,
+                (uint64_t)r.keep_h};
+    }
+    if (!gkey.empty() && gkey == c->graph_key && c->graph_a) {
+        ck(hipEventRecord(c->ev0, st), "event");
+        ck(hipGraphLaunch(c->graph_a, st), "graph launch");
+        ck(hipEventRecord(c->ev1, st), "event");
+        ck(hipGraphLaunch(c->graph_b, st), "graph launch");
+        c->stats.scan_launches += c->classes.size();
+        c->stats.graph_replays++;
+    } else if (!gkey.empty() && gkey == c->graph_prev_key) {
+        drop_graphs(c);
+        hipGraph_t ga = nullptr, gb = nullptr;
+        ck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+        part_a();
+        ck(hipStreamEndCapture(st, &ga), "end capture");
+        ck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+        part_b();
+        ck(hipStreamEndCapture(st, &gb), "end capture");
+        ck(hipGraphInstantiate(&c->graph_a, ga, nullptr, nullptr, 0), "graph instantiate");
+        ck(hipGraphInstantiate(&c->graph_b, gb, nullptr, nullptr, 0), "graph instantiate");
+        ck(hipGraphDestroy(ga), "graph destroy");
+        ck(hipGraphDestroy(gb), "graph destroy");
+        c->graph_key = gkey;
+        ck(hipEventRecord(c->ev0, st), "event");
+        ck(hipGraphLaunch(c->graph_a, st), "graph launch");
+        ck(hipEventRecord(c->ev1, st), "event");
+        ck(hipGraphLaunch(c->graph_b, st), "graph launch");
+    } else {
+        ck(hipEventRecord(c->ev0, st), "event");
+        part_a();
+        ck(hipEventRecord(c->ev1, st), "event");
+        part_b();
+    }
+    ck(hipEventRecord(c->ev2, st), "event");
+    c->graph_prev_key = gkey;
+    r.layout = pk;
+}
+
+// Plan the step over `which` (plus the streams holding carried hit ends),
+// upload the plan and queue the launch sequence.  Returns without waiting.
+void step_launch(oasm_ctx *c, const std::vector<uint32_t> &which, StepRun &r, int pin) {
+    hipStream_t st = c->st;
+    PhaseClock phase(c);
+    r = StepRun{};
+    r.which = which;
+    r.pin = pin;
+    build_plan(c, which, r.pl);
+    if ((uint64_t)r.pl.locals.size() * c->npat >= (1ull << 32))
         throw HipFail{hipErrorInvalidValue, "step too large (streams x patterns exceed 2^32)"};
+    r.ids.resize(r.pl.locals.size());
+    for (size_t l = 0; l < r.pl.locals.size(); ++l) r.ids[l] = c->streams[r.pl.locals[l]].id;
+    r.scan_to.resize(which.size());
+    r.closing.resize(which.size());
+    for (size_t k = 0; k < which.size(); ++k) {
+        r.scan_to[k] = c->streams[which[k]].valid;
+        r.closing[k] = c->streams[which[k]].close_pending ? 1 : 0;
+    }
 
     // upload the plan in one copy
     std::vector<uint8_t> blob;
-    const size_t o_chunks = put(blob, pl.chunks);
-    const size_t o_sdesc = put(blob, pl.sdesc);
-    const size_t o_s2l = put(blob, pl.slot_to_local);
+    r.o_chunks = put(blob, r.pl.chunks);
+    r.o_sdesc = put(blob, r.pl.sdesc);
+    r.o_s2l = put(blob, r.pl.slot_to_local);
     blob.resize(blob.size() + 16);
     c->pin_plan.ensure(blob.size(), st);
     wait_stream(c, "sync before plan upload");  // the pinned plan of the last step may still be read
@@ -380,325 +642,99 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
     c->plan.ensure(blob.size(), st);
     ck(hipMemcpyAsync(c->plan.p, c->pin_plan.p, blob.size(), hipMemcpyHostToDevice, st), "plan upload");
     phase(0);
-    uint8_t *pb = c->plan.as<uint8_t>();
-    const ChunkDesc *d_chunks = reinterpret_cast<const ChunkDesc *>(pb + o_chunks);
-    const StreamDesc *d_sdesc = reinterpret_cast<const StreamDesc *>(pb + o_sdesc);
-    const uint32_t *d_s2l = reinterpret_cast<const uint32_t *>(pb + o_s2l);
-    const uint32_t nchunks = (uint32_t)pl.chunks.size();
-    const uint32_t ncarry = c->ncarry;
-    const int cin = c->carry_cur, cout = 1 - c->carry_cur;
-    c->carry_buf[cin].ensure(std::max<uint32_t>(ncarry, 1) * sizeof(CarryRec), st);
-    c->carry_hk_buf[cin].ensure(std::max<uint32_t>(ncarry, 1) * (uint64_t)c->hks, st);
-    const CarryRec *d_carry = c->carry_buf[cin].as<CarryRec>();
-    const uint8_t *d_carry_hk = c->carry_hk_buf[cin].as<uint8_t>();
-
+    r.nchunks = (uint32_t)r.pl.chunks.size();
+    r.ncarry = c->ncarry;
+    r.cin = c->carry_cur;
+    r.cout = 1 - c->carry_cur;
+    c->carry_buf[r.cin].ensure(std::max<uint32_t>(r.ncarry, 1) * sizeof(CarryRec), st);
+    c->carry_hk_buf[r.cin].ensure(std::max<uint32_t>(r.ncarry, 1) * (uint64_t)c->hks, st);
     // control words: [0] max item count, [1] new hit ends, [2] occurrences, [3] carried, [4] recovery errors
     c->ctl.ensure(64, st);
-    uint32_t *ctl = c->ctl.as<uint32_t>();
     c->pin_ctl.ensure(64, st);
-
-    const uint64_t nitems = (uint64_t)nchunks * c->ntiles;
-    const uint32_t hks = c->hks;
-    const uint32_t out_stride = c->kmax + 1;
-    const uint32_t rules = c->rules;
-    uint32_t key_bits = 0;
-    while (key_bits < 32 && ((uint64_t)1 << key_bits) < (uint64_t)pl.locals.size() * c->npat) ++key_bits;
+    const uint64_t nitems = (uint64_t)r.nchunks * c->ntiles;
+    while (r.key_bits < 32 && ((uint64_t)1 << r.key_bits) < (uint64_t)r.pl.locals.size() * c->npat) ++r.key_bits;
     c->item_cnt.ensure(std::max<uint64_t>(1, nitems) * 4, st);
     c->offsets.ensure(std::max<uint64_t>(1, nitems) * 4, st);
-
-    const bool keep_raw = !(c->cfg.flags & OASM_CFG_NO_RAW);
-    const bool keep_h_out = (c->cfg.flags & OASM_CFG_KEEP_H) != 0;
-    const bool keep_any_raw = keep_raw || keep_h_out;
-
+    r.keep_raw = !(c->cfg.flags & OASM_CFG_NO_RAW);
+    r.keep_h = (c->cfg.flags & OASM_CFG_KEEP_H) != 0;
     // The whole step is queued at once: every kernel after the scan reads its
     // size from device memory and the buffers are sized by capacities that
     // grow (and the step runs again) when a count exceeds them.
-    uint32_t n_new = 0, nocc = 0, ncarry_out = 0;
-    PackArgs layout{};
-    for (int attempt = 0;; ++attempt) {
-        const uint32_t cap_n = c->cap_n, cap_occ = c->cap_occ, cap_carry = c->cap_carry;
-        const uint64_t n1 = cap_n;
-        c->item_rec.ensure(std::max<uint64_t>(1, nitems) * c->cap * 4, st);
-        c->scan_tmp.ensure(std::max<size_t>(scan_tmp_words(std::max<uint64_t>({nitems, n1, 1})) * 4, 1024), st);
-        c->sort_key.ensure(n1 * 8, st);  // two halves: ping-pong
-        c->sort_val.ensure(n1 * 8, st);
-        c->sort_end.ensure(n1 * 8, st);
-        c->sort_tmp.ensure(sort_tmp_words((uint32_t)n1) * 4, st);
-        c->r_pat.ensure(n1 * 4, st);
-        c->r_sl.ensure(n1 * 4, st);
-        c->r_end.ensure(n1 * 8, st);
-        c->r_flag.ensure(n1, st);
-        c->r_dist.ensure(n1, st);
-        c->r_hk.ensure(n1 * hks, st);
-        c->seg_cnt.ensure(n1 * 4, st);
-        c->seg_off.ensure(n1 * 4, st);
-        c->carry_flag.ensure(n1 * 4, st);
-        c->carry_off.ensure(n1 * 4, st);
-        c->seg_out.ensure(n1 * out_stride * sizeof(OccRec), st);
-        c->occ_out.ensure((uint64_t)cap_occ * sizeof(OccRec), st);
-        c->carry_buf[cout].ensure((uint64_t)cap_carry * sizeof(CarryRec), st);
-        c->carry_hk_buf[cout].ensure((uint64_t)cap_carry * hks, st);
+    step_enqueue(c, r);
+    r.active = true;
+    c->hold_release = true;
+    phase(1);
+}
 
-        // layout of the mapped pinned results buffer, by capacity
-        PackArgs pk{};
-        {
-            size_t off = 0;
-            auto region = [&](size_t bytes) {
-                const size_t o = (off + 255) & ~size_t(255);
-                off = o + bytes;
-                return (uint64_t)o;
-            };
-            pk.o_ctl = region(64);
-            pk.o_pat = region(keep_any_raw ? n1 * 4 : 0);
-            pk.o_sl = region(keep_any_raw ? n1 * 4 : 0);
-            pk.o_end = region(keep_any_raw ? n1 * 8 : 0);
-            pk.o_flag = region(keep_any_raw ? n1 : 0);
-            pk.o_dist = region(keep_any_raw ? n1 : 0);
-            pk.o_hk = region(keep_h_out ? n1 * hks : 0);
-            pk.o_occ = region((size_t)cap_occ * sizeof(OccRec));
-            pk.o_cr = region((size_t)cap_carry * sizeof(CarryRec));
-            c->pin_out.ensure(off + 256, st);
-        }
-        void *dev_host = nullptr;
-        ck(hipHostGetDevicePointer(&dev_host, c->pin_out.p, 0), "mapped results buffer");
-
-        // The step's launch sequence in two parts (the scan, then everything
-        // after it), with the scan-timing event between them.
-        auto part_a = [&]() {
-            ck(launch_fill_u32(ctl, 0, 16, st), "fill ctl");
-            uint32_t item_base = 0;
-            for (const ClassInfo &ci : c->classes) {
-                ScanArgs a;
-                a.chunks = d_chunks;
-                a.nchunks = nchunks;
-                a.tiles = c->d_tiles.as<TileDesc>();
-                a.tile_first = ci.tile_first;
-                a.ntiles = ci.ntiles;
-                a.peq_img = c->d_peq.as<uint32_t>();
-                a.slot_pat = c->d_slot_pat.as<uint32_t>();
-                a.pats = c->d_pats.as<PatDesc>();
-                a.nclass = c->nclass;
-                a.item_rec = c->item_rec.as<uint32_t>();
-                a.item_cnt = c->item_cnt.as<uint32_t>();
-                a.item_base = item_base;
-                a.cap = c->cap;
-                a.max_cnt = ctl + 0;
-                a.wsteps = reinterpret_cast<unsigned long long *>(ctl + 8);
-                ck(launch_scan(ci.W, ci.P, ci.cut, a, ci.waves, ci.lds, st), "scan launch");
-                item_base += nchunks * ci.ntiles;
-                c->stats.scan_launches++;
-            }
-        };
-        auto part_b = [&]() {
-            const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems, nullptr, 0u};
-            ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), items, ctl + 1,
-                                     c->scan_tmp.as<uint32_t>(), st),
-               "item count scan");
-            const DevN dn{ctl + 1, ncarry, cap_n, ctl + 0, c->cap};  // carried + new hit ends
-            uint32_t *key0 = c->sort_key.as<uint32_t>(), *key1 = key0 + n1;
-            uint32_t *val0 = c->sort_val.as<uint32_t>(), *val1 = val0 + n1;
-            ck(launch_place_carry(d_carry, std::min(ncarry, cap_n), d_s2l, c->npat, key0, val0,
-                                  c->sort_end.as<uint64_t>(), st),
-               "place carry");
-            uint32_t item_base = 0;
-            for (const ClassInfo &ci : c->classes) {
-                ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
-                                      c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(),
-                                      c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), item_base, c->cap, ncarry,
-                                      cap_n, c->npat, key0, val0, c->sort_end.as<uint64_t>(), st),
-                   "compact hit ends");
-                item_base += nchunks * ci.ntiles;
-            }
-            bool second = false;
-            ck(launch_radix_sort(key0, val0, key1, val1, dn, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
-               "radix sort");
-            ck(launch_gather_raw(second ? key1 : key0, second ? val1 : val0, dn, c->npat, ncarry,
-                                 c->sort_end.as<uint64_t>(), d_carry, d_carry_hk, hks, c->r_pat.as<uint32_t>(),
-                                 c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(), c->r_flag.as<uint8_t>(),
-                                 c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), st),
-               "gather hit ends");
-            ck(launch_recover(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                              c->r_flag.as<uint8_t>(), dn, c->d_pats.as<PatDesc>(), c->d_rpeq.as<uint64_t>(), d_sdesc,
-                              c->nclass, hks, c->r_hk.as<uint8_t>(), c->r_dist.as<uint8_t>(), ctl + 4, st),
-               "recover");
-            ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                             c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, rules, out_stride,
-                             c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
-               "filter");
-            ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
-                                     c->scan_tmp.as<uint32_t>(), st),
-               "occ scan");
-            ck(launch_exclusive_scan(c->carry_flag.as<uint32_t>(), c->carry_off.as<uint32_t>(), dn, ctl + 3,
-                                     c->scan_tmp.as<uint32_t>(), st),
-               "carry scan");
-            ck(launch_compact_occ(c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn,
-                                  out_stride, c->occ_out.as<OccRec>(), cap_occ, st),
-               "compact occ");
-            ck(launch_compact_carry(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
-                                    c->r_dist.as<uint8_t>(), c->r_hk.as<uint8_t>(), hks, c->carry_flag.as<uint32_t>(),
-                                    c->carry_off.as<uint32_t>(), d_sdesc, dn, c->carry_buf[cout].as<CarryRec>(),
-                                    c->carry_hk_buf[cout].as<uint8_t>(), cap_carry, st),
-               "compact carry");
-            pk.ctl = ctl;
-            pk.n = dn;
-            pk.r_pat = c->r_pat.as<uint32_t>();
-            pk.r_sl = c->r_sl.as<uint32_t>();
-            pk.r_end = c->r_end.as<uint64_t>();
-            pk.r_flag = c->r_flag.as<uint8_t>();
-            pk.r_dist = c->r_dist.as<uint8_t>();
-            pk.r_hk = c->r_hk.as<uint8_t>();
-            pk.hks = hks;
-            pk.with_raw = keep_any_raw ? 1u : 0u;
-            pk.with_hk = keep_h_out ? 1u : 0u;
-            pk.occ = c->occ_out.as<OccRec>();
-            pk.cap_occ = cap_occ;
-            pk.carry = c->carry_buf[cout].as<CarryRec>();
-            pk.cap_carry = cap_carry;
-            pk.host = reinterpret_cast<uint8_t *>(dev_host);
-            ck(launch_pack_results(pk, st), "pack results");
-        };
-        // Replay captured graphs when this step has the same shape (every kernel
-        // argument and buffer) as the last; capture when a shape repeats.
-        std::vector<uint64_t> gkey;
-        if (c->cfg.flags & OASM_CFG_GRAPHS) {
-            gkey = {nchunks, ncarry, c->cap, cap_n, cap_occ, cap_carry, key_bits, (uint64_t)pl.locals.size(),
-                    (uint64_t)(uintptr_t)c->plan.p, o_chunks, o_sdesc, o_s2l, (uint64_t)cin,
-                    (uint64_t)(uintptr_t)c->item_rec.p, (uint64_t)(uintptr_t)c->scan_tmp.p,
-                    (uint64_t)(uintptr_t)c->sort_key.p, (uint64_t)(uintptr_t)c->sort_tmp.p,
-                    (uint64_t)(uintptr_t)c->seg_out.p, (uint64_t)(uintptr_t)c->occ_out.p,
-                    (uint64_t)(uintptr_t)c->carry_buf[cin].p, (uint64_t)(uintptr_t)c->carry_buf[cout].p,
-                    (uint64_t)(uintptr_t)c->r_hk.p, (uint64_t)(uintptr_t)c->pin_out.p, (uint64_t)keep_any_raw,
-                    (uint64_t)keep_h_out};
-        }
-        if (!gkey.empty() && gkey == c->graph_key && c->graph_a) {
-            ck(hipEventRecord(c->ev0, st), "event");
-            ck(hipGraphLaunch(c->graph_a, st), "graph launch");
-            ck(hipEventRecord(c->ev1, st), "event");
-            ck(hipGraphLaunch(c->graph_b, st), "graph launch");
-            c->stats.scan_launches += c->classes.size();
-            c->stats.graph_replays++;
-        } else if (!gkey.empty() && gkey == c->graph_prev_key) {
-            drop_graphs(c);
-            hipGraph_t ga = nullptr, gb = nullptr;
-            ck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-            part_a();
-            ck(hipStreamEndCapture(st, &ga), "end capture");
-            ck(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-            part_b();
-            ck(hipStreamEndCapture(st, &gb), "end capture");
-            ck(hipGraphInstantiate(&c->graph_a, ga, nullptr, nullptr, 0), "graph instantiate");
-            ck(hipGraphInstantiate(&c->graph_b, gb, nullptr, nullptr, 0), "graph instantiate");
-            ck(hipGraphDestroy(ga), "graph destroy");
-            ck(hipGraphDestroy(gb), "graph destroy");
-            c->graph_key = gkey;
-            ck(hipEventRecord(c->ev0, st), "event");
-            ck(hipGraphLaunch(c->graph_a, st), "graph launch");
-            ck(hipEventRecord(c->ev1, st), "event");
-            ck(hipGraphLaunch(c->graph_b, st), "graph launch");
-        } else {
-            ck(hipEventRecord(c->ev0, st), "event");
-            part_a();
-            ck(hipEventRecord(c->ev1, st), "event");
-            part_b();
-        }
-        ck(hipEventRecord(c->ev2, st), "event");
-        c->graph_prev_key = gkey;
-        wait_stream(c, "step sync");
-        phase(1);
-        const uint32_t *h = reinterpret_cast<const uint32_t *>(c->pin_out.as<uint8_t>() + pk.o_ctl);
-        layout = pk;
-        n_new = h[1];
-        nocc = h[2];
-        ncarry_out = h[3];
-        const uint64_t n_all = (uint64_t)ncarry + n_new;
+// Wait for the step; when a count exceeded its capacity, grow the capacity
+// and run the step again (synchronously) until everything fits.
+void step_wait(oasm_ctx *c, StepRun &r) {
+    PhaseClock phase(c);
+    for (;;) {
+        const double t0 = now_ms();
+        ck(hipEventSynchronize(c->ev2), "step sync");
+        c->stats.wait_ms += now_ms() - t0;
+        const uint32_t *h = reinterpret_cast<const uint32_t *>(c->pin_out[r.pin].as<uint8_t>() + r.layout.o_ctl);
+        r.n_new = h[1];
+        r.nocc = h[2];
+        r.ncarry_out = h[3];
+        const uint64_t n_all = (uint64_t)r.ncarry + r.n_new;
         bool again = false;
         if (h[0] > c->cap) {  // a scan item overflowed its record buffer
             c->cap = pow2_at_least(h[0]);
             again = true;
         }
-        if (n_all > cap_n) {
+        if (n_all > c->cap_n) {
             c->cap_n = pow2_at_least(2 * n_all);
             again = true;
         }
-        if (!again && nocc > cap_occ) {
-            c->cap_occ = pow2_at_least(2ull * nocc);
+        if (!again && r.nocc > c->cap_occ) {
+            c->cap_occ = pow2_at_least(2ull * r.nocc);
             again = true;
         }
-        if (!again && ncarry_out > cap_carry) {
-            c->cap_carry = pow2_at_least(2ull * ncarry_out);
+        if (!again && r.ncarry_out > c->cap_carry) {
+            c->cap_carry = pow2_at_least(2ull * r.ncarry_out);
             again = true;
         }
-        if (again) continue;
+        if (again) {
+            step_enqueue(c, r);
+            continue;
+        }
         if (h[4]) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
         c->stats.word_steps_done += (uint64_t)h[8] | ((uint64_t)h[9] << 32);
         float ms = 0;
         if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->stats.scan_ms += ms;
+        if (hipEventElapsedTime(&ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += ms;
         break;
     }
-    const uint32_t n = ncarry + n_new;
+    phase(1);
+}
 
-    // results are already in the mapped pinned buffer (written by the pack kernel)
-    float step_ms = 0;
-    if (hipEventElapsedTime(&step_ms, c->ev0, c->ev2) == hipSuccess) c->stats.step_ms += step_ms;
-    uint8_t *hp = c->pin_out.as<uint8_t>();
-    const size_t o_pat = layout.o_pat, o_sl = layout.o_sl, o_end = layout.o_end, o_flag = layout.o_flag;
-    const size_t o_dist = layout.o_dist, o_hk = layout.o_hk, o_occ = layout.o_occ, o_cr = layout.o_cr;
-    const bool need_raw = keep_any_raw;
-    const bool keep_h = keep_h_out;
-    phase(2);
-    // host bookkeeping: queue results
-    const uint32_t *hpat = reinterpret_cast<const uint32_t *>(hp + o_pat);
-    const uint32_t *hsl = reinterpret_cast<const uint32_t *>(hp + o_sl);
-    const uint64_t *hend = reinterpret_cast<const uint64_t *>(hp + o_end);
-    const uint8_t *hflag = hp + o_flag;
-    const uint8_t *hdist = hp + o_dist;
-    const uint8_t *hhk = hp + o_hk;
-    uint64_t new_raw = 0;
-    if (need_raw) {
-        std::vector<uint64_t> sid_of(pl.locals.size());
-        for (size_t l = 0; l < pl.locals.size(); ++l) sid_of[l] = c->streams[pl.locals[l]].id;
-        if (keep_raw) c->q_raw.reserve(c->q_raw.size() + n);
-        for (uint32_t i = 0; i < n; ++i) {
-            if (hflag[i]) continue;  // carried from an earlier step: reported there
-            ++new_raw;
-            const uint64_t sid = sid_of[hsl[i]];
-            if (keep_raw) c->q_raw.push_back(oasm_hit{sid, hend[i], hpat[i], hdist[i]});
-            if (keep_h) {
-                const uint32_t p = hpat[i];
-                const int m = c->m[p], K = c->k[p];
-                for (int l = std::max(1, m - K); l <= m + K; ++l) {
-                    const uint8_t kk = hhk[(size_t)i * hks + (l - (m - K))];
-                    if (kk == kNoHit) continue;
-                    c->q_h.push_back(oasm_occ{sid, hend[i] + 1 - (uint64_t)l, p, (uint32_t)l, kk, 0});
-                    c->stats.h_records++;
-                }
-            }
-        }
-    } else {
-        new_raw = n - ncarry;
-    }
-    const OccRec *ho = reinterpret_cast<const OccRec *>(hp + o_occ);
-    c->q_occ.reserve(c->q_occ.size() + nocc);
-    for (uint32_t i = 0; i < nocc; ++i) {
-        const uint64_t sid = c->streams[pl.locals[ho[i].stream_local]].id;
-        c->q_occ.push_back(oasm_occ{sid, ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
-    }
-    // the new carry stays on the device; the host keeps per-stream counts
-    for (uint32_t si : pl.locals) c->streams[si].ncarry = 0;
-    const CarryRec *hc = reinterpret_cast<const CarryRec *>(hp + o_cr);
-    for (uint32_t i = 0; i < ncarry_out; ++i) c->streams[hc[i].stream_slot].ncarry++;
-    c->ncarry = ncarry_out;
-    if (ncarry_out) c->carry_cur = cout;  // nothing carried: keep the buffers (and the step's shape) as they are
-    // stream bookkeeping (matched streams only): keep a look-back tail of
-    // each stream's symbols, the moves batched into few launches
-    for (uint32_t si : which) {
-        StreamState &s = c->streams[si];
-        c->stats.bytes_scanned += s.valid - s.scanned;
-        c->pending_bytes -= s.valid - s.scanned;
-        s.scanned = s.valid;
-        if (s.close_pending) {
-            // finished: a closed stream carries nothing (its filter segments
-            // all completed in this step), so its slot is free for reuse
+// After the step: the carried hit ends stay on the device (the host keeps
+// per-stream counts); every matched stream keeps a look-back tail of its
+// symbols (moved to the front of its buffer, together with any bytes fed
+// since the step was launched), and a stream that ended is released.
+void step_bookkeep(oasm_ctx *c, StepRun &r) {
+    PhaseClock phase(c);
+    hipStream_t st = c->st;
+    c->hold_release = false;
+    for (auto &h : c->held) release_staging(c, h.first, h.second);
+    c->held.clear();
+    for (uint32_t si : r.pl.locals) c->streams[si].ncarry = 0;
+    const CarryRec *hc = reinterpret_cast<const CarryRec *>(c->pin_out[r.pin].as<uint8_t>() + r.layout.o_cr);
+    for (uint32_t i = 0; i < r.ncarry_out; ++i) c->streams[hc[i].stream_slot].ncarry++;
+    c->ncarry = r.ncarry_out;
+    if (r.ncarry_out) c->carry_cur = r.cout;  // nothing carried: keep the buffers (and the step's shape) as they are
+    for (size_t k = 0; k < r.which.size(); ++k) {
+        StreamState &s = c->streams[r.which[k]];
+        const uint64_t done = r.scan_to[k] - s.scanned;
+        c->stats.bytes_scanned += done;
+        c->pending_bytes -= done;
+        s.scanned = r.scan_to[k];
+        if (r.closing[k]) {
+            // finished (no feed is accepted after a close): a closed stream
+            // carries nothing (its filter segments all completed in this
+            // step), so its slot is free for reuse
             s.close_pending = false;
             s.closed = true;
             c->staged_bytes -= s.cap;
@@ -711,25 +747,73 @@ void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
             c->free_slots.push_back(s.slot);
             continue;
         }
-        const size_t keep = std::min<size_t>(s.valid, c->lookback + 4);
-        if (keep < s.valid) {
-            const size_t drop = s.valid - keep;
-            if (keep <= UINT32_MAX) {
-                c->moves.push_back(StagingMove{s.sym + drop, s.sym, (uint32_t)keep, 0});
+        const size_t keep = std::min<size_t>(s.scanned, c->lookback + 4);
+        const size_t drop = s.scanned - keep;
+        if (drop > 0) {
+            const size_t len = s.valid - drop;  // the tail and any bytes fed since the launch
+            if (len <= UINT32_MAX) {
+                c->moves.push_back(StagingMove{s.sym + drop, s.sym, (uint32_t)len, 0});
             } else {
-                // never for a look-back tail (at most m_max + K_max + 3 symbols)
-                ck(hipMemcpyAsync(s.sym, s.sym + drop, keep, hipMemcpyDeviceToDevice, st), "tail move");
+                ck(hipMemcpyAsync(s.sym, s.sym + drop, len, hipMemcpyDeviceToDevice, st), "tail move");
             }
             s.base_abs += drop;
-            s.valid = s.scanned = keep;
+            s.valid -= drop;
+            s.scanned -= drop;
         }
     }
     flush_moves(c, st);
-    c->stats.raw_hits += new_raw;
-    c->stats.occurrences += nocc;
+    c->stats.raw_hits += r.n_new;
+    c->stats.occurrences += r.nocc;
     c->stats.syncs++;
-    phase(3);
     c->pin_feed_used = 0;
+    phase(3);
+}
+
+// The step's results (in its mapped pinned buffer) into the drain queues.
+void step_convert(oasm_ctx *c, StepRun &r) {
+    PhaseClock phase(c);
+    const uint32_t n = r.ncarry + r.n_new;
+    uint8_t *hp = c->pin_out[r.pin].as<uint8_t>();
+    const PackArgs &ly = r.layout;
+    const uint32_t *hpat = reinterpret_cast<const uint32_t *>(hp + ly.o_pat);
+    const uint32_t *hsl = reinterpret_cast<const uint32_t *>(hp + ly.o_sl);
+    const uint64_t *hend = reinterpret_cast<const uint64_t *>(hp + ly.o_end);
+    const uint8_t *hflag = hp + ly.o_flag;
+    const uint8_t *hdist = hp + ly.o_dist;
+    const uint8_t *hhk = hp + ly.o_hk;
+    const uint32_t hks = c->hks;
+    if (r.keep_raw || r.keep_h) {
+        if (r.keep_raw) grow_for(c->q_raw, r.n_new);
+        for (uint32_t i = 0; i < n; ++i) {
+            if (hflag[i]) continue;  // carried from an earlier step: reported there
+            const uint64_t sid = r.ids[hsl[i]];
+            if (r.keep_raw) c->q_raw.push_back(oasm_hit{sid, hend[i], hpat[i], hdist[i]});
+            if (r.keep_h) {
+                const uint32_t p = hpat[i];
+                const int m = c->m[p], K = c->k[p];
+                for (int l = std::max(1, m - K); l <= m + K; ++l) {
+                    const uint8_t kk = hhk[(size_t)i * hks + (l - (m - K))];
+                    if (kk == kNoHit) continue;
+                    c->q_h.push_back(oasm_occ{sid, hend[i] + 1 - (uint64_t)l, p, (uint32_t)l, kk, 0});
+                    c->stats.h_records++;
+                }
+            }
+        }
+    }
+    const OccRec *ho = reinterpret_cast<const OccRec *>(hp + ly.o_occ);
+    grow_for(c->q_occ, r.nocc);
+    for (uint32_t i = 0; i < r.nocc; ++i)
+        c->q_occ.push_back(oasm_occ{r.ids[ho[i].stream_local], ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
+    r.active = false;
+    phase(2);
+}
+
+void run_step(oasm_ctx *c, const std::vector<uint32_t> &which) {
+    StepRun r;
+    step_launch(c, which, r, 0);
+    step_wait(c, r);
+    step_bookkeep(c, r);
+    step_convert(c, r);
 }
 
 void sort_h_queue_tail(oasm_ctx *c, size_t from) {
@@ -863,7 +947,12 @@ void flush_moves(oasm_ctx *c, hipStream_t st) {
         ck(launch_staging_moves(b, n, st), "staging moves");
     }
     c->moves.clear();
-    for (auto &r : c->move_release) release_staging(c, r.first, r.second);
+    for (auto &r : c->move_release) {
+        if (c->hold_release)
+            c->held.push_back(r);
+        else
+            release_staging(c, r.first, r.second);
+    }
     c->move_release.clear();
 }
 
@@ -1599,101 +1688,190 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
     oasm_serve_report rep{};
     const uint8_t *pool = reinterpret_cast<const uint8_t *>(dev_pool);
     const double t0 = now_ms();
-    // on every return: the segments served so far (a prefix in arrival order)
+    double slept = 0;
+    size_t next = 0;
+    std::deque<size_t> ready;
+    std::vector<size_t> admitted;                // mapped into their streams, not yet in a launched step
+    std::vector<SegCopy> copies;
+    std::unordered_map<uint64_t, uint64_t> add;  // stream id -> bytes admitted at once
+    std::unordered_set<uint64_t> closing;        // streams a segment admitted at once closes
+    std::vector<uint32_t> created;               // slots of streams created by that admission
+    // Two steps: while one runs on the device, the host converts the results
+    // of the one before it and admits and maps the segments that arrive (their
+    // copies are queued behind the running step); when it has finished, the
+    // segments that arrived meanwhile are admitted too and the next step is
+    // launched over all of them.
+    StepRun runs[2];
+    std::vector<size_t> batch_of[2];
+    int fly = -1;   // the step in flight
+    int done = -1;  // a finished step whose results are not converted yet
+    std::vector<uint32_t> which;
+
+    // Admit the arrived segments in arrival order while the fed-but-unmatched
+    // bytes stay within the budget.  Every admitted segment is checked before
+    // any stream changes, so an error leaves the streams as they were.
+    auto admit_ready = [&]() -> oasm_status {
+        const double t = (now_ms() - t0) * 1e-3;
+        while (next < n && segs[next].arrival_s <= t) ready.push_back(next++);
+        if (ready.empty()) return OASM_OK;
+        add.clear();
+        closing.clear();
+        uint64_t admit = 0;
+        size_t take = 0;
+        const uint64_t budget = c->cfg.device_mem_budget;
+        for (; take < ready.size(); ++take) {
+            const oasm_segment &sg = segs[ready[take]];
+            if (budget && c->pending_bytes + admit + sg.len > budget && (admit > 0 || c->pending_bytes > 0)) {
+                rep.deferred++;
+                break;
+            }
+            bool closed = is_finished(c, sg.stream) || closing.count(sg.stream) != 0;
+            if (!closed) {
+                auto it = c->slot_of.find(sg.stream);
+                if (it != c->slot_of.end())
+                    closed = c->streams[it->second].closed || c->streams[it->second].close_pending;
+            }
+            if (closed) return fail(c, OASM_E_INVAL, "segment for a closed stream");
+            add[sg.stream] += sg.len;
+            admit += sg.len;
+            if (sg.flags & OASM_FEED_LAST) closing.insert(sg.stream);
+        }
+        if (take == 0) return OASM_OK;
+        // one staging reservation per stream; on failure the streams this
+        // admission created are removed again (the others only grew)
+        created.clear();
+        for (auto &kv : add) {
+            if (c->slot_of.find(kv.first) == c->slot_of.end()) created.push_back(get_stream(c, kv.first, true).slot);
+            oasm_status r = reserve_stream(c, c->streams[c->slot_of[kv.first]], kv.second, true);
+            if (r != OASM_OK) {
+                flush_moves(c, c->st);  // the streams grown so far keep their symbols
+                for (uint32_t slot : created) {
+                    StreamState &s = c->streams[slot];
+                    if (s.sym) {
+                        c->staged_bytes -= s.cap;
+                        release_staging(c, s.sym, s.cap);
+                    }
+                    c->slot_of.erase(s.id);
+                    s = StreamState{};
+                    c->free_slots.push_back(slot);
+                }
+                return r;
+            }
+        }
+        flush_moves(c, c->st);
+        copies.clear();
+        for (size_t q = 0; q < take; ++q) {
+            const size_t i = ready[q];
+            const oasm_segment &sg = segs[i];
+            StreamState &s = c->streams[c->slot_of[sg.stream]];
+            if (sg.len) copies.push_back(SegCopy{pool + sg.offset, s.sym + s.valid, sg.len, 0});
+            s.valid += sg.len;
+            c->pending_bytes += sg.len;
+            c->stats.cells += (uint64_t)sg.len * c->msum;
+            c->stats.word_steps += (uint64_t)sg.len * c->wsum;
+            if (sg.flags & OASM_FEED_LAST) s.close_pending = true;
+            admitted.push_back(i);
+        }
+        ready.erase(ready.begin(), ready.begin() + (ptrdiff_t)take);
+        map_copies(c, copies);  // queued behind the step in flight
+        return OASM_OK;
+    };
+    // segments of a finished step (or admitted empty ones) are served: their
+    // results are drainable
+    auto served = [&](const std::vector<size_t> &idx) {
+        const double fin = (now_ms() - t0) * 1e-3;
+        for (size_t i : idx) {
+            if (latency_s) latency_s[i] = fin - segs[i].arrival_s;
+            rep.segments++;
+            rep.bytes += segs[i].len;
+        }
+    };
+    auto finish_flying = [&]() {
+        if (fly < 0) return;
+        step_wait(c, runs[fly]);
+        step_bookkeep(c, runs[fly]);
+        done = fly;
+        fly = -1;
+    };
+    // the next step, over every stream with unmatched bytes (the admitted
+    // segments', and any fed before the run)
+    auto launch_pending = [&]() {
+        which.clear();
+        for (uint32_t i = 0; i < c->streams.size(); ++i) {
+            const StreamState &s = c->streams[i];
+            if (!s.closed && (s.valid > s.scanned || s.close_pending)) which.push_back(i);
+        }
+        if (which.empty()) {  // only empty segments: nothing to match
+            served(admitted);
+            admitted.clear();
+            return;
+        }
+        const int k = done >= 0 ? 1 - done : 0;
+        step_launch(c, which, runs[k], k);
+        batch_of[k].swap(admitted);
+        admitted.clear();
+        uint64_t bytes = 0;
+        for (size_t i : batch_of[k]) bytes += segs[i].len;
+        rep.steps++;
+        rep.max_batch_bytes = std::max<uint64_t>(rep.max_batch_bytes, bytes);
+        fly = k;
+    };
+    auto convert_done = [&]() {
+        if (done < 0) return;
+        const size_t h0 = c->q_h.size();
+        step_convert(c, runs[done]);
+        if (c->cfg.flags & OASM_CFG_KEEP_H) sort_h_queue_tail(c, h0);
+        served(batch_of[done]);
+        batch_of[done].clear();
+        done = -1;
+    };
+    // on every return: the step in flight and the admitted segments are
+    // matched, and the report counts the segments served (a prefix of the
+    // segments in arrival order)
     auto done_with = [&](oasm_status st) {
+        if (st != OASM_E_DEVICE && !c->poisoned) {
+            try {
+                while (fly >= 0 || done >= 0 || !admitted.empty()) {
+                    finish_flying();
+                    launch_pending();
+                    convert_done();
+                }
+            } catch (const HipFail &f) {
+                st = device_fail(c, f);
+            } catch (const std::bad_alloc &) {
+                st = step_alloc_fail(c);
+            }
+        }
         rep.wall_s = (now_ms() - t0) * 1e-3;
+        rep.busy_s = rep.wall_s - slept;
         if (report) *report = rep;
         return st;
     };
-    size_t next = 0;
-    std::deque<size_t> ready;
-    std::vector<size_t> batch;
-    std::vector<SegCopy> copies;
-    std::unordered_map<uint64_t, uint64_t> add;  // stream id -> bytes admitted this iteration
-    std::unordered_set<uint64_t> closing;        // streams a segment of this iteration closes
-    std::vector<uint32_t> created;               // slots of streams this iteration created
     try {
         ck(hipSetDevice(c->device), "hipSetDevice");
-        while (next < n || !ready.empty()) {
-            const double t = (now_ms() - t0) * 1e-3;
-            while (next < n && segs[next].arrival_s <= t) ready.push_back(next++);
-            if (ready.empty()) {
-                const double dt = segs[next].arrival_s - t;
-                if (dt > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(dt, 0.01)));
+        while (next < n || !ready.empty() || fly >= 0 || !admitted.empty()) {
+            oasm_status r = admit_ready();  // while a step runs: overlapped with it
+            if (r != OASM_OK) return done_with(r);
+            if (fly < 0 && admitted.empty() && ready.empty()) {
+                const double dt = segs[next].arrival_s - (now_ms() - t0) * 1e-3;
+                if (dt > 0) {
+                    const double ts = now_ms();
+                    std::this_thread::sleep_for(std::chrono::duration<double>(std::min(dt, 0.01)));
+                    slept += (now_ms() - ts) * 1e-3;
+                }
                 continue;
             }
-            // admission: arrival order, within the budget for unmatched bytes.
-            // Every admitted segment is checked before any stream changes, so
-            // an error leaves the streams as the previous iteration left them.
-            add.clear();
-            closing.clear();
-            uint64_t admit = 0;
-            size_t take = 0;
-            const uint64_t budget = c->cfg.device_mem_budget;
-            for (; take < ready.size(); ++take) {
-                const oasm_segment &sg = segs[ready[take]];
-                if (budget && c->pending_bytes + admit + sg.len > budget && (admit > 0 || c->pending_bytes > 0)) {
-                    rep.deferred++;
-                    break;
-                }
-                bool closed = is_finished(c, sg.stream) || closing.count(sg.stream) != 0;
-                if (!closed) {
-                    auto it = c->slot_of.find(sg.stream);
-                    if (it != c->slot_of.end())
-                        closed = c->streams[it->second].closed || c->streams[it->second].close_pending;
-                }
-                if (closed) return done_with(fail(c, OASM_E_INVAL, "segment for a closed stream"));
-                add[sg.stream] += sg.len;
-                admit += sg.len;
-                if (sg.flags & OASM_FEED_LAST) closing.insert(sg.stream);
-            }
-            // one staging reservation per stream; on failure the streams this
-            // iteration created are removed again (the others only grew)
-            created.clear();
-            for (auto &kv : add) {
-                if (c->slot_of.find(kv.first) == c->slot_of.end()) created.push_back(get_stream(c, kv.first, true).slot);
-                oasm_status r = reserve_stream(c, c->streams[c->slot_of[kv.first]], kv.second, true);
-                if (r != OASM_OK) {
-                    flush_moves(c, c->st);  // the streams grown so far keep their symbols
-                    for (uint32_t slot : created) {
-                        StreamState &s = c->streams[slot];
-                        if (s.sym) {
-                            c->staged_bytes -= s.cap;
-                            release_staging(c, s.sym, s.cap);
-                        }
-                        c->slot_of.erase(s.id);
-                        s = StreamState{};
-                        c->free_slots.push_back(slot);
-                    }
-                    return done_with(r);
-                }
-            }
-            flush_moves(c, c->st);
-            batch.assign(ready.begin(), ready.begin() + (ptrdiff_t)take);
-            ready.erase(ready.begin(), ready.begin() + (ptrdiff_t)take);
-            copies.clear();
-            for (size_t i : batch) {
-                const oasm_segment &sg = segs[i];
-                StreamState &s = c->streams[c->slot_of[sg.stream]];
-                if (sg.len) copies.push_back(SegCopy{pool + sg.offset, s.sym + s.valid, sg.len, 0});
-                s.valid += sg.len;
-                c->pending_bytes += sg.len;
-                c->stats.cells += (uint64_t)sg.len * c->msum;
-                c->stats.word_steps += (uint64_t)sg.len * c->wsum;
-                if (sg.flags & OASM_FEED_LAST) s.close_pending = true;
-            }
-            const double tb = now_ms();
-            map_copies(c, copies);
-            sync_all(c);
-            const double te = now_ms();
-            rep.busy_s += (te - tb) * 1e-3;
-            rep.steps++;
-            rep.max_batch_bytes = std::max<uint64_t>(rep.max_batch_bytes, admit);
-            rep.segments += batch.size();
-            rep.bytes += admit;
-            const double fin = (te - t0) * 1e-3;
-            if (latency_s)
-                for (size_t i : batch) latency_s[i] = fin - segs[i].arrival_s;
+            const bool had_step = fly >= 0;
+            finish_flying();
+            r = admit_ready();  // the arrivals during the wait join the next step
+            if (r != OASM_OK) return done_with(r);
+            launch_pending();
+            convert_done();  // while the new step runs
+            // nothing ran, nothing was admitted and nothing can be: arrived
+            // segments wait for a budget that no step will free (the budget
+            // counts bytes that no stream holds); an internal error, not a spin
+            if (!had_step && fly < 0 && admitted.empty() && !ready.empty() && c->pending_bytes > 0)
+                return done_with(fail(c, OASM_E_DEVICE, "internal: serving budget held by no stream"));
         }
     } catch (const HipFail &f) {
         return done_with(device_fail(c, f));
@@ -1891,7 +2069,8 @@ void oasm_destroy(oasm_ctx *c) {
     for (DevBuf *b : bufs) b->release();
     c->pin_plan.release();
     c->pin_ctl.release();
-    c->pin_out.release();
+    c->pin_out[0].release();
+    c->pin_out[1].release();
     c->pin_feed.release();
     c->pin_seg.release();
     c->d_seg.release();
