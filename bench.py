@@ -60,7 +60,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="batched", choices=["batched", "long", "tiny", "multiword"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "long", "tiny", "multiword", "homopolymer"])
+    ap.add_argument("--homopolymer-bytes", type=int, default=1 << 20,
+                    help="stream bytes of the homopolymer workload (a hit end at every position)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target length of the oracle sample")
     ap.add_argument("--chunk", type=int, default=0, help="chunk bytes (0 = library default)")
@@ -175,6 +177,16 @@ WORKLOADS = {
 def make_workload(name: str, args):
     from paper_1712_03560_amd import workloads as W
 
+    if name == "homopolymer":
+        # the filter's worst case: one stream of a single letter, so that the
+        # homopolymer patterns end a hit at every position and every filter
+        # segment spans the whole stream
+        n = int(args.homopolymer_bytes)
+        pats = [b"aaaaaaaa", b"aaaa", b"gcaacc", b"acgttgca", b"a" * 40]
+        w = W.Workload("homopolymer", [np.full(n, ord("a"), dtype=np.uint8)], pats,
+                       np.array([2, 1, 2, 2, 8], dtype=np.uint16), [])
+        return w, (f"homopolymer: one stream of {n} bytes 'a', 5 patterns (aaaaaaaa K=2, aaaa K=1, gcaacc K=2, "
+                   f"acgttgca K=2, a*40 K=8): a hit end at every position for three of them")
     if name == "long":
         return W.long_stream(), WORKLOADS["long"]
     if name == "tiny":

@@ -166,12 +166,16 @@ hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uin
                           uint32_t nclass, uint32_t hks, uint8_t *r_hk, uint8_t *r_dist, uint32_t *err,
                           hipStream_t st);
 
-// K3: the filter, one thread per segment of a (stream, pattern) run.
+// K3: the filter, one thread per segment of a (stream, pattern) run, and
+// one wavefront per segment longer than 32 hit ends (two launches).
 // `rules`: kRule* bits (0 = no filtering, only the open-segment flags).
+// `long_list` holds filter_long_list_words(n.cap) words; `*long_cnt` must be
+// 0 before the launch.  out_stride = K_max + 1 <= 64.
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
                          DevN n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams,
                          uint32_t rules, uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt,
-                         uint32_t *carry_flag, hipStream_t st);
+                         uint32_t *carry_flag, uint32_t *long_list, uint32_t *long_cnt, hipStream_t st);
+size_t filter_long_list_words(uint32_t cap);
 
 // Gather the filter output into a dense array.
 hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, DevN n,

@@ -480,15 +480,16 @@ hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uin
 }
 
 // ------------------------------------------------------------------ K3
-constexpr int kMaxLevels = 64;  // K <= 63
+constexpr int kMaxLevels = 64;       // K <= 63
+constexpr uint32_t kShortSeg = 32;   // longer segments are walked by a wavefront (k_filter_long)
+constexpr uint32_t kTile = 256;      // hit ends per LDS tile of k_filter_long
 
-// One thread per hit end; the thread that owns the first end of a segment
-// runs Alg. 1 over the segment.  A segment is a maximal run of one
-// (stream, pattern)'s hit ends in which consecutive ends are less than m + K
-// apart.  Alg. 1's state is empty between segments: any pending occurrence
-// ends at or before the last end of its segment, completes there, and every
-// hit of the next segment starts after it.  So segments are filtered in
-// parallel, each from the initial state.
+// A segment is a maximal run of one (stream, pattern)'s hit ends in which
+// consecutive ends are less than m + K apart.  Alg. 1's state is empty
+// between segments: any pending occurrence ends at or before the last end of
+// its segment, completes there, and every hit of the next segment starts
+// after it.  So segments are filtered in parallel, each from the initial
+// state.
 //
 // Inside a segment the hit set is walked in (start, length) order, the
 // order of Alg. 1's loops: for a start s the candidate ends are the hit ends
@@ -496,7 +497,8 @@ constexpr int kMaxLevels = 64;  // K <= 63
 // length); starts with no candidate are skipped.  The completion test of
 // Alg. 1 is applied lazily: the stored best completes at its own end, which
 // is acted on before the first later start is examined (nothing changes at
-// starts without hits).
+// starts without hits).  Hit ends of one pair are distinct and increasing,
+// so a start has at most 2K + 1 candidates.
 //
 // A segment whose last end is within m + K of the stream's scanned frontier
 // may still grow: it is not filtered now but carried to the next step.
@@ -505,15 +507,151 @@ constexpr int kMaxLevels = 64;  // K <= 63
 // readings of R2 and Eq. 3 (bit values as the public OASM_RULES_* flags).
 // None of them changes when a stored best completes (at its own end), so the
 // segment argument holds for every combination.
+//
+// Alg. 1's mem rows (start, length per priority level) live in LDS, at
+// `lv_s[q * lstride]` / `lv_l[q * lstride]` for level q.
+
+// Hit ends and hit-set bytes read straight from the step's arrays.
+struct RecsGlobal {
+    const uint64_t *end;
+    const uint8_t *hk;
+    uint32_t hks;
+    __device__ __forceinline__ void need(uint32_t, uint32_t) {}
+    __device__ __forceinline__ uint64_t e(uint32_t j) const { return end[j]; }
+    __device__ __forceinline__ uint32_t k(uint32_t j, int q) const { return hk[(size_t)j * hks + q]; }
+};
+
+// The same through a tile of kTile records in LDS, refilled by the whole
+// wavefront (every lane runs the walk with the same values) whenever a record
+// outside the tile is needed; the tile then starts at the walk's lowest live
+// record.
+struct RecsTile {
+    const uint64_t *end;
+    const uint8_t *hk;
+    uint32_t hks, j1;
+    uint64_t *tend;  // [kTile]
+    uint8_t *thk;    // [kTile * hks]
+    uint32_t base, lim;
+    __device__ __forceinline__ void need(uint32_t lo, uint32_t j) {
+        if (j < lim && lo >= base) return;
+        __syncthreads();  // the tile's last readers are done
+        base = lo;
+        lim = min(j1, lo + kTile);
+        const uint32_t cnt = lim - base;
+        for (uint32_t x = threadIdx.x; x < cnt; x += blockDim.x) tend[x] = end[base + x];
+        for (uint32_t x = threadIdx.x; x < cnt * hks; x += blockDim.x) thk[x] = hk[(size_t)base * hks + x];
+        __syncthreads();
+    }
+    __device__ __forceinline__ uint64_t e(uint32_t j) const { return tend[j - base]; }
+    __device__ __forceinline__ uint32_t k(uint32_t j, int q) const { return thk[(j - base) * hks + q]; }
+};
+
+// Alg. 1 over the hit ends i .. j1-1 of one segment of pattern p in stream
+// sl, emitting into out; returns the number of occurrences.
+template <class Recs>
+__device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, uint32_t sl, int m, int K,
+                                uint32_t rules, uint64_t *lv_s, uint32_t *lv_l, uint32_t lstride, OccRec *out) {
+    const bool acc_last = (rules & kRuleAccLast) != 0, eq3_ge = (rules & kRuleEq3Ge) != 0;
+    const bool start_order = (rules & kRuleStartOrder) != 0, disjoint = (rules & kRuleDisjoint) != 0;
+    const int lmax = m + K;
+    const int lmin = m - K < 1 ? 1 : m - K;
+    const int qoff = m - K;
+    for (int q = 0; q <= K; ++q) lv_l[q * lstride] = 0;
+    int idx = K;
+    bool ins = false;
+    uint32_t cnt = 0;
+
+    auto emit = [&](uint64_t pos) {
+        int64_t acc = 0;
+        uint64_t accepted = 0;  // levels accepted so far in this emission
+        for (int j = idx; j <= K; ++j) {
+            const uint32_t lj = lv_l[j * lstride];
+            if (lj == 0) continue;
+            const uint64_t sj = lv_s[j * lstride];
+            const int64_t r = (int64_t)(pos - sj + 1);  // validation counter r(j)
+            const int64_t l = (int64_t)lj;
+            bool ok = j == idx || (eq3_ge ? r - acc >= l : r - acc > l);  // Eq. 3
+            if (ok && disjoint && j != idx) {
+                const uint64_t je = sj + lj - 1;
+                for (uint64_t mk = accepted; mk; mk &= mk - 1) {
+                    const int q = __builtin_ctzll(mk);
+                    const uint64_t qs = lv_s[q * lstride], qe = qs + lv_l[q * lstride] - 1;
+                    if (!(je < qs || qe < sj)) ok = false;
+                }
+            }
+            if (ok) {
+                OccRec o;
+                o.start_abs = sj;
+                o.pattern = p;
+                o.stream_local = sl;
+                o.len = lj;
+                o.k = (uint32_t)j;
+                out[cnt++] = o;
+                acc = acc_last ? l : acc + l;
+                accepted |= 1ull << j;
+            }
+        }
+        for (int j = idx; j <= K; ++j) lv_l[j * lstride] = 0;
+        idx = K;
+        ins = false;
+    };
+
+    uint32_t lo = i;
+    R.need(i, i);
+    const uint64_t e0 = R.e(i);
+    uint64_t s = e0 + 1 >= (uint64_t)lmax ? e0 + 1 - lmax : 0;
+    while (true) {
+        for (; lo < j1; ++lo) {
+            R.need(lo, lo);
+            if (R.e(lo) + 1 >= s + lmin) break;
+        }
+        if (lo >= j1) break;
+        if (R.e(lo) + 1 > s + lmax) {  // no hit end reachable from s: jump
+            s = R.e(lo) + 1 - lmax;
+            continue;
+        }
+        if (ins && lv_s[idx * lstride] + lv_l[idx * lstride] - 1 < s)
+            emit(lv_s[idx * lstride] + lv_l[idx * lstride] - 1);
+        R.need(lo, min(j1, lo + 2 * K + 2) - 1);  // every candidate of s and the end test
+        for (uint32_t j = lo; j < j1 && R.e(j) + 1 <= s + lmax; ++j) {
+            const int l = (int)(R.e(j) + 1 - s);
+            const uint32_t k = R.k(j, l - qoff);
+            if (k == kNoHit) continue;
+            if ((int)k < idx) {  // R1
+                idx = (int)k;
+                ins = true;
+                lv_s[k * lstride] = s;
+                lv_l[k * lstride] = (uint32_t)l;
+            } else if ((int)k == idx) {  // R2 / R3: earlier end, then shorter (or: keep the first)
+                const uint32_t lk = lv_l[k * lstride];
+                const uint64_t be = lv_s[k * lstride] + lk;
+                if (lk == 0 || (!start_order && (s + l < be || (s + l == be && (uint32_t)l < lk)))) {
+                    ins = true;
+                    lv_s[k * lstride] = s;
+                    lv_l[k * lstride] = (uint32_t)l;
+                }
+            }
+        }
+        ++s;
+    }
+    if (ins) emit(lv_s[idx * lstride] + lv_l[idx * lstride] - 1);
+    return cnt;
+}
+
+// One thread per hit end; the thread that owns the first end of a segment
+// filters it when the segment has at most kShortSeg ends, and otherwise
+// hands it to k_filter_long (appended to `long_list`).  Dynamic LDS: the mem
+// rows of the 64 threads, [level][thread].
 __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
                                                const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
                                                DevN dn, uint32_t hks, const PatDesc *__restrict__ pats,
                                                const StreamDesc *__restrict__ streams, uint32_t rules,
                                                uint32_t out_stride, OccRec *__restrict__ seg_out,
-                                               uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag) {
+                                               uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag,
+                                               uint32_t *__restrict__ long_list, uint32_t *__restrict__ long_cnt,
+                                               uint32_t nlevels) {
+    extern __shared__ uint64_t lds_lv[];
     const bool do_filter = (rules & kRulePaper) != 0;
-    const bool acc_last = (rules & kRuleAccLast) != 0, eq3_ge = (rules & kRuleEq3Ge) != 0;
-    const bool start_order = (rules & kRuleStartOrder) != 0, disjoint = (rules & kRuleDisjoint) != 0;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = dev_n(dn);
     if (i >= n) return;
@@ -528,7 +666,12 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
         return;
     }
     uint32_t j1 = i + 1;
-    while (j1 < n && r_pat[j1] == p && r_sl[j1] == sl && r_end[j1] - r_end[j1 - 1] < gap) ++j1;
+    while (j1 < n && j1 - i <= kShortSeg && r_pat[j1] == p && r_sl[j1] == sl && r_end[j1] - r_end[j1 - 1] < gap) ++j1;
+    if (j1 - i > kShortSeg) {  // a long segment: one wavefront walks it
+        seg_cnt[i] = 0;
+        long_list[atomicAdd(long_cnt, 1u)] = i;
+        return;
+    }
     const StreamDesc sd = streams[sl];
     const bool open = do_filter && !sd.closed && r_end[j1 - 1] + gap > sd.frontier;
     for (uint32_t j = i; j < j1; ++j) carry_flag[j] = open ? 1u : 0u;
@@ -536,103 +679,112 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
         seg_cnt[i] = 0;
         return;
     }
+    uint64_t *lv_s = lds_lv + threadIdx.x;
+    uint32_t *lv_l = reinterpret_cast<uint32_t *>(lds_lv + (size_t)nlevels * 64) + threadIdx.x;
+    RecsGlobal R{r_end, r_hk, hks};
+    seg_cnt[i] = filter_walk(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 64, seg_out + (size_t)i * out_stride);
+}
 
-    const int lmax = m + K;
-    const int lmin = m - K < 1 ? 1 : m - K;
-    const int qoff = m - K;
-    uint64_t lvl_s[kMaxLevels];
-    uint32_t lvl_l[kMaxLevels];
-    for (int q = 0; q <= K; ++q) lvl_l[q] = 0;
-    int idx = K;
-    bool ins = false;
-    uint32_t cnt = 0;
-    OccRec *out = seg_out + (size_t)i * out_stride;
-
-    auto emit = [&](uint64_t pos) {
-        int64_t acc = 0;
-        uint64_t accepted = 0;  // levels accepted so far in this emission
-        for (int j = idx; j <= K; ++j) {
-            if (lvl_l[j] == 0) continue;
-            const int64_t r = (int64_t)(pos - lvl_s[j] + 1);  // validation counter r(j)
-            const int64_t l = (int64_t)lvl_l[j];
-            bool ok = j == idx || (eq3_ge ? r - acc >= l : r - acc > l);  // Eq. 3
-            if (ok && disjoint && j != idx) {
-                const uint64_t js = lvl_s[j], je = lvl_s[j] + lvl_l[j] - 1;
-                for (uint64_t mk = accepted; mk; mk &= mk - 1) {
-                    const int q = __builtin_ctzll(mk);
-                    const uint64_t qs = lvl_s[q], qe = lvl_s[q] + lvl_l[q] - 1;
-                    if (!(je < qs || qe < js)) ok = false;
-                }
-            }
-            if (ok) {
-                OccRec o;
-                o.start_abs = lvl_s[j];
-                o.pattern = p;
-                o.stream_local = sl;
-                o.len = lvl_l[j];
-                o.k = (uint32_t)j;
-                out[cnt++] = o;
-                acc = acc_last ? l : acc + l;
-                accepted |= 1ull << j;
+// One wavefront (block of 64) per long segment (grid-stride over the list):
+// the lanes find the segment's end together, write its carry flags, and all
+// run the walk with the same values, reading the hit ends and hit-set bytes
+// from an LDS tile.  Dynamic LDS: kTile ends, kTile * hks bytes, the mem rows.
+__global__ void __launch_bounds__(64) k_filter_long(const uint32_t *__restrict__ r_pat,
+                                                    const uint32_t *__restrict__ r_sl,
+                                                    const uint64_t *__restrict__ r_end,
+                                                    const uint8_t *__restrict__ r_hk, DevN dn, uint32_t hks,
+                                                    const PatDesc *__restrict__ pats,
+                                                    const StreamDesc *__restrict__ streams, uint32_t rules,
+                                                    uint32_t out_stride, OccRec *__restrict__ seg_out,
+                                                    uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag,
+                                                    const uint32_t *__restrict__ long_list,
+                                                    const uint32_t *__restrict__ long_cnt, uint32_t nlevels) {
+    extern __shared__ uint64_t lds_tile[];
+    const bool do_filter = (rules & kRulePaper) != 0;
+    const uint32_t n = dev_n(dn);
+    const uint32_t nlong = *long_cnt;
+    const uint32_t lane = threadIdx.x;
+    uint64_t *tend = lds_tile;
+    uint64_t *lv_s = lds_tile + kTile;
+    uint32_t *lv_l = reinterpret_cast<uint32_t *>(lv_s + nlevels);
+    uint8_t *thk = reinterpret_cast<uint8_t *>(lv_l + nlevels);
+    for (uint32_t x = blockIdx.x; x < nlong; x += gridDim.x) {
+        const uint32_t i = long_list[x];
+        const uint32_t p = r_pat[i], sl = r_sl[i];
+        const PatDesc d = pats[p];
+        const int m = d.m, K = d.k;
+        const uint64_t gap = (uint64_t)(m + K);
+        // the segment's end: the first record past i that breaks the run
+        uint32_t j1 = n;
+        for (uint32_t b = i + 1; b < n; b += 64) {
+            const uint32_t j = b + lane;
+            const bool brk = j >= n || r_pat[j] != p || r_sl[j] != sl || r_end[j] - r_end[j - 1] >= gap;
+            const uint64_t bal = __ballot(brk);
+            if (bal) {
+                j1 = b + (uint32_t)__builtin_ctzll(bal);
+                break;
             }
         }
-        for (int j = idx; j <= K; ++j) lvl_l[j] = 0;
-        idx = K;
-        ins = false;
-    };
-
-    uint32_t lo = i;
-    uint64_t s = e0 + 1 >= (uint64_t)lmax ? e0 + 1 - lmax : 0;
-    while (true) {
-        while (lo < j1 && r_end[lo] + 1 < s + lmin) ++lo;
-        if (lo >= j1) break;
-        if (r_end[lo] + 1 > s + lmax) {  // no hit end reachable from s: jump
-            s = r_end[lo] + 1 - lmax;
+        const StreamDesc sd = streams[sl];
+        const bool open = do_filter && !sd.closed && r_end[j1 - 1] + gap > sd.frontier;
+        for (uint32_t j = i + lane; j < j1; j += 64) carry_flag[j] = open ? 1u : 0u;
+        if (open || !do_filter) {
+            if (lane == 0) seg_cnt[i] = 0;
             continue;
         }
-        if (ins && lvl_s[idx] + lvl_l[idx] - 1 < s) emit(lvl_s[idx] + lvl_l[idx] - 1);
-        for (uint32_t j = lo; j < j1 && r_end[j] + 1 <= s + lmax; ++j) {
-            const int l = (int)(r_end[j] + 1 - s);
-            const int k = r_hk[(size_t)j * hks + (l - qoff)];
-            if (k == kNoHit) continue;
-            if (k < idx) {  // R1
-                idx = k;
-                ins = true;
-                lvl_s[k] = s;
-                lvl_l[k] = (uint32_t)l;
-            } else if (k == idx) {  // R2 / R3: earlier end, then shorter (or: keep the first)
-                const uint64_t be = lvl_s[k] + lvl_l[k];
-                if (lvl_l[k] == 0 ||
-                    (!start_order && (s + l < be || (s + l == be && (uint32_t)l < lvl_l[k])))) {
-                    ins = true;
-                    lvl_s[k] = s;
-                    lvl_l[k] = (uint32_t)l;
-                }
-            }
-        }
-        ++s;
+        RecsTile R{r_end, r_hk, hks, j1, tend, thk, 0u, 0u};
+        const uint32_t cnt = filter_walk(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 1, seg_out + (size_t)i * out_stride);
+        if (lane == 0) seg_cnt[i] = cnt;
+        __syncthreads();  // the next segment's tile and mem rows
     }
-    if (ins) emit(lvl_s[idx] + lvl_l[idx] - 1);
-    seg_cnt[i] = cnt;
 }
 
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
                          DevN n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams, uint32_t rules,
                          uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt, uint32_t *carry_flag,
-                         hipStream_t st) {
+                         uint32_t *long_list, uint32_t *long_cnt, hipStream_t st) {
     if (n.cap == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_filter, dim3((n.cap + 63) / 64), dim3(64), 0, st, r_pat, r_sl, r_end, r_hk, n, hks, pats, streams,
-                       rules, out_stride, seg_out, seg_cnt, carry_flag);
+    const uint32_t nlevels = out_stride;  // K_max + 1 levels
+    if (nlevels > (uint32_t)kMaxLevels) return hipErrorInvalidValue;
+    const size_t sh = (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t));
+    hipLaunchKernelGGL(k_filter, dim3((n.cap + 63) / 64), dim3(64), sh, st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
+                       streams, rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // at most one long segment per kShortSeg + 1 hit ends; a fixed grid that
+    // reads the count on the device (nothing to do in most steps)
+    const uint32_t maxlong = n.cap / (kShortSeg + 1) + 1;
+    const uint32_t grid = maxlong < 512 ? maxlong : 512;
+    const size_t shl = kTile * sizeof(uint64_t) + (size_t)nlevels * (sizeof(uint64_t) + sizeof(uint32_t)) +
+                       (size_t)kTile * hks;
+    hipLaunchKernelGGL(k_filter_long, dim3(grid), dim3(64), shl, st, r_pat, r_sl, r_end, r_hk, n, hks, pats, streams,
+                       rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
     return hipGetLastError();
 }
 
+size_t filter_long_list_words(uint32_t cap) { return cap / (kShortSeg + 1) + 1; }
+
+// Occurrences of every segment into one dense array.  A thread copies its
+// own segment's records; a segment with more than 64 of them is copied by
+// the whole wavefront.
 __global__ void k_compact_occ(const OccRec *__restrict__ seg_out, const uint32_t *__restrict__ seg_cnt,
                               const uint32_t *__restrict__ seg_off, DevN dn, uint32_t stride,
                               OccRec *__restrict__ out, uint32_t out_cap) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= dev_n(dn)) return;
-    const uint32_t c = seg_cnt[i];
-    for (uint32_t q = 0; q < c && seg_off[i] + q < out_cap; ++q) out[seg_off[i] + q] = seg_out[(size_t)i * stride + q];
+    const uint32_t n = dev_n(dn);
+    const uint32_t c = i < n ? seg_cnt[i] : 0u;
+    const uint32_t lane = lane_id();
+    const bool big = c > 64;
+    if (!big) {
+        for (uint32_t q = 0; q < c && seg_off[i] + q < out_cap; ++q)
+            out[seg_off[i] + q] = seg_out[(size_t)i * stride + q];
+    }
+    for (uint64_t bal = __ballot(big); bal; bal &= bal - 1) {
+        const uint32_t src = (uint32_t)__builtin_ctzll(bal);
+        const uint32_t si = __shfl(i, src, 64), sc = __shfl(c, src, 64);
+        const uint32_t so = seg_off[si];
+        for (uint32_t q = lane; q < sc && so + q < out_cap; q += 64) out[so + q] = seg_out[(size_t)si * stride + q];
+    }
 }
 
 hipError_t launch_compact_occ(const OccRec *seg_out, const uint32_t *seg_cnt, const uint32_t *seg_off, DevN n,

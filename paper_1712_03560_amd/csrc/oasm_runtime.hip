@@ -160,7 +160,7 @@ struct oasm_ctx {
 
     // step buffers
     DevBuf plan, offsets, item_rec, item_cnt, ctl, scan_tmp, sort_key, sort_val, sort_end, sort_tmp;
-    DevBuf r_pat, r_sl, r_end, r_flag, r_dist, r_hk, seg_cnt, seg_off, carry_flag, carry_off;
+    DevBuf r_pat, r_sl, r_end, r_flag, r_dist, r_hk, seg_cnt, seg_off, carry_flag, carry_off, long_list;
     DevBuf seg_out, occ_out, raw_in;
     // Hit ends of filter segments that may still grow, for every stream,
     // resident on the device between steps (double-buffered: read one,
@@ -438,6 +438,7 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
     c->seg_off.ensure(n1 * 4, st);
     c->carry_flag.ensure(n1 * 4, st);
     c->carry_off.ensure(n1 * 4, st);
+    c->long_list.ensure(filter_long_list_words((uint32_t)n1) * 4, st);
     c->seg_out.ensure(n1 * out_stride * sizeof(OccRec), st);
     c->occ_out.ensure((uint64_t)cap_occ * sizeof(OccRec), st);
     c->carry_buf[cout].ensure((uint64_t)cap_carry * sizeof(CarryRec), st);
@@ -527,7 +528,8 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
            "recover");
         ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
                          c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, rules, out_stride,
-                         c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(), st),
+                         c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(),
+                         c->long_list.as<uint32_t>(), ctl + 6, st),
            "filter");
         ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
                                  c->scan_tmp.as<uint32_t>(), st),
@@ -648,7 +650,8 @@ void step_launch(oasm_ctx *c, const std::vector<uint32_t> &which, StepRun &r, in
     r.cout = 1 - c->carry_cur;
     c->carry_buf[r.cin].ensure(std::max<uint32_t>(r.ncarry, 1) * sizeof(CarryRec), st);
     c->carry_hk_buf[r.cin].ensure(std::max<uint32_t>(r.ncarry, 1) * (uint64_t)c->hks, st);
-    // control words: [0] max item count, [1] new hit ends, [2] occurrences, [3] carried, [4] recovery errors
+    // control words: [0] max item count, [1] new hit ends, [2] occurrences, [3] carried, [4] recovery
+    // errors, [6] long filter segments, [8..9] word-steps (all cleared at the step's start)
     c->ctl.ensure(64, st);
     c->pin_ctl.ensure(64, st);
     const uint64_t nitems = (uint64_t)r.nchunks * c->ntiles;
@@ -2064,7 +2067,7 @@ void oasm_destroy(oasm_ctx *c) {
                       &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->offsets, &c->item_rec,
                       &c->item_cnt, &c->ctl, &c->scan_tmp, &c->sort_key, &c->sort_val, &c->sort_end, &c->sort_tmp,
                       &c->r_pat, &c->r_sl, &c->r_end, &c->r_flag, &c->r_dist, &c->r_hk, &c->seg_cnt, &c->seg_off,
-                      &c->carry_flag, &c->carry_off, &c->seg_out, &c->occ_out, &c->carry_buf[0], &c->carry_buf[1],
+                      &c->carry_flag, &c->carry_off, &c->long_list, &c->seg_out, &c->occ_out, &c->carry_buf[0], &c->carry_buf[1],
                       &c->carry_hk_buf[0], &c->carry_hk_buf[1], &c->raw_in, &c->d_lc_ids, &c->d_lc_unit};
     for (DevBuf *b : bufs) b->release();
     c->pin_plan.release();

@@ -112,6 +112,31 @@ def test_dense_shadow_hits():
     compare(res, {0: t}, pats, ks, check_h=True, label="dense")
 
 
+@pytest.mark.parametrize("n", [33 * 8 + 5, 70_000])
+def test_long_filter_segments(n):
+    """Segments of more than 32 hit ends are filtered by one wavefront each,
+    from LDS tiles of 256 records: homopolymer text, where three patterns end
+    a hit at every position (one segment per pattern over the whole stream),
+    mixed with a text whose runs of the letter make segments of every length
+    around the tile and hand-over sizes; closed and carried (split feeds)."""
+    pats = [b"aaaaaaaa", b"aaaa", b"gcaacc", b"acgttgca", b"a" * 40, b"aaagaaa"]
+    ks = [2, 1, 2, 2, 8, 3]
+    rng = np.random.default_rng(n)
+    t1 = np.full(n, ord("a"), dtype=np.uint8)
+    t2 = np.full(n, ord("a"), dtype=np.uint8)
+    pos = 0
+    while pos < n:  # runs of 'a' of 20..700 symbols between single other letters
+        pos += int(rng.integers(20, 700))
+        if pos < n:
+            t2[pos] = rng.choice(np.frombuffer(b"cgt", np.uint8))
+    streams = {0: t1, 1: t2}
+    say(f"long filter segments, n={n}")
+    res = run(pats, ks, streams)
+    compare(res, streams, pats, ks, check_h=True, label=f"long-seg{n}")
+    res = run(pats, ks, streams, pieces=n)
+    compare(res, streams, pats, ks, check_h=True, label=f"long-seg{n}-split")
+
+
 def test_k_zero_and_edge_streams():
     pats = [b"ACGT", b"A", b"TTTTT", b"GATTACA"]
     ks = [0, 0, 1, 0]
