@@ -90,8 +90,7 @@ def parse():
     ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--levcalc-bytes", type=int, default=1 << 23, help="text bytes of the LEV CALC leg")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 256 MiB device copy three times and a one-tile scan of the "
-                         "workload's text (PMC traffic calibration)")
+                    help="first run a plain 256 MiB device copy three times (PMC traffic calibration)")
     return ap.parse_args()
 
 
@@ -129,34 +128,25 @@ def copy_calibration():
     del src, dst
 
 
-def single_tile_calibration(oasm, torch, w):
-    """One scan launch that reads its text exactly once: 64 one-word patterns
-    of the workload (one tile) over all of its streams, one step.  Its
-    FETCH_SIZE per dispatch, against the text's byte count, shows how the
-    counter scores the scan's own (scalar) loads, beside the copy kernel's
-    factor."""
-    idx = [i for i, p in enumerate(w.patterns) if len(p) <= 32][:64]
-    dev = [torch.from_numpy(t).cuda() for t in w.streams]
-    with oasm.Matcher([w.patterns[i] for i in idx], [w.ks[i] for i in idx], autotune=False, graphs=False) as mt:
-        mt.feed_many([(i, t, True) for i, t in enumerate(dev)])
-        mt.sync()
-        mt.results()
-    torch.cuda.synchronize()
-    del dev
-
-
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("oasm_scan.hip", "oasm_device.h", "oasm_internal.h"):
+    for f in ("oasm_scan.hip", "oasm_device.h"):
         with open(os.path.join(ROOT, "paper_1712_03560_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
+HBM_PEAK_BYTES = 8.0e12  # MI355X HBM3E, 8 TB/s
+
+
 def traffic_from_profiles(workload: str):
-    """HBM bytes per scan launch from committed rocprofv3 PMC summaries, if
-    they were taken with the current kernel source; and the launch's fetch
-    over a one-tile scan's of the same text."""
+    """HBM bytes of the scan launches of one step, from the committed
+    rocprofv3 PMC summary of this workload, if it was taken with the current
+    kernel source: the raw FETCH_SIZE and WRITE_SIZE of the step's scan
+    launches, each divided by the factor the counter reads for a kernel of
+    known size and the same access kind (scalar-load reads for the fetch, as
+    the scan reads its text with scalar loads; plain stores for the write).
+    Returns (bytes per step, summary dict) or (None, None)."""
     path = os.path.join(ROOT, "profiles", f"scan_{workload}_traffic.json")
     if not os.path.exists(path):
         return None, None
@@ -164,8 +154,7 @@ def traffic_from_profiles(workload: str):
         d = json.load(fh)
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None, None
-    one = d.get("one_tile_scan") or {}
-    return d.get("hbm_bytes_per_launch"), one.get("full_launch_fetch_over_one_tile_fetch")
+    return d.get("hbm_bytes_per_step"), d
 
 
 WORKLOADS = {
@@ -198,6 +187,18 @@ def make_workload(name: str, args):
     w = W.batched(n_streams=args.batched_streams)
     return w, (f"batched: {len(w.streams)} streams log-uniform in [1 KiB, 1 MiB] ({w.total_bytes} bytes), "
                f"Zipf(1.1) 20 letters, 1024 patterns m~U[8,64], K=floor(m/10), one batched step")
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def cpu_baseline(w, target_s: float):
@@ -265,6 +266,7 @@ def cpu_baseline(w, target_s: float):
             oracle.run_pair(w.patterns[i], t, int(w.ks[i]))
     dt1 = time.perf_counter() - t0
     return {"value": round(msum * nbytes / dt / 1e9, 3), "unit": "GCUPS", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{what} (hit ends, hit set and filter), {dt:.1f} s",
             "one_thread": {"value": round(msum * n1 / dt1 / 1e9, 3), "unit": "GCUPS",
                            "sample": f"{len(one)} of those streams ({n1} bytes) x all patterns, {dt1:.1f} s"}}
@@ -352,20 +354,28 @@ def summarize(w, r, workload):
     ops = done * OPS_PER_WORD_STEP
     achieved = ops / (scan_ms * 1e-3) / 1e12 if scan_ms > 0 else None
     peak = VALU_PEAK_OPS / 1e12
-    traffic, vs_one_tile = traffic_from_profiles(workload)
+    traffic, tsum = traffic_from_profiles(workload)
+    hbm_frac = None
+    if traffic and scan_ms > 0:
+        hbm_frac = round(traffic / (scan_ms * 1e-3) / HBM_PEAK_BYTES, 5)
     return {
         "gcups": cells / (elapsed / steps) / 1e9,
         "ms_per_step": elapsed / steps * 1e3,
         "cells": cells,
         "roofline": {"bound": "alu", "achieved": round(achieved, 2) if achieved else None, "peak": round(peak, 2),
                      "unit": "TOP/s", "frac": round(achieved / peak, 4) if achieved else None,
-                     "traffic": traffic, "kernel": "k_scan", "scan_ms_per_step": round(scan_ms, 3),
+                     "traffic": traffic, "traffic_unit": "HBM bytes per step's scan launches",
+                     "hbm_frac": hbm_frac, "hbm_peak_GBps": HBM_PEAK_BYTES / 1e9,
+                     "traffic_calibration": ({k: tsum[k] for k in ("fetch_factor_scalar_reads",
+                                                                     "fetch_factor_vector_reads",
+                                                                     "write_factor", "profile")}
+                                             if tsum else None),
+                     "kernel": "k_scan", "scan_ms_per_step": round(scan_ms, 3),
                      "scan_launches_per_step": (s1["scan_launches"] - s0["scan_launches"]) / steps,
                      "word_steps": int(done), "word_steps_full_columns": word_steps,
                      "ops_per_word_step": OPS_PER_WORD_STEP, "word_cutoff": cut,
-                     # FETCH_SIZE of a launch over that of a one-tile scan of
-                     # the same text (which reads it exactly once)
-                     "fetch_vs_one_tile_scan": round(vs_one_tile, 3) if vs_one_tile else None},
+                     # algorithmic bytes: the text of the step, read once
+                     "algorithmic_bytes_per_step": w.total_bytes},
         "scan_gcups": round(cells / (scan_ms * 1e-3) / 1e9, 1) if scan_ms > 0 else None,
         "step_breakdown_ms": {
             "scan_kernel": round(scan_ms, 3),
@@ -572,8 +582,6 @@ def main():
     if args.calibrate_copy:
         copy_calibration()
     w, desc = make_workload(args.workload, args)
-    if args.calibrate_copy:
-        single_tile_calibration(oasm, torch, w)
     r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk, autotune=not args.no_autotune,
                   graphs=not args.no_graphs)
     m = summarize(w, r, args.workload)

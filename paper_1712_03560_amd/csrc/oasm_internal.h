@@ -113,6 +113,7 @@ struct SegCopy {
     uint32_t len;
     uint32_t pad;
 };
+constexpr uint32_t kMapPiece = 4096;  // symbols of one segment piece (one workgroup)
 hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *class_of, hipStream_t st);
 
 // K1: the bit-parallel scan for one word-count class (W words, P patterns

@@ -131,29 +131,40 @@ hipError_t launch_map_symbols(const uint8_t *src, uint8_t *dst, uint64_t n, cons
     return hipGetLastError();
 }
 
-// Many segments at once (one block per segment piece; the host cuts long
-// segments into pieces): batched ingest into the streams' staging buffers.
-// Four symbols per thread and step when source and destination are 4-byte
-// aligned, else one.
+// Many segments at once (one block per segment piece of at most kMapPiece
+// symbols; the host cuts longer segments into pieces): batched ingest into
+// the streams' staging buffers.  Sixteen symbols per thread: four 4-byte
+// words when source and destination are 4-byte aligned, else single bytes
+// (a wavefront's byte accesses are 64 consecutive bytes).
 __global__ void __launch_bounds__(256) k_map_segments(const SegCopy *__restrict__ segs,
                                                       const uint8_t *__restrict__ class_of) {
+    static_assert(kMapPiece == 256 * 16, "sixteen symbols per thread");
     __shared__ uint8_t tab[256];
     tab[threadIdx.x] = class_of[threadIdx.x];
     __syncthreads();
     const SegCopy sc = segs[blockIdx.x];
-    uint32_t done = 0;
+    const uint32_t t = threadIdx.x;
     if ((((uintptr_t)sc.src | (uintptr_t)sc.dst) & 3) == 0) {
         const uint32_t nw = sc.len / 4;
         const uint32_t *s4 = reinterpret_cast<const uint32_t *>(sc.src);
         uint32_t *d4 = reinterpret_cast<uint32_t *>(sc.dst);
-        for (uint32_t i = threadIdx.x; i < nw; i += blockDim.x) {
-            const uint32_t x = s4[i];
-            d4[i] = (uint32_t)tab[x & 0xFF] | ((uint32_t)tab[(x >> 8) & 0xFF] << 8) |
-                    ((uint32_t)tab[(x >> 16) & 0xFF] << 16) | ((uint32_t)tab[x >> 24] << 24);
-        }
-        done = nw * 4;
+        uint32_t x[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) x[r] = t + 256u * r < nw ? s4[t + 256u * r] : 0u;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (t + 256u * r < nw)
+                d4[t + 256u * r] = (uint32_t)tab[x[r] & 0xFF] | ((uint32_t)tab[(x[r] >> 8) & 0xFF] << 8) |
+                                   ((uint32_t)tab[(x[r] >> 16) & 0xFF] << 16) | ((uint32_t)tab[x[r] >> 24] << 24);
+        for (uint32_t i = nw * 4 + t; i < sc.len; i += 256) sc.dst[i] = tab[sc.src[i]];
+        return;
     }
-    for (uint32_t i = done + threadIdx.x; i < sc.len; i += blockDim.x) sc.dst[i] = tab[sc.src[i]];
+    uint8_t v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = t + 256u * r < sc.len ? sc.src[t + 256u * r] : 0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if (t + 256u * r < sc.len) sc.dst[t + 256u * r] = tab[v[r]];
 }
 
 hipError_t launch_map_segments(const SegCopy *segs, uint32_t n, const uint8_t *class_of, hipStream_t st) {
@@ -950,11 +961,47 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__r
     }
 }
 
+// Small counts: the whole exclusive scan in one block of 1024 threads, each
+// summing a run of at most kSmallPer consecutive values.
+constexpr uint32_t kSmallThreads = 1024, kSmallPer = 32, kSmallMax = kSmallThreads * kSmallPer;
+
+__global__ void __launch_bounds__(kSmallThreads) k_scan_small(const uint32_t *__restrict__ in,
+                                                              uint32_t *__restrict__ out, DevN dn,
+                                                              uint32_t *__restrict__ total) {
+    __shared__ uint32_t wsum[kSmallThreads / kWave];
+    const uint32_t n = dev_n(dn);
+    const uint32_t per = (n + kSmallThreads - 1) / kSmallThreads;
+    const uint32_t b = threadIdx.x * per, e = min(n, b + per);
+    uint32_t s = 0;
+    for (uint32_t i = b; i < e; ++i) s += in[i];
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t incl = wave_incl_scan(s);
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (uint32_t w = 0; w < kSmallThreads / kWave; ++w) {
+        const uint32_t x = wsum[w];
+        if (w < wave) before += x;
+        all += x;
+    }
+    uint32_t run = before + incl - s;
+    for (uint32_t i = b; i < e; ++i) {
+        const uint32_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) *total = all;
+}
+
 size_t scan_tmp_words(size_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
 
 // Exclusive scan of the first dev_n(n) values (blocks sized for n.cap).
 hipError_t launch_exclusive_scan(const uint32_t *in, uint32_t *out, DevN n, uint32_t *total, uint32_t *tmp,
                                  hipStream_t st) {
+    if (n.cap <= kSmallMax) {  // one launch instead of three
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kSmallThreads), 0, st, in, out, n, total);
+        return hipGetLastError();
+    }
     const uint32_t nb = (uint32_t)((n.cap + kScanTile - 1) / kScanTile);
     if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, st, in, n, tmp);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, st, tmp, nb, total);

@@ -107,8 +107,9 @@ struct StreamState {
     uint8_t *sym = nullptr;  // class-mapped symbols (device)
     size_t cap = 0;
     uint64_t base_abs = 0;   // absolute position of sym[0]
-    size_t valid = 0;        // symbols held
-    size_t scanned = 0;      // symbols already matched (the retained tail)
+    size_t valid = 0;        // symbols held (from sym[0])
+    size_t scanned = 0;      // of these, symbols already matched; the m_max + K_max + 3 before
+                             // sym[scanned] are the look-back of the next chunk
     bool close_pending = false;
     bool closed = false;
     uint32_t ncarry = 0;     // hit ends of this stream held in the device carry
@@ -374,7 +375,7 @@ struct StepRun {
     bool active = false;
     StepPlan pl;
     std::vector<uint32_t> which;     // streams with new bytes (ctx->streams indices)
-    std::vector<uint64_t> scan_to;   // per `which` entry: its symbols matched by this step
+    std::vector<uint64_t> scan_to;   // per `which` entry: absolute end of its symbols matched by this step
     std::vector<char> closing;       // per `which` entry: the stream ends with this step
     std::vector<uint64_t> ids;       // per step-local stream: the stream id
     // fixed at launch (a re-run after a capacity overflow reuses them)
@@ -628,7 +629,7 @@ void step_launch(oasm_ctx *c, const std::vector<uint32_t> &which, StepRun &r, in
     r.scan_to.resize(which.size());
     r.closing.resize(which.size());
     for (size_t k = 0; k < which.size(); ++k) {
-        r.scan_to[k] = c->streams[which[k]].valid;
+        r.scan_to[k] = c->streams[which[k]].base_abs + c->streams[which[k]].valid;
         r.closing[k] = c->streams[which[k]].close_pending ? 1 : 0;
     }
 
@@ -714,9 +715,9 @@ void step_wait(oasm_ctx *c, StepRun &r) {
 }
 
 // After the step: the carried hit ends stay on the device (the host keeps
-// per-stream counts); every matched stream keeps a look-back tail of its
-// symbols (moved to the front of its buffer, together with any bytes fed
-// since the step was launched), and a stream that ended is released.
+// per-stream counts); every matched stream records how far it is matched
+// (its symbols stay in place until reserve_stream needs the room), and a
+// stream that ended is released.
 void step_bookkeep(oasm_ctx *c, StepRun &r) {
     PhaseClock phase(c);
     hipStream_t st = c->st;
@@ -730,10 +731,13 @@ void step_bookkeep(oasm_ctx *c, StepRun &r) {
     if (r.ncarry_out) c->carry_cur = r.cout;  // nothing carried: keep the buffers (and the step's shape) as they are
     for (size_t k = 0; k < r.which.size(); ++k) {
         StreamState &s = c->streams[r.which[k]];
-        const uint64_t done = r.scan_to[k] - s.scanned;
+        // scan_to is absolute: a compaction queued while the step ran may
+        // have shifted the buffer's indices
+        const uint64_t upto = r.scan_to[k] - s.base_abs;
+        const uint64_t done = upto - s.scanned;
         c->stats.bytes_scanned += done;
         c->pending_bytes -= done;
-        s.scanned = r.scan_to[k];
+        s.scanned = upto;
         if (r.closing[k]) {
             // finished (no feed is accepted after a close): a closed stream
             // carries nothing (its filter segments all completed in this
@@ -750,19 +754,8 @@ void step_bookkeep(oasm_ctx *c, StepRun &r) {
             c->free_slots.push_back(s.slot);
             continue;
         }
-        const size_t keep = std::min<size_t>(s.scanned, c->lookback + 4);
-        const size_t drop = s.scanned - keep;
-        if (drop > 0) {
-            const size_t len = s.valid - drop;  // the tail and any bytes fed since the launch
-            if (len <= UINT32_MAX) {
-                c->moves.push_back(StagingMove{s.sym + drop, s.sym, (uint32_t)len, 0});
-            } else {
-                ck(hipMemcpyAsync(s.sym, s.sym + drop, len, hipMemcpyDeviceToDevice, st), "tail move");
-            }
-            s.base_abs += drop;
-            s.valid -= drop;
-            s.scanned -= drop;
-        }
+        // the matched symbols stay in place: reserve_stream reclaims them
+        // when the buffer needs room
     }
     flush_moves(c, st);
     c->stats.raw_hits += r.n_new;
@@ -964,20 +957,40 @@ void flush_moves(oasm_ctx *c, hipStream_t st) {
 // queued staging moves (the caller runs flush_moves before anything reads
 // the new buffer); otherwise it is a copy of its own.
 oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n, bool queue = false) {
-    const size_t need = s.valid + n + kPad;
-    if (need <= s.cap) return OASM_OK;
-    const size_t want = std::max(need, s.cap + s.cap / 2);
+    if (s.valid + n + kPad <= s.cap) return OASM_OK;
+    // symbols matched before the look-back tail are no longer read: the live
+    // part (tail and unmatched symbols) moves to the front of the buffer, or
+    // into a larger one
+    const size_t keep = std::min<size_t>(s.scanned, c->lookback + 4);
+    const size_t drop = s.scanned - keep;
+    const size_t live = s.valid - drop;
+    if (live + n + kPad <= s.cap) {
+        if (live <= UINT32_MAX) {
+            c->moves.push_back(StagingMove{s.sym + drop, s.sym, (uint32_t)live, 0});
+            if (!queue) flush_moves(c, c->st);
+        } else {
+            ck(hipMemcpyAsync(s.sym, s.sym + drop, live, hipMemcpyDeviceToDevice, c->st), "staging compaction");
+        }
+        s.base_abs += drop;
+        s.valid -= drop;
+        s.scanned -= drop;
+        return OASM_OK;
+    }
+    const size_t want = std::max(live + n + kPad, s.cap + s.cap / 2);
     size_t cap = 0;
     uint8_t *p = acquire_staging(c, want, cap);
     if (!p) return fail(c, OASM_E_NOMEM, "hipMalloc for stream staging failed");
     if (s.sym) {
-        if (queue && s.valid && s.valid <= UINT32_MAX) {
-            c->moves.push_back(StagingMove{s.sym, p, (uint32_t)s.valid, 0});
+        if (queue && live <= UINT32_MAX) {
+            if (live) c->moves.push_back(StagingMove{s.sym + drop, p, (uint32_t)live, 0});
             c->move_release.emplace_back(s.sym, s.cap);  // not reused before the move
         } else {
-            if (s.valid) ck(hipMemcpyAsync(p, s.sym, s.valid, hipMemcpyDeviceToDevice, c->st), "staging grow");
+            if (live) ck(hipMemcpyAsync(p, s.sym + drop, live, hipMemcpyDeviceToDevice, c->st), "staging grow");
             release_staging(c, s.sym, s.cap);
         }
+        s.base_abs += drop;
+        s.valid -= drop;
+        s.scanned -= drop;
     }
     c->staged_bytes += cap - s.cap;
     s.sym = p;
@@ -1488,10 +1501,11 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
 }
 
 // Map a list of (source, staging destination, length) copies with one
-// launch: long copies are cut into 64 KiB pieces (one block each), the table
-// goes up through pinned memory (reused once its previous upload is done).
+// launch: long copies are cut into kMapPiece-symbol pieces (one block each),
+// the table goes up through pinned memory (reused once its previous upload
+// is done).
 static void map_copies(oasm_ctx *c, const std::vector<SegCopy> &in) {
-    constexpr uint32_t kPiece = 64 * 1024;
+    constexpr uint32_t kPiece = kMapPiece;
     std::vector<SegCopy> copies;
     copies.reserve(in.size());
     for (const SegCopy &sc : in)
