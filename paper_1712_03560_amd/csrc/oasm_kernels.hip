@@ -441,39 +441,55 @@ __global__ void __launch_bounds__(256) k_recover(const uint32_t *__restrict__ r_
     const int top_w = (m - 1) >> 6, top_b = (m - 1) & 63;
     int score = m;
     int best = 255;
-    for (int l = 1; l <= steps; ++l) {
-        const uint32_t c = t[-(l - 1)];
-        uint64_t ph[kMaxW64], mh[kMaxW64], xv[kMaxW64];
-        uint64_t carry = 0;
+    // four symbols at a time: their text bytes, then their match masks, are
+    // loaded before the four column steps, so the loads overlap instead of
+    // each step waiting for two dependent loads
+    constexpr int kBatch = 4;
+    for (int l0 = 1; l0 <= steps; l0 += kBatch) {
+        uint32_t cb[kBatch];
+        uint64_t eqb[kBatch][kMaxW64];
 #pragma unroll
-        for (int w = 0; w < kMaxW64; ++w) {
-            if (w < W) {
-                const uint64_t eq = rp[(size_t)c * W + w];
-                const uint64_t x = eq & pv[w];
-                const uint64_t t1 = x + carry;
-                const uint64_t c1 = t1 < carry;
-                const uint64_t u = t1 + pv[w];
-                const uint64_t c2 = u < t1;
-                carry = c1 | c2;
-                const uint64_t xh = (u ^ pv[w]) | eq;
-                xv[w] = eq | mv[w];
-                ph[w] = mv[w] | ~(xh | pv[w]);
-                mh[w] = pv[w] & xh;
-            }
-        }
-        score += (int)((ph[top_w] >> top_b) & 1ull) - (int)((mh[top_w] >> top_b) & 1ull);
+        for (int b = 0; b < kBatch; ++b) cb[b] = l0 + b <= steps ? t[-(l0 + b - 1)] : 0u;
 #pragma unroll
-        for (int w = 0; w < kMaxW64; ++w) {
-            if (w < W) {
-                const uint64_t ph2 = (ph[w] << 1) | (w == 0 ? 1ull : ph[w - 1] >> 63);
-                const uint64_t mh2 = (mh[w] << 1) | (w == 0 ? 0ull : mh[w - 1] >> 63);
-                pv[w] = mh2 | ~(xv[w] | ph2);
-                mv[w] = ph2 & xv[w];
+        for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+            for (int w = 0; w < kMaxW64; ++w) eqb[b][w] = w < W ? rp[(size_t)cb[b] * W + w] : 0ull;
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int l = l0 + b;
+            if (l > steps) break;
+            uint64_t ph[kMaxW64], mh[kMaxW64], xv[kMaxW64];
+            uint64_t carry = 0;
+#pragma unroll
+            for (int w = 0; w < kMaxW64; ++w) {
+                if (w < W) {
+                    const uint64_t eq = eqb[b][w];
+                    const uint64_t x = eq & pv[w];
+                    const uint64_t t1 = x + carry;
+                    const uint64_t c1 = t1 < carry;
+                    const uint64_t u = t1 + pv[w];
+                    const uint64_t c2 = u < t1;
+                    carry = c1 | c2;
+                    const uint64_t xh = (u ^ pv[w]) | eq;
+                    xv[w] = eq | mv[w];
+                    ph[w] = mv[w] | ~(xh | pv[w]);
+                    mh[w] = pv[w] & xh;
+                }
             }
-        }
-        if (l >= lmin && score <= K) {
-            hk[l - (m - K)] = (uint8_t)score;
-            if (score < best) best = score;
+            score += (int)((ph[top_w] >> top_b) & 1ull) - (int)((mh[top_w] >> top_b) & 1ull);
+#pragma unroll
+            for (int w = 0; w < kMaxW64; ++w) {
+                if (w < W) {
+                    const uint64_t ph2 = (ph[w] << 1) | (w == 0 ? 1ull : ph[w - 1] >> 63);
+                    const uint64_t mh2 = (mh[w] << 1) | (w == 0 ? 0ull : mh[w - 1] >> 63);
+                    pv[w] = mh2 | ~(xv[w] | ph2);
+                    mv[w] = ph2 & xv[w];
+                }
+            }
+            if (l >= lmin && score <= K) {
+                hk[l - (m - K)] = (uint8_t)score;
+                if (score < best) best = score;
+            }
         }
     }
     r_dist[i] = (uint8_t)best;
@@ -558,8 +574,17 @@ struct RecsTile {
 };
 
 // Alg. 1 over the hit ends i .. j1-1 of one segment of pattern p in stream
-// sl, emitting into out; returns the number of occurrences.
-template <class Recs>
+// sl, emitting into out; returns the number of occurrences.  The stored best
+// (mem row idx) is also kept in registers (bs, bl), since R2 compares only
+// with it; the candidates of a start are read in batches of CAND (their
+// ends and hit-set bytes do not depend on the state) before R1-R3 are
+// applied to them in order.  Batches pay where the records come from global
+// memory (k_filter: 8); from an LDS tile (k_filter_long) they only add reads.
+constexpr int kCandGlobal = 8, kCandTile = 1;
+// a start's candidates and the batch past them fit one tile of k_filter_long
+static_assert(2 * (kMaxLevels - 1) + 1 + kCandTile <= (int)kTile, "filter tile too small");
+
+template <int CAND, class Recs>
 __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, uint32_t sl, int m, int K,
                                 uint32_t rules, uint64_t *lv_s, uint32_t *lv_l, uint32_t lstride, OccRec *out) {
     const bool acc_last = (rules & kRuleAccLast) != 0, eq3_ge = (rules & kRuleEq3Ge) != 0;
@@ -569,7 +594,8 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
     const int qoff = m - K;
     for (int q = 0; q <= K; ++q) lv_l[q * lstride] = 0;
     int idx = K;
-    bool ins = false;
+    uint64_t bs = 0;  // mem row idx: start and length (0 = empty)
+    uint32_t bl = 0;
     uint32_t cnt = 0;
 
     auto emit = [&](uint64_t pos) {
@@ -604,7 +630,7 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
         }
         for (int j = idx; j <= K; ++j) lv_l[j * lstride] = 0;
         idx = K;
-        ins = false;
+        bl = 0;
     };
 
     uint32_t lo = i;
@@ -617,35 +643,52 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
             if (R.e(lo) + 1 >= s + lmin) break;
         }
         if (lo >= j1) break;
-        if (R.e(lo) + 1 > s + lmax) {  // no hit end reachable from s: jump
-            s = R.e(lo) + 1 - lmax;
+        const uint64_t elo = R.e(lo);
+        if (elo + 1 > s + lmax) {  // no hit end reachable from s: jump
+            s = elo + 1 - lmax;
             continue;
         }
-        if (ins && lv_s[idx * lstride] + lv_l[idx * lstride] - 1 < s)
-            emit(lv_s[idx * lstride] + lv_l[idx * lstride] - 1);
-        R.need(lo, min(j1, lo + 2 * K + 2) - 1);  // every candidate of s and the end test
-        for (uint32_t j = lo; j < j1 && R.e(j) + 1 <= s + lmax; ++j) {
-            const int l = (int)(R.e(j) + 1 - s);
-            const uint32_t k = R.k(j, l - qoff);
-            if (k == kNoHit) continue;
-            if ((int)k < idx) {  // R1
-                idx = (int)k;
-                ins = true;
-                lv_s[k * lstride] = s;
-                lv_l[k * lstride] = (uint32_t)l;
-            } else if ((int)k == idx) {  // R2 / R3: earlier end, then shorter (or: keep the first)
-                const uint32_t lk = lv_l[k * lstride];
-                const uint64_t be = lv_s[k * lstride] + lk;
-                if (lk == 0 || (!start_order && (s + l < be || (s + l == be && (uint32_t)l < lk)))) {
-                    ins = true;
+        if (bl && bs + bl - 1 < s) emit(bs + bl - 1);
+        // the candidates of s: at most 2K + 1 ends, read CAND at a time
+        R.need(lo, min(j1, lo + 2 * K + 1 + CAND) - 1);
+        for (uint32_t j = lo; j < j1; j += CAND) {
+            uint64_t ee[CAND];
+            uint32_t kk[CAND];
+#pragma unroll
+            for (int b = 0; b < CAND; ++b) ee[b] = j + b < j1 ? R.e(j + b) : ~0ull;
+#pragma unroll
+            for (int b = 0; b < CAND; ++b)
+                kk[b] = ee[b] != ~0ull && ee[b] + 1 <= s + lmax ? R.k(j + b, (int)(ee[b] + 1 - s) - qoff) : 0x100u;
+            bool past = false;
+#pragma unroll
+            for (int b = 0; b < CAND; ++b) {
+                if (kk[b] == 0x100u) {  // past the last candidate of s
+                    past = true;
+                    break;
+                }
+                const uint32_t k = kk[b];
+                if (k == kNoHit) continue;
+                const uint32_t l = (uint32_t)(ee[b] + 1 - s);
+                if ((int)k < idx) {  // R1
+                    idx = (int)k;
+                    bs = s;
+                    bl = l;
                     lv_s[k * lstride] = s;
-                    lv_l[k * lstride] = (uint32_t)l;
+                    lv_l[k * lstride] = l;
+                } else if ((int)k == idx) {  // R2 / R3: earlier end, then shorter (or: keep the first)
+                    if (bl == 0 || (!start_order && (s + l < bs + bl || (s + l == bs + bl && l < bl)))) {
+                        bs = s;
+                        bl = l;
+                        lv_s[k * lstride] = s;
+                        lv_l[k * lstride] = l;
+                    }
                 }
             }
+            if (past) break;
         }
         ++s;
     }
-    if (ins) emit(lv_s[idx * lstride] + lv_l[idx * lstride] - 1);
+    if (bl) emit(bs + bl - 1);
     return cnt;
 }
 
@@ -693,7 +736,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     uint64_t *lv_s = lds_lv + threadIdx.x;
     uint32_t *lv_l = reinterpret_cast<uint32_t *>(lds_lv + (size_t)nlevels * 64) + threadIdx.x;
     RecsGlobal R{r_end, r_hk, hks};
-    seg_cnt[i] = filter_walk(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 64, seg_out + (size_t)i * out_stride);
+    seg_cnt[i] = filter_walk<kCandGlobal>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 64, seg_out + (size_t)i * out_stride);
 }
 
 // One wavefront (block of 64) per long segment (grid-stride over the list):
@@ -744,7 +787,7 @@ __global__ void __launch_bounds__(64) k_filter_long(const uint32_t *__restrict__
             continue;
         }
         RecsTile R{r_end, r_hk, hks, j1, tend, thk, 0u, 0u};
-        const uint32_t cnt = filter_walk(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 1, seg_out + (size_t)i * out_stride);
+        const uint32_t cnt = filter_walk<kCandTile>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 1, seg_out + (size_t)i * out_stride);
         if (lane == 0) seg_cnt[i] = cnt;
         __syncthreads();  // the next segment's tile and mem rows
     }
