@@ -167,15 +167,49 @@ hipError_t launch_recover(const uint32_t *r_pat, const uint32_t *r_sl, const uin
                           uint32_t nclass, uint32_t hks, uint8_t *r_hk, uint8_t *r_dist, uint32_t *err,
                           hipStream_t st);
 
-// K3: the filter, one thread per segment of a (stream, pattern) run, and
-// one wavefront per segment longer than 32 hit ends (two launches).
+// A long filter segment walked in parallel (see launch_filter).
+struct LongDesc {
+    uint64_t s0;      // the segment's first start (absolute position)
+    uint32_t i, j1;   // its hit-end records
+    uint32_t off;     // first slot in the per-start array
+    uint32_t len;     // starts s0 .. s0 + len - 1 (0: not walked in parallel)
+    uint32_t nchain;  // emissions of the walk
+    uint32_t ncheck;  // checkpoints of its chain
+};
+
+// Per-step state of the parallel walk of long segments: `desc` holds
+// filter_long_list_words(n.cap) descriptors; `next`, `jump[0]` and `jump[1]`
+// cap_next slots each (one per start of every such segment; null when
+// cap_next is 0); `*res` (two
+// words) must be 0 before the launch and counts the descriptors (high 24
+// bits) and the slots asked for (low 40 bits), also beyond cap_next: when
+// `can_grow` is set, a segment that did not get its slots is left out (its
+// occurrences missing) and the caller runs the step again with more slots;
+// otherwise it is walked serially.  `*err` is set if a walk's emissions
+// outnumber its segment's hit ends (impossible: each emits its own best).
+struct LongWalk {
+    LongDesc *desc;
+    uint32_t *next;
+    uint32_t *jump[2];
+    uint32_t cap_next;
+    uint32_t can_grow;
+    unsigned long long *res;
+    uint32_t *err;
+};
+
+// K3: the filter, one thread per segment of a (stream, pattern) run of up to
+// 32 hit ends, one wavefront per longer segment, and for a segment with at
+// least kLongParStarts starts the walk split over its starts (three more
+// launches when cap_next > 0).
 // `rules`: kRule* bits (0 = no filtering, only the open-segment flags).
 // `long_list` holds filter_long_list_words(n.cap) words; `*long_cnt` must be
 // 0 before the launch.  out_stride = K_max + 1 <= 64.
+constexpr uint32_t kLongParStarts = 256;
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
                          DevN n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams,
                          uint32_t rules, uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt,
-                         uint32_t *carry_flag, uint32_t *long_list, uint32_t *long_cnt, hipStream_t st);
+                         uint32_t *carry_flag, uint32_t *long_list, uint32_t *long_cnt, const LongWalk &lw,
+                         hipStream_t st);
 size_t filter_long_list_words(uint32_t cap);
 
 // Gather the filter output into a dense array.

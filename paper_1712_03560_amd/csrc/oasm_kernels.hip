@@ -10,6 +10,7 @@
 //   compactions, prefix scan, symbol mapping.
 //
 // Integer bit-vector work only; no matrix cores.
+#include <algorithm>
 #include <utility>
 
 #include "oasm_device.h"
@@ -548,10 +549,12 @@ struct RecsGlobal {
     __device__ __forceinline__ uint32_t k(uint32_t j, int q) const { return hk[(size_t)j * hks + q]; }
 };
 
-// The same through a tile of kTile records in LDS, refilled by the whole
-// wavefront (every lane runs the walk with the same values) whenever a record
-// outside the tile is needed; the tile then starts at the walk's lowest live
-// record.
+// The same through a tile of kTile records in LDS, refilled by the one
+// wavefront that runs the walk (every lane runs it with the same values)
+// whenever a record outside the tile is needed; the tile then starts at the
+// walk's lowest live record.  A wavefront's LDS accesses complete in order,
+// so a wave barrier (keeping the compiler from moving them) is all the
+// ordering the refill needs.
 struct RecsTile {
     const uint64_t *end;
     const uint8_t *hk;
@@ -561,82 +564,99 @@ struct RecsTile {
     uint32_t base, lim;
     __device__ __forceinline__ void need(uint32_t lo, uint32_t j) {
         if (j < lim && lo >= base) return;
-        __syncthreads();  // the tile's last readers are done
+        const uint32_t lane = threadIdx.x & 63;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();  // the tile's last readers are done
         base = lo;
         lim = min(j1, lo + kTile);
         const uint32_t cnt = lim - base;
-        for (uint32_t x = threadIdx.x; x < cnt; x += blockDim.x) tend[x] = end[base + x];
-        for (uint32_t x = threadIdx.x; x < cnt * hks; x += blockDim.x) thk[x] = hk[(size_t)base * hks + x];
-        __syncthreads();
+        for (uint32_t x = lane; x < cnt; x += 64) tend[x] = end[base + x];
+        for (uint32_t x = lane; x < cnt * hks; x += 64) thk[x] = hk[(size_t)base * hks + x];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
     __device__ __forceinline__ uint64_t e(uint32_t j) const { return tend[j - base]; }
     __device__ __forceinline__ uint32_t k(uint32_t j, int q) const { return thk[(j - base) * hks + q]; }
 };
 
-// Alg. 1 over the hit ends i .. j1-1 of one segment of pattern p in stream
-// sl, emitting into out; returns the number of occurrences.  The stored best
-// (mem row idx) is also kept in registers (bs, bl), since R2 compares only
-// with it; the candidates of a start are read in batches of CAND (their
-// ends and hit-set bytes do not depend on the state) before R1-R3 are
-// applied to them in order.  Batches pay where the records come from global
-// memory (k_filter: 8); from an LDS tile (k_filter_long) they only add reads.
+// Alg. 1 over the hit ends of one segment of pattern p in stream sl (records
+// lo .. j1-1, lo at or before the first candidate of start s), from an empty
+// state at start s, emitting into out.  The stored best (mem row idx) is
+// also kept in registers (bs, bl), since R2 compares only with it; the
+// candidates of a start are read in batches of CAND (their ends and hit-set
+// bytes do not depend on the state) before R1-R3 are applied to them in
+// order.  Batches pay where the records come from global memory (8); from an
+// LDS tile (k_filter_long's serial walk) they only add reads.
+//
+// FIRST: stop at the walk's first emission, at the start where it happens
+// (returned in `next`; kEndOfSegment when the walk reaches the segment's end
+// instead, after emitting what it holds).  An emission leaves the state
+// empty, so the walk from an empty state at the start where an emission
+// happens is the rest of the walk: this is what the parallel form of long
+// segments builds on.  EMIT: write mem rows and occurrences (without it only
+// the emission points are computed, for which the best alone decides).
 constexpr int kCandGlobal = 8, kCandTile = 1;
 // a start's candidates and the batch past them fit one tile of k_filter_long
 static_assert(2 * (kMaxLevels - 1) + 1 + kCandTile <= (int)kTile, "filter tile too small");
+constexpr uint64_t kEndOfSegment = ~0ull;
 
-template <int CAND, class Recs>
-__device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, uint32_t sl, int m, int K,
-                                uint32_t rules, uint64_t *lv_s, uint32_t *lv_l, uint32_t lstride, OccRec *out) {
+struct WalkEnd {
+    uint64_t next;  // start of the first emission (FIRST), or kEndOfSegment
+    uint32_t cnt;   // occurrences written
+};
+
+template <int CAND, bool EMIT, bool FIRST, class Recs>
+__device__ WalkEnd walk_from(Recs &R, uint32_t lo, uint32_t j1, uint64_t s, uint32_t p, uint32_t sl, int m, int K,
+                             uint32_t rules, uint64_t *lv_s, uint32_t *lv_l, uint32_t lstride, OccRec *out) {
     const bool acc_last = (rules & kRuleAccLast) != 0, eq3_ge = (rules & kRuleEq3Ge) != 0;
     const bool start_order = (rules & kRuleStartOrder) != 0, disjoint = (rules & kRuleDisjoint) != 0;
     const int lmax = m + K;
     const int lmin = m - K < 1 ? 1 : m - K;
     const int qoff = m - K;
-    for (int q = 0; q <= K; ++q) lv_l[q * lstride] = 0;
+    if constexpr (EMIT)
+        for (int q = 0; q <= K; ++q) lv_l[q * lstride] = 0;
     int idx = K;
     uint64_t bs = 0;  // mem row idx: start and length (0 = empty)
     uint32_t bl = 0;
     uint32_t cnt = 0;
 
     auto emit = [&](uint64_t pos) {
-        int64_t acc = 0;
-        uint64_t accepted = 0;  // levels accepted so far in this emission
-        for (int j = idx; j <= K; ++j) {
-            const uint32_t lj = lv_l[j * lstride];
-            if (lj == 0) continue;
-            const uint64_t sj = lv_s[j * lstride];
-            const int64_t r = (int64_t)(pos - sj + 1);  // validation counter r(j)
-            const int64_t l = (int64_t)lj;
-            bool ok = j == idx || (eq3_ge ? r - acc >= l : r - acc > l);  // Eq. 3
-            if (ok && disjoint && j != idx) {
-                const uint64_t je = sj + lj - 1;
-                for (uint64_t mk = accepted; mk; mk &= mk - 1) {
-                    const int q = __builtin_ctzll(mk);
-                    const uint64_t qs = lv_s[q * lstride], qe = qs + lv_l[q * lstride] - 1;
-                    if (!(je < qs || qe < sj)) ok = false;
+        if constexpr (EMIT) {
+            int64_t acc = 0;
+            uint64_t accepted = 0;  // levels accepted so far in this emission
+            for (int j = idx; j <= K; ++j) {
+                const uint32_t lj = lv_l[j * lstride];
+                if (lj == 0) continue;
+                const uint64_t sj = lv_s[j * lstride];
+                const int64_t r = (int64_t)(pos - sj + 1);  // validation counter r(j)
+                const int64_t l = (int64_t)lj;
+                bool ok = j == idx || (eq3_ge ? r - acc >= l : r - acc > l);  // Eq. 3
+                if (ok && disjoint && j != idx) {
+                    const uint64_t je = sj + lj - 1;
+                    for (uint64_t mk = accepted; mk; mk &= mk - 1) {
+                        const int q = __builtin_ctzll(mk);
+                        const uint64_t qs = lv_s[q * lstride], qe = qs + lv_l[q * lstride] - 1;
+                        if (!(je < qs || qe < sj)) ok = false;
+                    }
+                }
+                if (ok) {
+                    OccRec o;
+                    o.start_abs = sj;
+                    o.pattern = p;
+                    o.stream_local = sl;
+                    o.len = lj;
+                    o.k = (uint32_t)j;
+                    out[cnt++] = o;
+                    acc = acc_last ? l : acc + l;
+                    accepted |= 1ull << j;
                 }
             }
-            if (ok) {
-                OccRec o;
-                o.start_abs = sj;
-                o.pattern = p;
-                o.stream_local = sl;
-                o.len = lj;
-                o.k = (uint32_t)j;
-                out[cnt++] = o;
-                acc = acc_last ? l : acc + l;
-                accepted |= 1ull << j;
-            }
+            for (int j = idx; j <= K; ++j) lv_l[j * lstride] = 0;
         }
-        for (int j = idx; j <= K; ++j) lv_l[j * lstride] = 0;
         idx = K;
         bl = 0;
     };
 
-    uint32_t lo = i;
-    R.need(i, i);
-    const uint64_t e0 = R.e(i);
-    uint64_t s = e0 + 1 >= (uint64_t)lmax ? e0 + 1 - lmax : 0;
     while (true) {
         for (; lo < j1; ++lo) {
             R.need(lo, lo);
@@ -648,7 +668,10 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
             s = elo + 1 - lmax;
             continue;
         }
-        if (bl && bs + bl - 1 < s) emit(bs + bl - 1);
+        if (bl && bs + bl - 1 < s) {
+            emit(bs + bl - 1);
+            if constexpr (FIRST) return WalkEnd{s, cnt};
+        }
         // the candidates of s: at most 2K + 1 ends, read CAND at a time
         R.need(lo, min(j1, lo + 2 * K + 1 + CAND) - 1);
         for (uint32_t j = lo; j < j1; j += CAND) {
@@ -673,14 +696,18 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
                     idx = (int)k;
                     bs = s;
                     bl = l;
-                    lv_s[k * lstride] = s;
-                    lv_l[k * lstride] = l;
+                    if constexpr (EMIT) {
+                        lv_s[k * lstride] = s;
+                        lv_l[k * lstride] = l;
+                    }
                 } else if ((int)k == idx) {  // R2 / R3: earlier end, then shorter (or: keep the first)
                     if (bl == 0 || (!start_order && (s + l < bs + bl || (s + l == bs + bl && l < bl)))) {
                         bs = s;
                         bl = l;
-                        lv_s[k * lstride] = s;
-                        lv_l[k * lstride] = l;
+                        if constexpr (EMIT) {
+                            lv_s[k * lstride] = s;
+                            lv_l[k * lstride] = l;
+                        }
                     }
                 }
             }
@@ -689,7 +716,19 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
         ++s;
     }
     if (bl) emit(bs + bl - 1);
-    return cnt;
+    return WalkEnd{kEndOfSegment, cnt};
+}
+
+// The whole segment i .. j1-1 from its first start; returns the number of
+// occurrences written.
+template <int CAND, class Recs>
+__device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, uint32_t sl, int m, int K,
+                                uint32_t rules, uint64_t *lv_s, uint32_t *lv_l, uint32_t lstride, OccRec *out) {
+    const uint64_t lmax = (uint64_t)(m + K);
+    R.need(i, i);
+    const uint64_t e0 = R.e(i);
+    const uint64_t s0 = e0 + 1 >= lmax ? e0 + 1 - lmax : 0;
+    return walk_from<CAND, true, false>(R, i, j1, s0, p, sl, m, K, rules, lv_s, lv_l, lstride, out).cnt;
 }
 
 // One thread per hit end; the thread that owns the first end of a segment
@@ -739,25 +778,34 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     seg_cnt[i] = filter_walk<kCandGlobal>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 64, seg_out + (size_t)i * out_stride);
 }
 
-// One wavefront (block of 64) per long segment (grid-stride over the list):
-// the lanes find the segment's end together, write its carry flags, and all
-// run the walk with the same values, reading the hit ends and hit-set bytes
-// from an LDS tile.  Dynamic LDS: kTile ends, kTile * hks bytes, the mem rows.
-__global__ void __launch_bounds__(64) k_filter_long(const uint32_t *__restrict__ r_pat,
-                                                    const uint32_t *__restrict__ r_sl,
-                                                    const uint64_t *__restrict__ r_end,
-                                                    const uint8_t *__restrict__ r_hk, DevN dn, uint32_t hks,
-                                                    const PatDesc *__restrict__ pats,
-                                                    const StreamDesc *__restrict__ streams, uint32_t rules,
-                                                    uint32_t out_stride, OccRec *__restrict__ seg_out,
-                                                    uint32_t *__restrict__ seg_cnt, uint32_t *__restrict__ carry_flag,
-                                                    const uint32_t *__restrict__ long_list,
-                                                    const uint32_t *__restrict__ long_cnt, uint32_t nlevels) {
+// One block of kLongBlock threads per long segment (grid-stride over the
+// list): the block finds the segment's end (each wavefront probes 512
+// records per round) and writes its carry flags; a segment with at least
+// kLongParStarts starts reserves its per-start slots for the parallel walk
+// below, and a shorter one is walked by wavefront 0 alone (every lane with
+// the same values) from an LDS tile.  Dynamic LDS: kTile ends, the mem rows,
+// kTile * hks bytes.
+constexpr uint32_t kLongBlock = 256;
+
+__global__ void __launch_bounds__(kLongBlock) k_filter_long(const uint32_t *__restrict__ r_pat,
+                                                            const uint32_t *__restrict__ r_sl,
+                                                            const uint64_t *__restrict__ r_end,
+                                                            const uint8_t *__restrict__ r_hk, DevN dn, uint32_t hks,
+                                                            const PatDesc *__restrict__ pats,
+                                                            const StreamDesc *__restrict__ streams, uint32_t rules,
+                                                            uint32_t out_stride, OccRec *__restrict__ seg_out,
+                                                            uint32_t *__restrict__ seg_cnt,
+                                                            uint32_t *__restrict__ carry_flag,
+                                                            const uint32_t *__restrict__ long_list,
+                                                            const uint32_t *__restrict__ long_cnt, uint32_t nlevels,
+                                                            LongWalk lw, uint32_t desc_cap) {
     extern __shared__ uint64_t lds_tile[];
+    __shared__ uint32_t s_brk;
+    __shared__ unsigned long long s_res;
     const bool do_filter = (rules & kRulePaper) != 0;
     const uint32_t n = dev_n(dn);
     const uint32_t nlong = *long_cnt;
-    const uint32_t lane = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
     uint64_t *tend = lds_tile;
     uint64_t *lv_s = lds_tile + kTile;
     uint32_t *lv_l = reinterpret_cast<uint32_t *>(lv_s + nlevels);
@@ -769,34 +817,259 @@ __global__ void __launch_bounds__(64) k_filter_long(const uint32_t *__restrict__
         const int m = d.m, K = d.k;
         const uint64_t gap = (uint64_t)(m + K);
         // the segment's end: the first record past i that breaks the run
+        constexpr int kProbe = 8;
         uint32_t j1 = n;
-        for (uint32_t b = i + 1; b < n; b += 64) {
-            const uint32_t j = b + lane;
-            const bool brk = j >= n || r_pat[j] != p || r_sl[j] != sl || r_end[j] - r_end[j - 1] >= gap;
-            const uint64_t bal = __ballot(brk);
-            if (bal) {
-                j1 = b + (uint32_t)__builtin_ctzll(bal);
+        for (uint32_t b = i + 1; b < n; b += nwave * 64 * kProbe) {
+            if (tid == 0) s_brk = 0xFFFFFFFFu;
+            __syncthreads();
+            const uint32_t wb = b + wave * 64 * kProbe;
+            bool brk[kProbe];
+#pragma unroll
+            for (int q = 0; q < kProbe; ++q) {
+                const uint32_t j = wb + q * 64 + lane;
+                brk[q] = j >= n || r_pat[j] != p || r_sl[j] != sl || r_end[j] - r_end[j - 1] >= gap;
+            }
+            uint32_t first = 0xFFFFFFFFu;
+#pragma unroll
+            for (int q = 0; q < kProbe; ++q) {
+                const uint64_t bal = __ballot(brk[q]);
+                if (bal && first == 0xFFFFFFFFu) first = wb + q * 64 + (uint32_t)__builtin_ctzll(bal);
+            }
+            if (lane == 0 && first != 0xFFFFFFFFu) atomicMin(&s_brk, first);
+            __syncthreads();
+            const uint32_t f = s_brk;
+            __syncthreads();  // every thread has read it before the next round resets it
+            if (f != 0xFFFFFFFFu) {
+                j1 = min(f, n);
                 break;
             }
         }
         const StreamDesc sd = streams[sl];
         const bool open = do_filter && !sd.closed && r_end[j1 - 1] + gap > sd.frontier;
-        for (uint32_t j = i + lane; j < j1; j += 64) carry_flag[j] = open ? 1u : 0u;
+        for (uint32_t j = i + tid; j < j1; j += blockDim.x) carry_flag[j] = open ? 1u : 0u;
         if (open || !do_filter) {
-            if (lane == 0) seg_cnt[i] = 0;
+            if (tid == 0) seg_cnt[i] = 0;
             continue;
         }
-        RecsTile R{r_end, r_hk, hks, j1, tend, thk, 0u, 0u};
-        const uint32_t cnt = filter_walk<kCandTile>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 1, seg_out + (size_t)i * out_stride);
-        if (lane == 0) seg_cnt[i] = cnt;
+        // a segment with many starts is walked in parallel by the kernels
+        // below: reserve a slot per start
+        const uint64_t lmax = (uint64_t)(m + K), lmin = (uint64_t)(m - K < 1 ? 1 : m - K);
+        const uint64_t e0 = r_end[i];
+        const uint64_t s0 = e0 + 1 >= lmax ? e0 + 1 - lmax : 0;
+        const uint64_t nstarts = r_end[j1 - 1] + 2 - lmin - s0;  // s0 .. the last end's shortest start
+        if (lw.desc != nullptr && nstarts >= kLongParStarts && nstarts < (1ull << 31)) {
+            if (tid == 0) s_res = atomicAdd(lw.res, (1ull << 40) | nstarts);
+            __syncthreads();
+            const uint64_t old = s_res;
+            const uint32_t di = (uint32_t)(old >> 40);
+            const uint64_t off = old & ((1ull << 40) - 1);
+            const bool fits = off + nstarts <= lw.cap_next && di < desc_cap;
+            if (tid == 0 && di < desc_cap) {
+                LongDesc ld;
+                ld.s0 = s0;
+                ld.i = i;
+                ld.j1 = j1;
+                ld.off = (uint32_t)(off < lw.cap_next ? off : lw.cap_next);  // keeps offsets ordered
+                ld.len = fits ? (uint32_t)nstarts : 0u;
+                ld.nchain = 0;
+                ld.ncheck = 0;
+                lw.desc[di] = ld;
+            }
+            if (fits || lw.can_grow) {  // walked below (or in the step's next run)
+                if (tid == 0) seg_cnt[i] = 0;
+                continue;
+            }
+        }
+        if (wave == 0) {
+            RecsTile R{r_end, r_hk, hks, j1, tend, thk, 0u, 0u};
+            const uint32_t cnt =
+                filter_walk<kCandTile>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 1, seg_out + (size_t)i * out_stride);
+            if (lane == 0) seg_cnt[i] = cnt;
+        }
         __syncthreads();  // the next segment's tile and mem rows
+    }
+}
+
+// ---- long segments walked in parallel
+// From an empty state at a start s, the walk up to its first emission
+// depends on s alone; after an emission the state is empty again.  So the
+// walk of a segment is the chain s0 -> next(s0) -> next(next(s0)) -> ...,
+// where next(s) is the start at which the walk from an empty state at s
+// first emits, and each link emits what the walk from its start holds at
+// the next one.
+//   k_long_next    next(s) for every start of every long segment (a slot
+//                  per start; slots hold slot indices, kNoNext for a walk
+//                  that reaches the segment's end)
+//   k_long_double  kChainLevels times: jump(x) = jump(jump(x)), so that the
+//                  last level jumps 2^kChainLevels links
+//   k_long_chain   one wavefront per segment follows the last level from
+//                  s0 and writes every 2^kChainLevels-th link (checkpoints)
+//   k_long_enum    from every checkpoint at once, the links up to the next
+//                  one, each written at its rank
+//   k_long_emit    every link of every chain at once re-walked, link k's
+//                  occurrences written in the slot of the segment's k-th
+//                  hit end (each emission writes its own best, whose ends
+//                  increase, so there are no more links than hit ends),
+//                  so that the compaction that follows keeps the walk's
+//                  order.
+constexpr uint32_t kNoNext = 0xFFFFFFFFu;
+constexpr int kChainLevels = 8;
+
+// The descriptor that owns per-start slot x: the last one whose offset is
+// <= x (offsets increase with the descriptor index); `nd` > 0.
+__device__ __forceinline__ uint32_t long_desc_of(const LongDesc *desc, uint32_t nd, uint32_t x) {
+    uint32_t lo = 0, hi = nd;  // desc[lo].off <= x (desc[0].off == 0)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (desc[mid].off <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// The first record in [lo, hi) whose end is >= v (ends increase), or hi.
+__device__ __forceinline__ uint32_t first_end_at_least(const uint64_t *end, uint32_t lo, uint32_t hi, uint64_t v) {
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        if (end[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void long_counts(const LongWalk &lw, uint32_t desc_cap, uint32_t &nd, uint32_t &nslots) {
+    const unsigned long long r = *lw.res;
+    nd = min((uint32_t)(r >> 40), desc_cap);
+    const uint64_t used = r & ((1ull << 40) - 1);
+    nslots = (uint32_t)min<uint64_t>(used, lw.cap_next);
+}
+
+__global__ void __launch_bounds__(64) k_long_next(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
+                                                  const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
+                                                  uint32_t hks, const PatDesc *__restrict__ pats, uint32_t rules,
+                                                  LongWalk lw, uint32_t desc_cap) {
+    uint32_t nd, nslots;
+    long_counts(lw, desc_cap, nd, nslots);
+    if (nd == 0) return;
+    RecsGlobal R{r_end, r_hk, hks};
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nslots; x += gridDim.x * blockDim.x) {
+        const LongDesc d = lw.desc[long_desc_of(lw.desc, nd, x)];
+        uint32_t nx = kNoNext;
+        if (x - d.off < d.len) {  // (slots of a descriptor that did not get them stay kNoNext)
+            const uint64_t s = d.s0 + (x - d.off);
+            const uint32_t p = r_pat[d.i], sl = r_sl[d.i];
+            const PatDesc pd = pats[p];
+            const int m = pd.m, K = pd.k;
+            const uint64_t lmin = (uint64_t)(m - K < 1 ? 1 : m - K);
+            const uint32_t lo = first_end_at_least(r_end, d.i, d.j1, s + lmin - 1);
+            if (lo < d.j1) {
+                const WalkEnd w = walk_from<kCandGlobal, false, true>(R, lo, d.j1, s, p, sl, m, K, rules, nullptr,
+                                                                       nullptr, 0, nullptr);
+                if (w.next != kEndOfSegment) nx = d.off + (uint32_t)(w.next - d.s0);
+            }
+        }
+        lw.next[x] = nx;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_long_double(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+                                                     LongWalk lw, uint32_t desc_cap) {
+    uint32_t nd, nslots;
+    long_counts(lw, desc_cap, nd, nslots);
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nslots; x += gridDim.x * blockDim.x) {
+        const uint32_t v = src[x];
+        dst[x] = v == kNoNext ? kNoNext : src[v];
+    }
+}
+
+// One wavefront per descriptor (its lane 0): the checkpoints, into `ckpt`.
+__global__ void __launch_bounds__(64) k_long_chain(const uint32_t *__restrict__ far, uint32_t *__restrict__ ckpt,
+                                                   LongWalk lw, uint32_t desc_cap) {
+    uint32_t nd, nslots;
+    long_counts(lw, desc_cap, nd, nslots);
+    if (threadIdx.x != 0) return;
+    for (uint32_t di = blockIdx.x; di < nd; di += gridDim.x) {
+        const LongDesc d = lw.desc[di];
+        uint32_t c = 0;
+        if (d.len != 0) {
+            uint32_t node = d.off;
+            while (true) {
+                ckpt[d.off + c] = node;
+                ++c;
+                const uint32_t nx = far[node];
+                if (nx == kNoNext || nx <= node || nx >= d.off + d.len) break;  // (links only move forward)
+                node = nx;
+            }
+        }
+        lw.desc[di].ncheck = c;
+    }
+}
+
+// From checkpoint c of a descriptor, links c * 2^kChainLevels onwards, each
+// written (as its slot index) at slot off + rank of `chain`.
+__global__ void __launch_bounds__(64) k_long_enum(const uint32_t *__restrict__ next, const uint32_t *__restrict__ ckpt,
+                                                  uint32_t *__restrict__ chain, LongWalk lw, uint32_t desc_cap) {
+    uint32_t nd, nslots;
+    long_counts(lw, desc_cap, nd, nslots);
+    if (nd == 0) return;
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nslots; x += gridDim.x * blockDim.x) {
+        const uint32_t di = long_desc_of(lw.desc, nd, x);
+        const LongDesc d = lw.desc[di];
+        const uint32_t c = x - d.off;
+        if (c >= d.len || c >= d.ncheck) continue;
+        uint32_t node = ckpt[x];
+        const uint32_t r0 = c << kChainLevels;
+        for (uint32_t j = 0; j < (1u << kChainLevels); ++j) {
+            if (r0 + j >= d.len) break;  // cannot happen: the links are distinct starts
+            chain[d.off + r0 + j] = node;
+            const uint32_t nx = next[node];
+            if (nx == kNoNext || nx <= node || nx >= d.off + d.len) {
+                lw.desc[di].nchain = r0 + j + 1;  // the last checkpoint's run reaches the end
+                break;
+            }
+            node = nx;
+        }
+    }
+}
+
+// Every link of every chain at once; mem rows in LDS as k_filter's.
+__global__ void __launch_bounds__(64) k_long_emit(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
+                                                  const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
+                                                  uint32_t hks, const PatDesc *__restrict__ pats, uint32_t rules,
+                                                  uint32_t out_stride, OccRec *__restrict__ seg_out,
+                                                  uint32_t *__restrict__ seg_cnt, const uint32_t *__restrict__ chain,
+                                                  LongWalk lw, uint32_t desc_cap, uint32_t nlevels) {
+    extern __shared__ uint64_t lds_lv[];
+    uint32_t nd, nslots;
+    long_counts(lw, desc_cap, nd, nslots);
+    if (nd == 0) return;
+    uint64_t *lv_s = lds_lv + threadIdx.x;
+    uint32_t *lv_l = reinterpret_cast<uint32_t *>(lds_lv + (size_t)nlevels * 64) + threadIdx.x;
+    RecsGlobal R{r_end, r_hk, hks};
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < nslots; x += gridDim.x * blockDim.x) {
+        const LongDesc d = lw.desc[long_desc_of(lw.desc, nd, x)];
+        const uint32_t k = x - d.off;
+        if (k >= d.len || k >= d.nchain) continue;
+        if (d.i + k >= d.j1) {  // cannot happen: one best per emission
+            atomicOr(lw.err, 1u);
+            continue;
+        }
+        const uint64_t s = d.s0 + (chain[x] - d.off);
+        const uint32_t p = r_pat[d.i], sl = r_sl[d.i];
+        const PatDesc pd = pats[p];
+        const int m = pd.m, K = pd.k;
+        const uint64_t lmin = (uint64_t)(m - K < 1 ? 1 : m - K);
+        const uint32_t lo = first_end_at_least(r_end, d.i, d.j1, s + lmin - 1);
+        const WalkEnd w = walk_from<kCandGlobal, true, true>(R, lo, d.j1, s, p, sl, m, K, rules, lv_s, lv_l, 64,
+                                                             seg_out + (size_t)(d.i + k) * out_stride);
+        seg_cnt[d.i + k] = w.cnt;
     }
 }
 
 hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint64_t *r_end, const uint8_t *r_hk,
                          DevN n, uint32_t hks, const PatDesc *pats, const StreamDesc *streams, uint32_t rules,
                          uint32_t out_stride, OccRec *seg_out, uint32_t *seg_cnt, uint32_t *carry_flag,
-                         uint32_t *long_list, uint32_t *long_cnt, hipStream_t st) {
+                         uint32_t *long_list, uint32_t *long_cnt, const LongWalk &lw, hipStream_t st) {
     if (n.cap == 0) return hipSuccess;
     const uint32_t nlevels = out_stride;  // K_max + 1 levels
     if (nlevels > (uint32_t)kMaxLevels) return hipErrorInvalidValue;
@@ -811,8 +1084,40 @@ hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint
     const uint32_t grid = maxlong < 512 ? maxlong : 512;
     const size_t shl = kTile * sizeof(uint64_t) + (size_t)nlevels * (sizeof(uint64_t) + sizeof(uint32_t)) +
                        (size_t)kTile * hks;
-    hipLaunchKernelGGL(k_filter_long, dim3(grid), dim3(64), shl, st, r_pat, r_sl, r_end, r_hk, n, hks, pats, streams,
-                       rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
+    const uint32_t desc_cap = (uint32_t)filter_long_list_words(n.cap);
+    hipLaunchKernelGGL(k_filter_long, dim3(grid), dim3(kLongBlock), shl, st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
+                       streams, rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels, lw,
+                       desc_cap);
+    e = hipGetLastError();
+    if (e != hipSuccess || lw.desc == nullptr || lw.cap_next == 0) return e;
+    // the parallel walk: fixed grids, sized by the slot capacity, that read
+    // the counts on the device (nothing to do in most steps)
+    const uint32_t gs = (uint32_t)std::min<uint64_t>((lw.cap_next + 63) / 64, 4096);
+    const uint32_t gd = (uint32_t)std::min<uint64_t>((lw.cap_next + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_long_next, dim3(gs), dim3(64), 0, st, r_pat, r_sl, r_end, r_hk, hks, pats, rules, lw,
+                       desc_cap);
+    e = hipGetLastError();
+    // jump levels alternate between the two other slot arrays; the last one
+    // (2^kChainLevels links) ends in jump[1] (kChainLevels is even)
+    static_assert(kChainLevels % 2 == 0, "the last level must land in jump[1]");
+    const uint32_t *src = lw.next;
+    for (int lv = 0; lv < kChainLevels && e == hipSuccess; ++lv) {
+        uint32_t *dst = lw.jump[lv & 1];
+        hipLaunchKernelGGL(k_long_double, dim3(gd), dim3(256), 0, st, src, dst, lw, desc_cap);
+        e = hipGetLastError();
+        src = dst;
+    }
+    if (e != hipSuccess) return e;
+    // checkpoints into jump[0] (its level is no longer needed), the links
+    // by rank into jump[1] (read by k_long_chain only)
+    hipLaunchKernelGGL(k_long_chain, dim3(grid), dim3(64), 0, st, lw.jump[1], lw.jump[0], lw, desc_cap);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_long_enum, dim3(gs), dim3(64), 0, st, lw.next, lw.jump[0], lw.jump[1], lw, desc_cap);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_long_emit, dim3(gs), dim3(64), sh, st, r_pat, r_sl, r_end, r_hk, hks, pats, rules,
+                       out_stride, seg_out, seg_cnt, lw.jump[1], lw, desc_cap, nlevels);
     return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ using namespace oasm;
 namespace {
 
 constexpr size_t kPad = 64;  // readable slack after every staging buffer
+constexpr uint32_t kLongSlotsMax = 1u << 26;  // per-start slots of the parallel filter walk (3 arrays: 768 MiB)
 
 struct HipFail {
     hipError_t e;
@@ -163,6 +164,9 @@ struct oasm_ctx {
     DevBuf plan, offsets, item_rec, item_cnt, ctl, scan_tmp, sort_key, sort_val, sort_end, sort_tmp;
     DevBuf r_pat, r_sl, r_end, r_flag, r_dist, r_hk, seg_cnt, seg_off, carry_flag, carry_off, long_list;
     DevBuf seg_out, occ_out, raw_in;
+    // the parallel walk of long filter segments: descriptors and one slot per
+    // start (cap_long slots, grown when a step asks for more)
+    DevBuf long_desc, long_next, long_jump[2];
     // Hit ends of filter segments that may still grow, for every stream,
     // resident on the device between steps (double-buffered: read one,
     // write the other).  Order: (step-local stream, pattern, end) of the
@@ -177,6 +181,7 @@ struct oasm_ctx {
     uint32_t cap_n = 1u << 16;  // hit ends per step (carried + new)
     uint32_t cap_occ = 1u << 16;
     uint32_t cap_carry = 1u << 12;
+    uint32_t cap_long = 0;  // per-start slots of the parallel filter walk
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr, ev3 = nullptr;
     hipEvent_t ev_seg = nullptr;  // after the last upload from pin_seg
     bool seg_pending = false;
@@ -440,6 +445,12 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
     c->carry_flag.ensure(n1 * 4, st);
     c->carry_off.ensure(n1 * 4, st);
     c->long_list.ensure(filter_long_list_words((uint32_t)n1) * 4, st);
+    c->long_desc.ensure(filter_long_list_words((uint32_t)n1) * sizeof(LongDesc), st);
+    if (c->cap_long) {
+        c->long_next.ensure((size_t)c->cap_long * 4, st);
+        c->long_jump[0].ensure((size_t)c->cap_long * 4, st);
+        c->long_jump[1].ensure((size_t)c->cap_long * 4, st);
+    }
     c->seg_out.ensure(n1 * out_stride * sizeof(OccRec), st);
     c->occ_out.ensure((uint64_t)cap_occ * sizeof(OccRec), st);
     c->carry_buf[cout].ensure((uint64_t)cap_carry * sizeof(CarryRec), st);
@@ -495,6 +506,15 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
             c->stats.scan_launches++;
         }
     };
+    LongWalk lw;
+    lw.desc = c->long_desc.as<LongDesc>();
+    lw.next = c->cap_long ? c->long_next.as<uint32_t>() : nullptr;
+    lw.jump[0] = c->cap_long ? c->long_jump[0].as<uint32_t>() : nullptr;
+    lw.jump[1] = c->cap_long ? c->long_jump[1].as<uint32_t>() : nullptr;
+    lw.cap_next = c->cap_long;
+    lw.can_grow = c->cap_long < kLongSlotsMax ? 1u : 0u;
+    lw.res = reinterpret_cast<unsigned long long *>(ctl + 10);
+    lw.err = ctl + 5;
     auto part_b = [&]() {
         const DevN items{nullptr, (uint32_t)nitems, (uint32_t)nitems, nullptr, 0u};
         ck(launch_exclusive_scan(c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(), items, ctl + 1,
@@ -530,7 +550,7 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
         ck(launch_filter(c->r_pat.as<uint32_t>(), c->r_sl.as<uint32_t>(), c->r_end.as<uint64_t>(),
                          c->r_hk.as<uint8_t>(), dn, hks, c->d_pats.as<PatDesc>(), d_sdesc, rules, out_stride,
                          c->seg_out.as<OccRec>(), c->seg_cnt.as<uint32_t>(), c->carry_flag.as<uint32_t>(),
-                         c->long_list.as<uint32_t>(), ctl + 6, st),
+                         c->long_list.as<uint32_t>(), ctl + 6, lw, st),
            "filter");
         ck(launch_exclusive_scan(c->seg_cnt.as<uint32_t>(), c->seg_off.as<uint32_t>(), dn, ctl + 2,
                                  c->scan_tmp.as<uint32_t>(), st),
@@ -575,7 +595,9 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
                 (uint64_t)(uintptr_t)c->seg_out.p, (uint64_t)(uintptr_t)c->occ_out.p,
                 (uint64_t)(uintptr_t)c->carry_buf[cin].p, (uint64_t)(uintptr_t)c->carry_buf[cout].p,
                 (uint64_t)(uintptr_t)c->r_hk.p, (uint64_t)(uintptr_t)pin_out.p, (uint64_t)keep_any_raw,
-                (uint64_t)r.keep_h};
+                (uint64_t)r.keep_h, (uint64_t)c->cap_long, (uint64_t)(uintptr_t)c->long_next.p,
+                (uint64_t)(uintptr_t)c->long_jump[0].p, (uint64_t)(uintptr_t)c->long_jump[1].p,
+                (uint64_t)(uintptr_t)c->long_desc.p};
     }
     if (!gkey.empty() && gkey == c->graph_key && c->graph_a) {
         ck(hipEventRecord(c->ev0, st), "event");
@@ -700,11 +722,18 @@ void step_wait(oasm_ctx *c, StepRun &r) {
             c->cap_carry = pow2_at_least(2ull * r.ncarry_out);
             again = true;
         }
+        // long filter segments that did not get their per-start slots
+        const uint64_t long_slots = (uint64_t)h[10] | ((uint64_t)(h[11] & 0xFFu) << 32);
+        if (!again && long_slots > c->cap_long && c->cap_long < kLongSlotsMax) {
+            c->cap_long = (uint32_t)std::min<uint64_t>(kLongSlotsMax, pow2_at_least(long_slots));
+            again = true;
+        }
         if (again) {
             step_enqueue(c, r);
             continue;
         }
         if (h[4]) throw HipFail{hipErrorUnknown, "internal: recovery found no hit-set record at a scan hit end"};
+        if (h[5]) throw HipFail{hipErrorUnknown, "internal: a filter walk emitted more often than its segment has ends"};
         c->stats.word_steps_done += (uint64_t)h[8] | ((uint64_t)h[9] << 32);
         float ms = 0;
         if (hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess) c->stats.scan_ms += ms;
@@ -2081,7 +2110,8 @@ void oasm_destroy(oasm_ctx *c) {
                       &c->d_pat_tile, &c->d_pat_slot, &c->d_tile_wp, &c->plan, &c->offsets, &c->item_rec,
                       &c->item_cnt, &c->ctl, &c->scan_tmp, &c->sort_key, &c->sort_val, &c->sort_end, &c->sort_tmp,
                       &c->r_pat, &c->r_sl, &c->r_end, &c->r_flag, &c->r_dist, &c->r_hk, &c->seg_cnt, &c->seg_off,
-                      &c->carry_flag, &c->carry_off, &c->long_list, &c->seg_out, &c->occ_out, &c->carry_buf[0], &c->carry_buf[1],
+                      &c->carry_flag, &c->carry_off, &c->long_list, &c->long_desc, &c->long_next, &c->long_jump[0], &c->long_jump[1], &c->seg_out,
+                      &c->occ_out, &c->carry_buf[0], &c->carry_buf[1],
                       &c->carry_hk_buf[0], &c->carry_hk_buf[1], &c->raw_in, &c->d_lc_ids, &c->d_lc_unit};
     for (DevBuf *b : bufs) b->release();
     c->pin_plan.release();

@@ -114,11 +114,13 @@ def test_dense_shadow_hits():
 
 @pytest.mark.parametrize("n", [33 * 8 + 5, 70_000])
 def test_long_filter_segments(n):
-    """Segments of more than 32 hit ends are filtered by one wavefront each,
-    from LDS tiles of 256 records: homopolymer text, where three patterns end
-    a hit at every position (one segment per pattern over the whole stream),
-    mixed with a text whose runs of the letter make segments of every length
-    around the tile and hand-over sizes; closed and carried (split feeds)."""
+    """Segments of more than 32 hit ends: up to 255 starts walked by one
+    wavefront each from LDS tiles of 256 records, longer ones split over
+    their starts (next pointers, the chain, its links re-walked at once):
+    homopolymer text, where three patterns end a hit at every position (one
+    segment per pattern over the whole stream), mixed with a text whose runs
+    of the letter make segments of every length around the tile and
+    hand-over sizes; closed and carried (split feeds)."""
     pats = [b"aaaaaaaa", b"aaaa", b"gcaacc", b"acgttgca", b"a" * 40, b"aaagaaa"]
     ks = [2, 1, 2, 2, 8, 3]
     rng = np.random.default_rng(n)
@@ -135,6 +137,44 @@ def test_long_filter_segments(n):
     compare(res, streams, pats, ks, check_h=True, label=f"long-seg{n}")
     res = run(pats, ks, streams, pieces=n)
     compare(res, streams, pats, ks, check_h=True, label=f"long-seg{n}-split")
+
+
+def test_long_segments_in_graph_replays():
+    """Steps of one shape whose filter segments are long enough for the
+    parallel walk (next pointers per start, the chain, its links re-walked
+    at once), captured as HIP graphs and replayed: every step equals an eager
+    run and the oracle; the first step also grows the per-start slots (the
+    step runs again)."""
+    pats = [b"aaaaaaaa", b"aaaa", b"gcaacc", b"a" * 40, b"aaagaaa"]
+    ks = [2, 1, 2, 8, 3]
+    rng = np.random.default_rng(77)
+    pieces = []
+    for i in range(5):
+        t = np.full(20000, ord("a"), dtype=np.uint8)
+        pos = 0
+        while pos < t.size:  # runs of 'a' of 100..3000 symbols
+            pos += int(rng.integers(100, 3000))
+            if pos < t.size:
+                t[pos] = rng.choice(np.frombuffer(b"cgt", np.uint8))
+        pieces.append(t)
+    say("long segments in graph replays")
+    outs = {}
+    for graphs in (False, True):
+        steps = []
+        with oasm.Matcher(pats, ks, graphs=graphs) as mt:
+            for i, t in enumerate(pieces):
+                mt.feed(i, torch.from_numpy(t).cuda(), last=True)
+                mt.sync()
+                steps.append(mt.results())
+            replays = mt.stats()["graph_replays"]
+        outs[graphs] = (steps, replays)
+    assert outs[False][1] == 0 and outs[True][1] >= 2
+    for a, b in zip(outs[False][0], outs[True][0]):
+        assert np.array_equal(a.raw, b.raw) and np.array_equal(a.occ, b.occ)
+    streams = {i: t for i, t in enumerate(pieces)}
+    merged = oasm.Results(np.concatenate([s.raw for s in outs[True][0]]),
+                          np.concatenate([s.occ for s in outs[True][0]]))
+    compare(merged, streams, pats, ks, label="long-graphs")
 
 
 def test_k_zero_and_edge_streams():
