@@ -198,8 +198,9 @@ struct LongWalk {
 };
 
 // K3: the filter, one thread per segment of a (stream, pattern) run of up to
-// 32 hit ends, one wavefront per longer segment, and for a segment with at
-// least kLongParStarts starts the walk split over its starts (three more
+// 32 hit ends, a block per longer segment (its end and carry flags; one
+// wavefront walks a segment of fewer than kLongParStarts starts), and for a
+// longer segment the walk split into links computed in parallel (twelve more
 // launches when cap_next > 0).
 // `rules`: kRule* bits (0 = no filtering, only the open-segment flags).
 // `long_list` holds filter_long_list_words(n.cap) words; `*long_cnt` must be
