@@ -731,10 +731,33 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
     return walk_from<CAND, true, false>(R, i, j1, s0, p, sl, m, K, rules, lv_s, lv_l, lstride, out).cnt;
 }
 
+// The records a block of k_filter can read: its 64 hit ends and the
+// kShortSeg after them (a short segment that starts in the block ends
+// within them, and its end test reads one record past its last).
+constexpr uint32_t kFilterWin = 64 + kShortSeg;
+
+// The same records through the block's window in LDS.
+struct RecsWin {
+    const uint64_t *tend;
+    const uint8_t *thk;
+    uint32_t hks, base;
+    __device__ __forceinline__ void need(uint32_t, uint32_t) {}
+    __device__ __forceinline__ uint64_t e(uint32_t j) const { return tend[j - base]; }
+    __device__ __forceinline__ uint32_t k(uint32_t j, int q) const { return thk[(j - base) * hks + q]; }
+};
+
+size_t filter_lds_bytes(uint32_t nlevels, uint32_t hks) {
+    return (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t)) + kFilterWin * (8 + 4 + 4) +
+           (((size_t)kFilterWin * hks + 7) & ~size_t(7));
+}
+
 // One thread per hit end; the thread that owns the first end of a segment
 // filters it when the segment has at most kShortSeg ends, and otherwise
-// hands it to k_filter_long (appended to `long_list`).  Dynamic LDS: the mem
-// rows of the 64 threads, [level][thread].
+// hands it to k_filter_long (appended to `long_list`).  The block first
+// copies its window of records (pattern, stream, end, hit-set bytes) into
+// LDS with coalesced loads, so that the segment scans and walks, which read
+// one record after another, read LDS.  Dynamic LDS: the mem rows of the 64
+// threads ([level][thread]), then the window.
 __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
                                                const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
                                                DevN dn, uint32_t hks, const PatDesc *__restrict__ pats,
@@ -745,28 +768,46 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
                                                uint32_t nlevels) {
     extern __shared__ uint64_t lds_lv[];
     const bool do_filter = (rules & kRulePaper) != 0;
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t n = dev_n(dn);
+    const uint32_t base = blockIdx.x * 64;
+    if (base >= n) return;  // whole block
+    uint64_t *tend = lds_lv + (size_t)nlevels * 64 + ((size_t)nlevels * 64 * sizeof(uint32_t) + 7) / 8;
+    uint32_t *tpat = reinterpret_cast<uint32_t *>(tend + kFilterWin);
+    uint32_t *tsl = tpat + kFilterWin;
+    uint8_t *thk = reinterpret_cast<uint8_t *>(tsl + kFilterWin);
+    const uint32_t cnt = min(n - base, kFilterWin);
+    for (uint32_t x = threadIdx.x; x < cnt; x += 64) {
+        tend[x] = r_end[base + x];
+        tpat[x] = r_pat[base + x];
+        tsl[x] = r_sl[base + x];
+    }
+    for (uint32_t x = threadIdx.x; x < cnt * hks; x += 64) thk[x] = r_hk[(size_t)base * hks + x];
+    __syncthreads();
+    const uint32_t i = base + threadIdx.x;
     if (i >= n) return;
-    const uint32_t p = r_pat[i], sl = r_sl[i];
-    const uint64_t e0 = r_end[i];
+    const uint32_t w = threadIdx.x;
+    const uint32_t p = tpat[w], sl = tsl[w];
+    const uint64_t e0 = tend[w];
     const PatDesc d = pats[p];
     const int m = d.m, K = d.k;
     const uint64_t gap = (uint64_t)(m + K);
-    const bool start = i == 0 || r_pat[i - 1] != p || r_sl[i - 1] != sl || e0 - r_end[i - 1] >= gap;
+    const bool start = i == 0 || (w > 0 ? (tpat[w - 1] != p || tsl[w - 1] != sl || e0 - tend[w - 1] >= gap)
+                                        : (r_pat[i - 1] != p || r_sl[i - 1] != sl || e0 - r_end[i - 1] >= gap));
     if (!start) {
         seg_cnt[i] = 0;
         return;
     }
-    uint32_t j1 = i + 1;
-    while (j1 < n && j1 - i <= kShortSeg && r_pat[j1] == p && r_sl[j1] == sl && r_end[j1] - r_end[j1 - 1] < gap) ++j1;
-    if (j1 - i > kShortSeg) {  // a long segment: one wavefront walks it
+    uint32_t j1 = i + 1;  // (j1 - base < kFilterWin while the scan runs: j1 <= i + kShortSeg)
+    while (j1 < n && j1 - i <= kShortSeg && tpat[j1 - base] == p && tsl[j1 - base] == sl &&
+           tend[j1 - base] - tend[j1 - 1 - base] < gap)
+        ++j1;
+    if (j1 - i > kShortSeg) {  // a long segment: k_filter_long takes it
         seg_cnt[i] = 0;
         long_list[atomicAdd(long_cnt, 1u)] = i;
         return;
     }
     const StreamDesc sd = streams[sl];
-    const bool open = do_filter && !sd.closed && r_end[j1 - 1] + gap > sd.frontier;
+    const bool open = do_filter && !sd.closed && tend[j1 - 1 - base] + gap > sd.frontier;
     for (uint32_t j = i; j < j1; ++j) carry_flag[j] = open ? 1u : 0u;
     if (open || !do_filter) {
         seg_cnt[i] = 0;
@@ -774,7 +815,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     }
     uint64_t *lv_s = lds_lv + threadIdx.x;
     uint32_t *lv_l = reinterpret_cast<uint32_t *>(lds_lv + (size_t)nlevels * 64) + threadIdx.x;
-    RecsGlobal R{r_end, r_hk, hks};
+    RecsWin R{tend, thk, hks, base};
     seg_cnt[i] = filter_walk<kCandGlobal>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 64, seg_out + (size_t)i * out_stride);
 }
 
@@ -1074,7 +1115,7 @@ hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint
     const uint32_t nlevels = out_stride;  // K_max + 1 levels
     if (nlevels > (uint32_t)kMaxLevels) return hipErrorInvalidValue;
     const size_t sh = (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t));
-    hipLaunchKernelGGL(k_filter, dim3((n.cap + 63) / 64), dim3(64), sh, st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
+    hipLaunchKernelGGL(k_filter, dim3((n.cap + 63) / 64), dim3(64), filter_lds_bytes(nlevels, hks), st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
                        streams, rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
