@@ -1350,36 +1350,58 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__r
     }
 }
 
-// Small counts: the whole exclusive scan in one block of 1024 threads, each
-// summing a run of at most kSmallPer consecutive values.
-constexpr uint32_t kSmallThreads = 1024, kSmallPer = 32, kSmallMax = kSmallThreads * kSmallPer;
+// Small counts (up to kSmallMax): the whole exclusive scan in one block of
+// 1024 threads, in rounds of kSmallRound values: coalesced loads into LDS,
+// each thread's sum of its kSmallPer consecutive values, the block's scan,
+// the values' prefixes written back through LDS (coalesced), and the round's
+// total carried into the next.
+constexpr uint32_t kSmallThreads = 1024, kSmallPer = 8, kSmallRound = kSmallThreads * kSmallPer;
+constexpr uint32_t kSmallMax = 4 * kSmallRound;  // larger arrays take the three-pass scan
+
+// LDS index of value i of a round, padded so that the threads' runs of
+// kSmallPer values start in different banks.
+__device__ __forceinline__ uint32_t small_pad(uint32_t i) { return i + (i >> 5); }
 
 __global__ void __launch_bounds__(kSmallThreads) k_scan_small(const uint32_t *__restrict__ in,
                                                               uint32_t *__restrict__ out, DevN dn,
                                                               uint32_t *__restrict__ total) {
+    __shared__ uint32_t buf[kSmallRound + kSmallRound / 32];
     __shared__ uint32_t wsum[kSmallThreads / kWave];
     const uint32_t n = dev_n(dn);
-    const uint32_t per = (n + kSmallThreads - 1) / kSmallThreads;
-    const uint32_t b = threadIdx.x * per, e = min(n, b + per);
-    uint32_t s = 0;
-    for (uint32_t i = b; i < e; ++i) s += in[i];
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint32_t incl = wave_incl_scan(s);
-    if (lane == kWave - 1) wsum[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-    for (uint32_t w = 0; w < kSmallThreads / kWave; ++w) {
-        const uint32_t x = wsum[w];
-        if (w < wave) before += x;
-        all += x;
+    uint32_t carry = 0;  // the sum of the earlier rounds
+    for (uint32_t r0 = 0; r0 < n; r0 += kSmallRound) {
+        const uint32_t cnt = min(n - r0, kSmallRound);
+        // coalesced loads; each thread then owns kSmallPer consecutive values
+        for (uint32_t i = threadIdx.x; i < kSmallRound; i += kSmallThreads)
+            buf[small_pad(i)] = i < cnt ? in[r0 + i] : 0u;
+        __syncthreads();
+        const uint32_t b = threadIdx.x * kSmallPer;
+        uint32_t s = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kSmallPer; ++k) s += buf[small_pad(b + k)];
+        const uint32_t incl = wave_incl_scan(s);
+        if (lane == kWave - 1) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (uint32_t w = 0; w < kSmallThreads / kWave; ++w) {
+            const uint32_t x = wsum[w];
+            if (w < wave) before += x;
+            all += x;
+        }
+        uint32_t run = carry + before + incl - s;
+#pragma unroll
+        for (uint32_t k = 0; k < kSmallPer; ++k) {
+            const uint32_t v = buf[small_pad(b + k)];
+            buf[small_pad(b + k)] = run;
+            run += v;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cnt; i += kSmallThreads) out[r0 + i] = buf[small_pad(i)];
+        carry += all;
+        __syncthreads();  // buf and wsum are reused by the next round
     }
-    uint32_t run = before + incl - s;
-    for (uint32_t i = b; i < e; ++i) {
-        const uint32_t v = in[i];
-        out[i] = run;
-        run += v;
-    }
-    if (threadIdx.x == 0) *total = all;
+    if (threadIdx.x == 0) *total = carry;
 }
 
 size_t scan_tmp_words(size_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
