@@ -746,18 +746,149 @@ struct RecsWin {
     __device__ __forceinline__ uint32_t k(uint32_t j, int q) const { return thk[(j - base) * hks + q]; }
 };
 
+// Alg. 1 over a short segment (records i .. j1-1 of the block's window) by
+// the whole wavefront, every lane with the same state: at each start, lane t
+// holds the start's t-th candidate (2K + 1 <= 64).  Of a start's candidates
+// in order, those before the first one of priority <= idx change nothing;
+// that one, when of priority idx, is the only one R2 can take (a later one
+// of the same priority ends later than it, or than the stored best it did
+// not replace); and R1 takes exactly the left-to-right minima below idx,
+// found with ballots.  Emissions are Alg. 1's, run by every lane with lane 0
+// writing the records.  The mem rows are the wave's own LDS rows (stride 1).
+__device__ uint32_t wave_walk(const RecsWin &R, uint32_t i, uint32_t j1, uint32_t p, uint32_t sl, int m, int K,
+                              uint32_t rules, uint64_t *lv_s, uint32_t *lv_l, OccRec *out) {
+    const uint32_t lane = threadIdx.x & 63;
+    const bool acc_last = (rules & kRuleAccLast) != 0, eq3_ge = (rules & kRuleEq3Ge) != 0;
+    const bool start_order = (rules & kRuleStartOrder) != 0, disjoint = (rules & kRuleDisjoint) != 0;
+    const uint64_t lmax = (uint64_t)(m + K), lmin = (uint64_t)(m - K < 1 ? 1 : m - K);
+    const int qoff = m - K;
+    if (lane <= (uint32_t)K) lv_l[lane] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    int idx = K;
+    uint64_t bs = 0;
+    uint32_t bl = 0, cnt = 0;
+
+    auto emit = [&](uint64_t pos) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        int64_t acc = 0;
+        uint64_t accepted = 0;
+        for (int j = idx; j <= K; ++j) {
+            const uint32_t lj = lv_l[j];
+            if (lj == 0) continue;
+            const uint64_t sj = lv_s[j];
+            const int64_t r = (int64_t)(pos - sj + 1);  // validation counter r(j)
+            const int64_t l = (int64_t)lj;
+            bool ok = j == idx || (eq3_ge ? r - acc >= l : r - acc > l);  // Eq. 3
+            if (ok && disjoint && j != idx) {
+                const uint64_t je = sj + lj - 1;
+                for (uint64_t mk = accepted; mk; mk &= mk - 1) {
+                    const int q = __builtin_ctzll(mk);
+                    const uint64_t qs = lv_s[q], qe = qs + lv_l[q] - 1;
+                    if (!(je < qs || qe < sj)) ok = false;
+                }
+            }
+            if (ok) {
+                if (lane == 0) {
+                    OccRec o;
+                    o.start_abs = sj;
+                    o.pattern = p;
+                    o.stream_local = sl;
+                    o.len = lj;
+                    o.k = (uint32_t)j;
+                    out[cnt] = o;
+                }
+                ++cnt;
+                acc = acc_last ? l : acc + l;
+                accepted |= 1ull << j;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane >= (uint32_t)idx && lane <= (uint32_t)K) lv_l[lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        idx = K;
+        bl = 0;
+    };
+
+    const uint64_t e0 = R.e(i);
+    uint64_t s = e0 + 1 >= lmax ? e0 + 1 - lmax : 0;
+    uint32_t lo = i;
+    while (true) {
+        // the first record (of at most 32 left) that ends a candidate of s or later
+        {
+            const uint32_t j = lo + lane;
+            const uint64_t b = __ballot(j < j1 && R.e(j) + 1 >= s + lmin);
+            if (!b) break;
+            lo += (uint32_t)__builtin_ctzll(b);
+        }
+        const uint64_t elo = R.e(lo);
+        if (elo + 1 > s + lmax) {  // no hit end reachable from s: jump
+            s = elo + 1 - lmax;
+            continue;
+        }
+        if (bl && bs + bl - 1 < s) emit(bs + bl - 1);
+        // lane t: the candidate ending at record lo + t (255: none, or no hit)
+        uint32_t k = 255u, l = 0;
+        {
+            const uint32_t j = lo + lane;
+            if (j < j1) {
+                const uint64_t e = R.e(j);
+                if (e + 1 <= s + lmax) {
+                    l = (uint32_t)(e + 1 - s);
+                    k = R.k(j, (int)l - qoff);
+                }
+            }
+        }
+        const uint64_t le = __ballot(k <= (uint32_t)idx);
+        if (le) {
+            const int f = __builtin_ctzll(le);
+            const uint32_t kf = __builtin_amdgcn_readlane(k, f), lf = __builtin_amdgcn_readlane(l, f);
+            if ((int)kf == idx && (bl == 0 || (!start_order && (s + lf < bs + bl || (s + lf == bs + bl && lf < bl))))) {
+                bs = s;  // R2 / R3
+                bl = lf;
+                if (lane == 0) {
+                    lv_s[kf] = s;
+                    lv_l[kf] = lf;
+                }
+            }
+            // R1: the left-to-right minima below idx
+            uint64_t below = __ballot(k < (uint32_t)idx);
+            while (below) {
+                const int t = __builtin_ctzll(below);
+                const uint32_t kt = __builtin_amdgcn_readlane(k, t), lt = __builtin_amdgcn_readlane(l, t);
+                idx = (int)kt;
+                bs = s;
+                bl = lt;
+                if (lane == 0) {
+                    lv_s[kt] = s;
+                    lv_l[kt] = lt;
+                }
+                below = __ballot(k < kt) & ~((2ull << t) - 1ull);
+            }
+        }
+        ++s;
+    }
+    if (bl) emit(bs + bl - 1);
+    return cnt;
+}
+
 size_t filter_lds_bytes(uint32_t nlevels, uint32_t hks) {
     return (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t)) + kFilterWin * (8 + 4 + 4) +
-           (((size_t)kFilterWin * hks + 7) & ~size_t(7));
+           (((size_t)kFilterWin * hks + 7) & ~size_t(7)) + (size_t)nlevels * (sizeof(uint64_t) + sizeof(uint32_t));
 }
 
 // One thread per hit end; the thread that owns the first end of a segment
-// filters it when the segment has at most kShortSeg ends, and otherwise
-// hands it to k_filter_long (appended to `long_list`).  The block first
-// copies its window of records (pattern, stream, end, hit-set bytes) into
-// LDS with coalesced loads, so that the segment scans and walks, which read
-// one record after another, read LDS.  Dynamic LDS: the mem rows of the 64
-// threads ([level][thread]), then the window.
+// finds its end and carry flags, and hands a segment of more than kShortSeg
+// ends to k_filter_long (appended to `long_list`).  The block (one
+// wavefront) first copies its window of records (pattern, stream, end,
+// hit-set bytes) into LDS with coalesced loads, so that the scans and walks,
+// which read one record after another, read LDS.  The short segments that
+// need filtering are then walked one after another by the whole wavefront
+// (wave_walk; a segment with 2K + 1 > 64 by its own thread).  Dynamic LDS:
+// the threads' mem rows ([level][thread]), the window, the wave's mem rows.
 __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
                                                const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
                                                DevN dn, uint32_t hks, const PatDesc *__restrict__ pats,
@@ -775,6 +906,8 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     uint32_t *tpat = reinterpret_cast<uint32_t *>(tend + kFilterWin);
     uint32_t *tsl = tpat + kFilterWin;
     uint8_t *thk = reinterpret_cast<uint8_t *>(tsl + kFilterWin);
+    uint64_t *wlv_s = reinterpret_cast<uint64_t *>(thk + (((size_t)kFilterWin * hks + 7) & ~size_t(7)));
+    uint32_t *wlv_l = reinterpret_cast<uint32_t *>(wlv_s + nlevels);
     const uint32_t cnt = min(n - base, kFilterWin);
     for (uint32_t x = threadIdx.x; x < cnt; x += 64) {
         tend[x] = r_end[base + x];
@@ -783,40 +916,55 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     }
     for (uint32_t x = threadIdx.x; x < cnt * hks; x += 64) thk[x] = r_hk[(size_t)base * hks + x];
     __syncthreads();
-    const uint32_t i = base + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t w = threadIdx.x;
-    const uint32_t p = tpat[w], sl = tsl[w];
-    const uint64_t e0 = tend[w];
-    const PatDesc d = pats[p];
-    const int m = d.m, K = d.k;
-    const uint64_t gap = (uint64_t)(m + K);
-    const bool start = i == 0 || (w > 0 ? (tpat[w - 1] != p || tsl[w - 1] != sl || e0 - tend[w - 1] >= gap)
-                                        : (r_pat[i - 1] != p || r_sl[i - 1] != sl || e0 - r_end[i - 1] >= gap));
-    if (!start) {
-        seg_cnt[i] = 0;
-        return;
+    const uint32_t w = threadIdx.x, i = base + w;
+    bool walk = false;
+    uint32_t j1 = i + 1, p = 0, sl = 0;
+    int m = 1, K = 0;
+    if (i < n) {
+        p = tpat[w];
+        sl = tsl[w];
+        const uint64_t e0 = tend[w];
+        const PatDesc d = pats[p];
+        m = d.m;
+        K = d.k;
+        const uint64_t gap = (uint64_t)(m + K);
+        const bool start = i == 0 || (w > 0 ? (tpat[w - 1] != p || tsl[w - 1] != sl || e0 - tend[w - 1] >= gap)
+                                            : (r_pat[i - 1] != p || r_sl[i - 1] != sl || e0 - r_end[i - 1] >= gap));
+        if (!start) {
+            seg_cnt[i] = 0;
+        } else {
+            // (j1 - base < kFilterWin while the scan runs: j1 <= i + kShortSeg)
+            while (j1 < n && j1 - i <= kShortSeg && tpat[j1 - base] == p && tsl[j1 - base] == sl &&
+                   tend[j1 - base] - tend[j1 - 1 - base] < gap)
+                ++j1;
+            if (j1 - i > kShortSeg) {  // a long segment: k_filter_long takes it
+                seg_cnt[i] = 0;
+                long_list[atomicAdd(long_cnt, 1u)] = i;
+            } else {
+                const StreamDesc sd = streams[sl];
+                const bool open = do_filter && !sd.closed && tend[j1 - 1 - base] + gap > sd.frontier;
+                for (uint32_t j = i; j < j1; ++j) carry_flag[j] = open ? 1u : 0u;
+                if (open || !do_filter) seg_cnt[i] = 0;
+                else walk = true;
+            }
+        }
     }
-    uint32_t j1 = i + 1;  // (j1 - base < kFilterWin while the scan runs: j1 <= i + kShortSeg)
-    while (j1 < n && j1 - i <= kShortSeg && tpat[j1 - base] == p && tsl[j1 - base] == sl &&
-           tend[j1 - base] - tend[j1 - 1 - base] < gap)
-        ++j1;
-    if (j1 - i > kShortSeg) {  // a long segment: k_filter_long takes it
-        seg_cnt[i] = 0;
-        long_list[atomicAdd(long_cnt, 1u)] = i;
-        return;
-    }
-    const StreamDesc sd = streams[sl];
-    const bool open = do_filter && !sd.closed && tend[j1 - 1 - base] + gap > sd.frontier;
-    for (uint32_t j = i; j < j1; ++j) carry_flag[j] = open ? 1u : 0u;
-    if (open || !do_filter) {
-        seg_cnt[i] = 0;
-        return;
-    }
-    uint64_t *lv_s = lds_lv + threadIdx.x;
-    uint32_t *lv_l = reinterpret_cast<uint32_t *>(lds_lv + (size_t)nlevels * 64) + threadIdx.x;
     RecsWin R{tend, thk, hks, base};
-    seg_cnt[i] = filter_walk<kCandGlobal>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 64, seg_out + (size_t)i * out_stride);
+    // the wavefront walks its short segments one after another
+    for (uint64_t wm = __ballot(walk && 2 * K + 1 <= 64); wm; wm &= wm - 1) {
+        const int L = __builtin_ctzll(wm);
+        const uint32_t iL = __builtin_amdgcn_readlane(i, L), jL = __builtin_amdgcn_readlane(j1, L);
+        const uint32_t pL = __builtin_amdgcn_readlane(p, L), sL = __builtin_amdgcn_readlane(sl, L);
+        const int mL = (int)__builtin_amdgcn_readlane((uint32_t)m, L), KL = (int)__builtin_amdgcn_readlane((uint32_t)K, L);
+        const uint32_t c = wave_walk(R, iL, jL, pL, sL, mL, KL, rules, wlv_s, wlv_l, seg_out + (size_t)iL * out_stride);
+        if (w == 0) seg_cnt[iL] = c;
+    }
+    if (walk && 2 * K + 1 > 64) {
+        uint64_t *lv_s = lds_lv + threadIdx.x;
+        uint32_t *lv_l = reinterpret_cast<uint32_t *>(lds_lv + (size_t)nlevels * 64) + threadIdx.x;
+        seg_cnt[i] = filter_walk<kCandGlobal>(R, i, j1, p, sl, m, K, rules, lv_s, lv_l, 64,
+                                              seg_out + (size_t)i * out_stride);
+    }
 }
 
 // One block of kLongBlock threads per long segment (grid-stride over the
