@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--no-multiword", action="store_true", help="skip the multiword leg")
     ap.add_argument("--multiword-leg-bytes", type=int, default=1 << 30, help="stream bytes of the multiword leg")
     ap.add_argument("--no-tiny", action="store_true", help="skip the tiny leg")
+    ap.add_argument("--no-worst-case", action="store_true", help="skip the filter worst-case (homopolymer) leg")
     ap.add_argument("--no-autotune", action="store_true", help="heuristic scan variants instead of measured ones")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel of a step instead of graph replay")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-loop measurement")
@@ -581,6 +582,17 @@ def main():
         return
     if args.calibrate_copy:
         copy_calibration()
+    worst = None
+    if args.workload != "homopolymer" and not args.no_worst_case:
+        # the filter's worst case, measured first (so that the main workload's
+        # scans are the last ones a profile of this command sees): a hit end
+        # at every position, each pattern's filter segment spanning the stream
+        wh, dh = make_workload("homopolymer", args)
+        rh = run_steps(oasm, torch, wh, 3, 1, autotune=not args.no_autotune, graphs=not args.no_graphs)
+        mh = summarize(wh, rh, "homopolymer")
+        worst = {"workload": dh, "ms_per_step": round(mh["ms_per_step"], 3),
+                 "device_step_ms": mh["step_breakdown_ms"]["device_step"], "hits": mh["hits"]}
+        del rh, wh
     w, desc = make_workload(args.workload, args)
     r = run_steps(oasm, torch, w, args.steps, args.warmup, chunk=args.chunk, autotune=not args.no_autotune,
                   graphs=not args.no_graphs)
@@ -646,6 +658,8 @@ def main():
         line["tiny"] = {"workload": dt_, "gcups": round(mt_["gcups"], 1), "ms_per_step": round(mt_["ms_per_step"], 3),
                         "scan_ms_per_step": mt_["roofline"]["scan_ms_per_step"], "hits": mt_["hits"]}
         del rt, wt
+    if worst is not None:
+        line["filter_worst_case"] = worst
     if not args.no_levcalc:
         line["levcalc"] = levcalc_legs(oasm, torch, args)
     if not args.no_serving:
