@@ -993,7 +993,12 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n, bool queue = f
     const size_t keep = std::min<size_t>(s.scanned, c->lookback + 4);
     const size_t drop = s.scanned - keep;
     const size_t live = s.valid - drop;
-    if (live + n + kPad <= s.cap) {
+    // While a launched step may still read this buffer (and, should it
+    // overflow a capacity, run again after whatever was queued behind it),
+    // its bytes must stay where the step's plan put them: compact into
+    // another buffer then, and hold this one until the step is booked.
+    const bool in_place = !c->hold_release;
+    if (in_place && live + n + kPad <= s.cap) {
         if (live <= UINT32_MAX) {
             c->moves.push_back(StagingMove{s.sym + drop, s.sym, (uint32_t)live, 0});
             if (!queue) flush_moves(c, c->st);
@@ -1005,7 +1010,7 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n, bool queue = f
         s.scanned -= drop;
         return OASM_OK;
     }
-    const size_t want = std::max(live + n + kPad, s.cap + s.cap / 2);
+    const size_t want = live + n + kPad <= s.cap ? s.cap : std::max(live + n + kPad, s.cap + s.cap / 2);
     size_t cap = 0;
     uint8_t *p = acquire_staging(c, want, cap);
     if (!p) return fail(c, OASM_E_NOMEM, "hipMalloc for stream staging failed");
@@ -1015,7 +1020,10 @@ oasm_status reserve_stream(oasm_ctx *c, StreamState &s, size_t n, bool queue = f
             c->move_release.emplace_back(s.sym, s.cap);  // not reused before the move
         } else {
             if (live) ck(hipMemcpyAsync(p, s.sym + drop, live, hipMemcpyDeviceToDevice, c->st), "staging grow");
-            release_staging(c, s.sym, s.cap);
+            if (c->hold_release)
+                c->held.emplace_back(s.sym, s.cap);  // a launched step may still read it
+            else
+                release_staging(c, s.sym, s.cap);
         }
         s.base_abs += drop;
         s.valid -= drop;

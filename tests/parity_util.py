@@ -63,7 +63,11 @@ def compare(res, streams: dict, patterns, ks, pairs=None, check_h=False, with_fi
         gd = g["dist"].astype(np.int64) if g is not None else np.zeros(0, np.int64)
         assert np.array_equal(ge, w.ends), f"{label} raw ends differ for stream {sid} pattern {pi}: " \
             f"gpu {ge[:10]}... ({ge.size}) oracle {w.ends[:10]}... ({w.ends.size})"
-        assert np.array_equal(gd, w.dists), f"{label} raw distances differ for stream {sid} pattern {pi}"
+        if not np.array_equal(gd, w.dists):
+            bad = np.nonzero(gd != w.dists)[0]
+            raise AssertionError(
+                f"{label} raw distances differ for stream {sid} pattern {pi} at {bad.size} of {gd.size} ends; "
+                f"first: " + ", ".join(f"end {int(ge[b])} gpu {int(gd[b])} oracle {int(w.dists[b])}" for b in bad[:8]))
         n_raw += ge.size
         if with_filter:
             o = occ.get((sid, pi))

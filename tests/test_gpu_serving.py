@@ -122,6 +122,44 @@ def test_serving_full_size_sampled_sessions():
     assert n_raw > 400 and n_occ > 80
 
 
+def test_serving_long_filter_segments():
+    """Sessions whose bytes hold long runs of one letter, with homopolymer
+    patterns: their filter segments are long enough for the parallel walk,
+    whose first use grows its per-start slots (the step runs again) inside
+    the pipelined loop; every session equals the oracle on its bytes."""
+    pats = [b"aaaaaaaa", b"aaaa", b"a" * 30, b"aagaa", b"gcaacc"]
+    ks = [2, 1, 6, 1, 2]
+    rng = np.random.default_rng(31)
+    pool = np.full(1 << 18, ord("a"), dtype=np.uint8)
+    pos = 0
+    while pos < pool.size:  # runs of 'a' of 50..5000 symbols between other letters
+        pos += int(rng.integers(50, 5000))
+        if pos < pool.size:
+            pool[pos] = rng.choice(np.frombuffer(b"cgt", np.uint8))
+    rows = []
+    for sidx in range(8):
+        nseg = int(rng.integers(2, 6))
+        times = np.sort(rng.uniform(0, 0.03, size=nseg))
+        for j, t in enumerate(times):
+            ln = int(rng.integers(500, 8000))
+            off = int(rng.integers(0, pool.size - ln))
+            rows.append((500 + sidx, off, ln, oasm.OASM_FEED_LAST if j == nseg - 1 else 0, float(t)))
+    rows.sort(key=lambda r: r[4])
+    segs = np.array(rows, dtype=oasm.SEG_DTYPE)
+    dpool = torch.from_numpy(pool).cuda()
+    rep, lat, res = serve(pats, ks, dpool, segs)
+    print(f"[serving] long segments: {rep}", file=sys.stderr, flush=True)
+    assert rep["segments"] == segs.size and (lat >= 0).all()
+    sids = sorted(set(int(x) for x in segs["stream"]))
+    streams = {sid: session_bytes(pool, segs, sid) for sid in sids}
+    for sid in sids:  # where each session's segments begin, for a failure's report
+        lens = [int(r["len"]) for r in segs if int(r["stream"]) == sid]
+        print(f"[serving] session {sid}: segments start at {np.cumsum([0] + lens[:-1]).tolist()}",
+              file=sys.stderr, flush=True)
+    n_raw, n_occ = compare(res, streams, pats, ks, label="serving-long-segments")
+    assert n_raw > 10000 and n_occ > 1000
+
+
 def _close_all_and_sync(mt, sids):
     for sid in sids:
         try:
