@@ -160,6 +160,39 @@ def test_serving_long_filter_segments():
     assert n_raw > 10000 and n_occ > 1000
 
 
+def test_serving_budget_graphs_keep_h_dense_text():
+    """Deferred admissions under a tight budget, compactions while steps run,
+    steps that outgrow their capacities (dense hits) and run again, graphs
+    on and the hit set kept: every session's hit ends, H and S equal the
+    oracle's, with the rule variant that keeps the first hit of a priority."""
+    pats = [b"aaaaaa", b"acgtac", b"a" * 20, b"ttgacatt", b"gattaca"]
+    ks = [1, 1, 4, 2, 2]
+    rng = np.random.default_rng(41)
+    pool = np.where(rng.random(1 << 18) < 0.7, ord("a"), rng.choice(np.frombuffer(b"cgt", np.uint8), 1 << 18))
+    pool = pool.astype(np.uint8)
+    rows = []
+    for sidx in range(12):
+        nseg = int(rng.integers(3, 9))
+        times = np.sort(rng.uniform(0, 0.002, size=nseg))  # a burst: the budget defers admissions
+        for j, t in enumerate(times):
+            ln = int(rng.integers(200, 6000))
+            off = int(rng.integers(0, pool.size - ln))
+            rows.append((900 + sidx, off, ln, oasm.OASM_FEED_LAST if j == nseg - 1 else 0, float(t)))
+    rows.sort(key=lambda r: r[4])
+    segs = np.array(rows, dtype=oasm.SEG_DTYPE)
+    dpool = torch.from_numpy(pool).cuda()
+    rules = oasm.OASM_RULES_PAPER | oasm.OASM_RULES_START_ORDER
+    with oasm.Matcher(pats, ks, rules, keep_h=True, graphs=True, mem_budget=120_000) as mt:
+        rep, lat = mt.serve(segs, dpool)
+        res = mt.results()
+    print(f"[serving] budget/graphs/H: {rep}", file=sys.stderr, flush=True)
+    assert rep["segments"] == segs.size and rep["deferred"] > 0 and (lat >= 0).all()
+    sids = sorted(set(int(x) for x in segs["stream"]))
+    streams = {sid: session_bytes(pool, segs, sid) for sid in sids}
+    n_raw, n_occ = compare(res, streams, pats, ks, check_h=True, label="serving-budget-graphs-h", rules=rules)
+    assert n_raw > 20000 and n_occ > 2000
+
+
 def _close_all_and_sync(mt, sids):
     for sid in sids:
         try:
