@@ -974,7 +974,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
 // below, and a shorter one is walked by wavefront 0 alone (every lane with
 // the same values) from an LDS tile.  Dynamic LDS: kTile ends, the mem rows,
 // kTile * hks bytes.
-constexpr uint32_t kLongBlock = 256;
+constexpr uint32_t kLongBlock = 1024;
 
 __global__ void __launch_bounds__(kLongBlock) k_filter_long(const uint32_t *__restrict__ r_pat,
                                                             const uint32_t *__restrict__ r_sl,
