@@ -26,6 +26,10 @@ HIPCC_FLAGS = [
 ]
 
 
+# roctx (trace ranges around the host phases of a step)
+LINK_LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+
+
 def _hipcc() -> str:
     for cand in ("/opt/rocm/bin/hipcc", "hipcc"):
         if os.path.sep not in cand or os.path.exists(cand):
@@ -52,7 +56,7 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc, *HIPCC_FLAGS, "-shared", *objs, "-o", tmp]
+    cmd = [hipcc, *HIPCC_FLAGS, "-shared", *objs, *LINK_LIBS, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")

@@ -403,6 +403,103 @@ hipError_t launch_gather_raw(const uint32_t *skey, const uint32_t *sval, DevN n,
     return hipGetLastError();
 }
 
+// A byte in global memory: a pointer read from a descriptor is otherwise
+// generic, and generic loads make the compiler wait for every load in flight
+// before it uses any of them.
+typedef __attribute__((address_space(1))) const uint8_t global_u8;
+
+// The anchored column of K2 for one hit end, NW 64-bit words per column
+// (NW at least the pattern's own word count W): steps backwards from the
+// hit end over `steps` text symbols, writing each length's distance <= K
+// into hk and returning the least one.  Four symbols per batch; the loads
+// run ahead of the column steps (the text bytes two batches ahead, the
+// masks, which depend on them, one batch ahead, in two register sets used
+// in turn), so that a batch waits only for loads issued a batch earlier.
+// Every load is unconditional: a symbol past the last step re-reads the
+// last one, and a word at or above W re-reads word W - 1.
+template <int NW>
+__device__ __forceinline__ int recover_column(const global_u8 *t, const uint64_t *rp, int W, int m, int K, int steps,
+                                              int lmin, uint8_t *hk) {
+    constexpr int kBatch = 4;
+    uint64_t pv[NW], mv[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int nb = m - 64 * w;
+        pv[w] = nb >= 64 ? ~0ull : (nb <= 0 ? 0ull : ((1ull << nb) - 1));
+        mv[w] = 0;
+    }
+    const int top_w = (m - 1) >> 6, top_b = (m - 1) & 63;
+    int score = m, best = 255;
+    auto load_bytes = [&](int l0, uint32_t (&cb)[kBatch]) {
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) cb[b] = t[-(min(l0 + b, steps) - 1)];
+    };
+    auto load_masks = [&](const uint32_t (&cb)[kBatch], uint64_t (&eq)[kBatch][NW]) {
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b)
+#pragma unroll
+            for (int w = 0; w < NW; ++w) eq[b][w] = rp[(size_t)cb[b] * W + min(w, W - 1)];
+    };
+    auto run_batch = [&](int l0, const uint64_t (&eq)[kBatch][NW]) {
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int l = l0 + b;
+            const bool live = l <= steps;
+            uint64_t ph[NW], mh[NW], xv[NW];
+            uint64_t carry = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint64_t e = eq[b][w];
+                const uint64_t x = e & pv[w];
+                const uint64_t t1 = x + carry;
+                const uint64_t c1 = t1 < carry;
+                const uint64_t u = t1 + pv[w];
+                const uint64_t c2 = u < t1;
+                carry = c1 | c2;
+                const uint64_t xh = (u ^ pv[w]) | e;
+                xv[w] = e | mv[w];
+                ph[w] = mv[w] | ~(xh | pv[w]);
+                mh[w] = pv[w] & xh;
+            }
+            uint64_t pt = ph[0], mt = mh[0];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+                pt = top_w == w ? ph[w] : pt;
+                mt = top_w == w ? mh[w] : mt;
+            }
+            const int ns = score + (int)((pt >> top_b) & 1ull) - (int)((mt >> top_b) & 1ull);
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint64_t ph2 = (ph[w] << 1) | (w == 0 ? 1ull : ph[w - 1] >> 63);
+                const uint64_t mh2 = (mh[w] << 1) | (w == 0 ? 0ull : mh[w - 1] >> 63);
+                const uint64_t npv = mh2 | ~(xv[w] | ph2), nmv = ph2 & xv[w];
+                pv[w] = live ? npv : pv[w];
+                mv[w] = live ? nmv : mv[w];
+            }
+            score = live ? ns : score;
+            if (live && l >= lmin && score <= K) {
+                hk[l - (m - K)] = (uint8_t)score;
+                best = score < best ? score : best;
+            }
+        }
+    };
+    uint32_t cb[kBatch];
+    uint64_t eqa[kBatch][NW], eqb[kBatch][NW];
+    load_bytes(1, cb);
+    load_masks(cb, eqa);
+    load_bytes(1 + kBatch, cb);
+    for (int l0 = 1; l0 <= steps; l0 += 2 * kBatch) {
+        load_masks(cb, eqb);  // batch l0 + kBatch
+        load_bytes(l0 + 2 * kBatch, cb);
+        run_batch(l0, eqa);
+        if (l0 + kBatch > steps) break;
+        load_masks(cb, eqa);  // batch l0 + 2 kBatch
+        load_bytes(l0 + 3 * kBatch, cb);
+        run_batch(l0 + kBatch, eqb);
+    }
+    return best;
+}
+
 // ------------------------------------------------------------------ K2
 // One thread per new hit end e.  The reversed pattern is aligned against
 // t[e], t[e-1], ... with an anchored column recurrence (a +1 horizontal delta
@@ -426,72 +523,23 @@ __global__ void __launch_bounds__(256) k_recover(const uint32_t *__restrict__ r_
     const int lmax = m + K;
     const int lmin = m - K < 1 ? 1 : m - K;
     const int steps = (uint64_t)lmax <= e + 1 ? lmax : (int)(e + 1);
-    const uint8_t *t = sd.sym + (e - sd.base_abs);  // t[0] = symbol at e; walk backwards
+    // t[0] = symbol at e; the column walks backwards
+    const global_u8 *t = (const global_u8 *)(sd.sym + (e - sd.base_abs));
     const uint64_t *rp = rpeq + d.rpeq_off;
     uint8_t *hk = r_hk + (size_t)i * hks;
     for (uint32_t q = 0; q < hks; ++q) hk[q] = kNoHit;
 
-    uint64_t pv[kMaxW64], mv[kMaxW64];
-#pragma unroll
-    for (int w = 0; w < kMaxW64; ++w) {
-        const int lo = 64 * w;
-        const int nb = m - lo;
-        pv[w] = nb >= 64 ? ~0ull : (nb <= 0 ? 0ull : ((1ull << nb) - 1));
-        mv[w] = 0;
-    }
-    const int top_w = (m - 1) >> 6, top_b = (m - 1) & 63;
-    int score = m;
+    // every lane of the wavefront steps as many words as its longest
+    // pattern needs (a lane's words above its own count hold values that
+    // never reach its lower words)
+    uint32_t wm = (uint32_t)W;
+    wm = __ballot(wm >= 4) ? 4u : __ballot(wm >= 3) ? 3u : __ballot(wm >= 2) ? 2u : 1u;
     int best = 255;
-    // four symbols at a time: their text bytes, then their match masks, are
-    // loaded before the four column steps, so the loads overlap instead of
-    // each step waiting for two dependent loads
-    constexpr int kBatch = 4;
-    for (int l0 = 1; l0 <= steps; l0 += kBatch) {
-        uint32_t cb[kBatch];
-        uint64_t eqb[kBatch][kMaxW64];
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) cb[b] = l0 + b <= steps ? t[-(l0 + b - 1)] : 0u;
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b)
-#pragma unroll
-            for (int w = 0; w < kMaxW64; ++w) eqb[b][w] = w < W ? rp[(size_t)cb[b] * W + w] : 0ull;
-#pragma unroll
-        for (int b = 0; b < kBatch; ++b) {
-            const int l = l0 + b;
-            if (l > steps) break;
-            uint64_t ph[kMaxW64], mh[kMaxW64], xv[kMaxW64];
-            uint64_t carry = 0;
-#pragma unroll
-            for (int w = 0; w < kMaxW64; ++w) {
-                if (w < W) {
-                    const uint64_t eq = eqb[b][w];
-                    const uint64_t x = eq & pv[w];
-                    const uint64_t t1 = x + carry;
-                    const uint64_t c1 = t1 < carry;
-                    const uint64_t u = t1 + pv[w];
-                    const uint64_t c2 = u < t1;
-                    carry = c1 | c2;
-                    const uint64_t xh = (u ^ pv[w]) | eq;
-                    xv[w] = eq | mv[w];
-                    ph[w] = mv[w] | ~(xh | pv[w]);
-                    mh[w] = pv[w] & xh;
-                }
-            }
-            score += (int)((ph[top_w] >> top_b) & 1ull) - (int)((mh[top_w] >> top_b) & 1ull);
-#pragma unroll
-            for (int w = 0; w < kMaxW64; ++w) {
-                if (w < W) {
-                    const uint64_t ph2 = (ph[w] << 1) | (w == 0 ? 1ull : ph[w - 1] >> 63);
-                    const uint64_t mh2 = (mh[w] << 1) | (w == 0 ? 0ull : mh[w - 1] >> 63);
-                    pv[w] = mh2 | ~(xv[w] | ph2);
-                    mv[w] = ph2 & xv[w];
-                }
-            }
-            if (l >= lmin && score <= K) {
-                hk[l - (m - K)] = (uint8_t)score;
-                if (score < best) best = score;
-            }
-        }
+    switch (__builtin_amdgcn_readfirstlane(wm)) {
+        case 1: best = recover_column<1>(t, rp, W, m, K, steps, lmin, hk); break;
+        case 2: best = recover_column<2>(t, rp, W, m, K, steps, lmin, hk); break;
+        case 3: best = recover_column<3>(t, rp, W, m, K, steps, lmin, hk); break;
+        default: best = recover_column<4>(t, rp, W, m, K, steps, lmin, hk); break;
     }
     r_dist[i] = (uint8_t)best;
     if (best > K) atomicAdd(err, 1u);  // the scan reported a hit the recovery does not see
@@ -734,7 +782,8 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
 // The records a block of k_filter can read: its 64 hit ends and the
 // kShortSeg after them (a short segment that starts in the block ends
 // within them, and its end test reads one record past its last).
-constexpr uint32_t kFilterWin = 64 + kShortSeg;
+constexpr uint32_t kFilterRecs = 16;  // hit ends owned by one k_filter wavefront
+constexpr uint32_t kFilterWin = kFilterRecs + kShortSeg;
 
 // The same records through the block's window in LDS.
 struct RecsWin {
@@ -880,15 +929,18 @@ size_t filter_lds_bytes(uint32_t nlevels, uint32_t hks) {
            (((size_t)kFilterWin * hks + 7) & ~size_t(7)) + (size_t)nlevels * (sizeof(uint64_t) + sizeof(uint32_t));
 }
 
-// One thread per hit end; the thread that owns the first end of a segment
-// finds its end and carry flags, and hands a segment of more than kShortSeg
-// ends to k_filter_long (appended to `long_list`).  The block (one
-// wavefront) first copies its window of records (pattern, stream, end,
-// hit-set bytes) into LDS with coalesced loads, so that the scans and walks,
-// which read one record after another, read LDS.  The short segments that
-// need filtering are then walked one after another by the whole wavefront
-// (wave_walk; a segment with 2K + 1 > 64 by its own thread).  Dynamic LDS:
-// the threads' mem rows ([level][thread]), the window, the wave's mem rows.
+// A block of one wavefront owns kFilterRecs hit ends, a thread each (few,
+// so that the segments one wavefront walks in turn are few and the blocks
+// many); the thread that owns the first end of a segment finds its end and
+// carry flags, and hands a segment of more than kShortSeg ends to
+// k_filter_long (appended to `long_list`).  The block first copies its
+// window of records (its own and the kShortSeg after them: pattern, stream,
+// end, hit-set bytes) into LDS with coalesced loads, so that the scans and
+// walks, which read one record after another, read LDS.  The short segments
+// that need filtering are then walked one after another by the whole
+// wavefront (wave_walk; a segment with 2K + 1 > 64 by its own thread).
+// Dynamic LDS: the threads' mem rows ([level][thread]), the window, the
+// wave's mem rows.
 __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
                                                const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
                                                DevN dn, uint32_t hks, const PatDesc *__restrict__ pats,
@@ -900,7 +952,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     extern __shared__ uint64_t lds_lv[];
     const bool do_filter = (rules & kRulePaper) != 0;
     const uint32_t n = dev_n(dn);
-    const uint32_t base = blockIdx.x * 64;
+    const uint32_t base = blockIdx.x * kFilterRecs;
     if (base >= n) return;  // whole block
     uint64_t *tend = lds_lv + (size_t)nlevels * 64 + ((size_t)nlevels * 64 * sizeof(uint32_t) + 7) / 8;
     uint32_t *tpat = reinterpret_cast<uint32_t *>(tend + kFilterWin);
@@ -920,7 +972,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     bool walk = false;
     uint32_t j1 = i + 1, p = 0, sl = 0;
     int m = 1, K = 0;
-    if (i < n) {
+    if (w < kFilterRecs && i < n) {
         p = tpat[w];
         sl = tsl[w];
         const uint64_t e0 = tend[w];
@@ -950,7 +1002,8 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
         }
     }
     RecsWin R{tend, thk, hks, base};
-    // the wavefront walks its short segments one after another
+    // the wavefront walks its short segments (at most kFilterRecs) one after
+    // another, the lanes taking a start's candidates
     for (uint64_t wm = __ballot(walk && 2 * K + 1 <= 64); wm; wm &= wm - 1) {
         const int L = __builtin_ctzll(wm);
         const uint32_t iL = __builtin_amdgcn_readlane(i, L), jL = __builtin_amdgcn_readlane(j1, L);
@@ -1263,7 +1316,7 @@ hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint
     const uint32_t nlevels = out_stride;  // K_max + 1 levels
     if (nlevels > (uint32_t)kMaxLevels) return hipErrorInvalidValue;
     const size_t sh = (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t));
-    hipLaunchKernelGGL(k_filter, dim3((n.cap + 63) / 64), dim3(64), filter_lds_bytes(nlevels, hks), st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
+    hipLaunchKernelGGL(k_filter, dim3((n.cap + kFilterRecs - 1) / kFilterRecs), dim3(64), filter_lds_bytes(nlevels, hks), st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
                        streams, rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -33,6 +33,9 @@
 #include "oasm_internal.h"
 #include "oasm_levcalc.h"
 #include "oasm_staging.h"
+#include "oasm_hostpar.h"
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 using namespace oasm;
 
@@ -190,8 +193,8 @@ struct oasm_ctx {
     std::vector<uint64_t> graph_key, graph_prev_key;
 
     // results
-    std::vector<oasm_hit> q_raw;
-    std::vector<oasm_occ> q_occ, q_h;
+    HitQueue q_raw;
+    OccQueue q_occ, q_h;
     size_t rd_raw = 0, rd_occ = 0, rd_h = 0;
 
     oasm_stats stats{};
@@ -364,14 +367,6 @@ void build_plan(oasm_ctx *c, const std::vector<uint32_t> &which_in, StepPlan &pl
     }
 }
 
-// Room for `more` records at the end of a result queue, growing it at least
-// geometrically (an exact reserve would copy the whole queue at every step
-// when the caller drains rarely, as a serving run does).
-template <class T>
-void grow_for(std::vector<T> &q, size_t more) {
-    if (q.size() + more > q.capacity()) q.reserve(std::max(q.size() + more, 2 * q.capacity()));
-}
-
 // ------------------------------------------------------------------ step
 // One matching step, from its launch to its results.  run_step runs the four
 // parts back to back; the serving loop launches the next step before it
@@ -394,10 +389,22 @@ struct StepRun {
 };
 
 // host time since the last mark, excluding device waits, into phase ph
+// A named range in a trace taken with rocprofv3 --marker-trace (roctx);
+// without a tool attached a push or pop is a call that returns at once.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
+// A host phase of a step: its time (less the time spent waiting for the
+// device) goes into the statistics, and it is a named trace range.
 struct PhaseClock {
+    TraceRange range;
     oasm_ctx *c;
     double tmark, twait0;
-    explicit PhaseClock(oasm_ctx *cc) : c(cc), tmark(now_ms()), twait0(cc->stats.wait_ms) {}
+    PhaseClock(oasm_ctx *cc, const char *name) : range(name), c(cc), tmark(now_ms()), twait0(cc->stats.wait_ms) {}
     void operator()(int ph) {
         const double t = now_ms();
         c->stats.host_ms[ph] += (t - tmark) - (c->stats.wait_ms - twait0);
@@ -639,7 +646,7 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
 // upload the plan and queue the launch sequence.  Returns without waiting.
 void step_launch(oasm_ctx *c, const std::vector<uint32_t> &which, StepRun &r, int pin) {
     hipStream_t st = c->st;
-    PhaseClock phase(c);
+    PhaseClock phase(c, "oasm step launch");
     r = StepRun{};
     r.which = which;
     r.pin = pin;
@@ -695,7 +702,7 @@ void step_launch(oasm_ctx *c, const std::vector<uint32_t> &which, StepRun &r, in
 // Wait for the step; when a count exceeded its capacity, grow the capacity
 // and run the step again (synchronously) until everything fits.
 void step_wait(oasm_ctx *c, StepRun &r) {
-    PhaseClock phase(c);
+    PhaseClock phase(c, "oasm step wait");
     for (;;) {
         const double t0 = now_ms();
         ck(hipEventSynchronize(c->ev2), "step sync");
@@ -748,7 +755,7 @@ void step_wait(oasm_ctx *c, StepRun &r) {
 // (its symbols stay in place until reserve_stream needs the room), and a
 // stream that ended is released.
 void step_bookkeep(oasm_ctx *c, StepRun &r) {
-    PhaseClock phase(c);
+    PhaseClock phase(c, "oasm step bookkeep");
     hipStream_t st = c->st;
     c->hold_release = false;
     for (auto &h : c->held) release_staging(c, h.first, h.second);
@@ -796,7 +803,7 @@ void step_bookkeep(oasm_ctx *c, StepRun &r) {
 
 // The step's results (in its mapped pinned buffer) into the drain queues.
 void step_convert(oasm_ctx *c, StepRun &r) {
-    PhaseClock phase(c);
+    PhaseClock phase(c, "oasm step convert");
     const uint32_t n = r.ncarry + r.n_new;
     uint8_t *hp = c->pin_out[r.pin].as<uint8_t>();
     const PackArgs &ly = r.layout;
@@ -807,28 +814,24 @@ void step_convert(oasm_ctx *c, StepRun &r) {
     const uint8_t *hdist = hp + ly.o_dist;
     const uint8_t *hhk = hp + ly.o_hk;
     const uint32_t hks = c->hks;
-    if (r.keep_raw || r.keep_h) {
-        if (r.keep_raw) grow_for(c->q_raw, r.n_new);
+    // (a record with its flag set was carried from an earlier step and
+    // reported there)
+    if (r.keep_raw) convert_raw(hflag, hsl, hend, hpat, hdist, r.ids.data(), n, c->q_raw);
+    if (r.keep_h) {
         for (uint32_t i = 0; i < n; ++i) {
-            if (hflag[i]) continue;  // carried from an earlier step: reported there
+            if (hflag[i]) continue;
             const uint64_t sid = r.ids[hsl[i]];
-            if (r.keep_raw) c->q_raw.push_back(oasm_hit{sid, hend[i], hpat[i], hdist[i]});
-            if (r.keep_h) {
-                const uint32_t p = hpat[i];
-                const int m = c->m[p], K = c->k[p];
-                for (int l = std::max(1, m - K); l <= m + K; ++l) {
-                    const uint8_t kk = hhk[(size_t)i * hks + (l - (m - K))];
-                    if (kk == kNoHit) continue;
-                    c->q_h.push_back(oasm_occ{sid, hend[i] + 1 - (uint64_t)l, p, (uint32_t)l, kk, 0});
-                    c->stats.h_records++;
-                }
+            const uint32_t p = hpat[i];
+            const int m = c->m[p], K = c->k[p];
+            for (int l = std::max(1, m - K); l <= m + K; ++l) {
+                const uint8_t kk = hhk[(size_t)i * hks + (l - (m - K))];
+                if (kk == kNoHit) continue;
+                c->q_h.push_back(oasm_occ{sid, hend[i] + 1 - (uint64_t)l, p, (uint32_t)l, kk, 0});
+                c->stats.h_records++;
             }
         }
     }
-    const OccRec *ho = reinterpret_cast<const OccRec *>(hp + ly.o_occ);
-    grow_for(c->q_occ, r.nocc);
-    for (uint32_t i = 0; i < r.nocc; ++i)
-        c->q_occ.push_back(oasm_occ{r.ids[ho[i].stream_local], ho[i].start_abs, ho[i].pattern, ho[i].len, ho[i].k, 0});
+    convert_occ(reinterpret_cast<const OccRec *>(hp + ly.o_occ), r.ids.data(), r.nocc, c->q_occ);
     r.active = false;
     phase(2);
 }
@@ -1713,6 +1716,7 @@ oasm_status oasm_sync(oasm_ctx *c) {
     if (!c) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
     if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
+    TraceRange range("oasm_sync");
     const double t0 = now_ms();
     try {
         ck(hipSetDevice(c->device), "hipSetDevice");
@@ -1732,6 +1736,7 @@ oasm_status oasm_serve(oasm_ctx *c, const oasm_segment *segs, size_t n, const vo
     if (report) *report = oasm_serve_report{};
     if (!c || (n > 0 && (!segs || !dev_pool))) return OASM_E_INVAL;
     std::lock_guard<std::mutex> g(c->mu);
+    TraceRange range("oasm_serve");
     if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
     for (size_t i = 0; i < n; ++i) {
         if (segs[i].offset > pool_bytes || segs[i].len > pool_bytes - segs[i].offset)
@@ -1958,7 +1963,7 @@ oasm_status oasm_hits(oasm_ctx *c, uint32_t kind, void *out, size_t cap, size_t 
     if (kind == OASM_RAW) {
         const size_t avail = c->q_raw.size() - c->rd_raw;
         const size_t take = std::min(avail, cap);
-        if (take) std::memcpy(out, c->q_raw.data() + c->rd_raw, take * sizeof(oasm_hit));
+        if (take) parallel_copy(out, c->q_raw.data() + c->rd_raw, take * sizeof(oasm_hit));
         c->rd_raw += take;
         *n_out = take;
         if (more) *more = avail > take;
@@ -1969,13 +1974,13 @@ oasm_status oasm_hits(oasm_ctx *c, uint32_t kind, void *out, size_t cap, size_t 
         return OASM_OK;
     }
     if (kind == OASM_FILTERED || kind == OASM_H) {
-        std::vector<oasm_occ> &q = kind == OASM_FILTERED ? c->q_occ : c->q_h;
+        OccQueue &q = kind == OASM_FILTERED ? c->q_occ : c->q_h;
         size_t &rd = kind == OASM_FILTERED ? c->rd_occ : c->rd_h;
         if (kind == OASM_H && !(c->cfg.flags & OASM_CFG_KEEP_H))
             return fail(c, OASM_E_INVAL, "OASM_H needs OASM_CFG_KEEP_H");
         const size_t avail = q.size() - rd;
         const size_t take = std::min(avail, cap);
-        if (take) std::memcpy(out, q.data() + rd, take * sizeof(oasm_occ));
+        if (take) parallel_copy(out, q.data() + rd, take * sizeof(oasm_occ));
         rd += take;
         *n_out = take;
         if (more) *more = avail > take;
@@ -2013,6 +2018,7 @@ oasm_status oasm_levcalc(oasm_ctx *c, const void *dev_text, size_t n, void *dev_
     if (oasm_levcalc_size(c, n, &need) != OASM_OK) return fail(c, OASM_E_INVAL, "output size overflows size_t");
     if (out_bytes < need) return fail(c, OASM_E_INVAL, "output buffer too small for n * sum(2K + 1) bytes");
     if (n == 0) return OASM_OK;
+    TraceRange range("oasm_levcalc");
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     try {
         ck(hipSetDevice(c->device), "hipSetDevice");
@@ -2071,6 +2077,7 @@ oasm_status oasm_levcalc_noalloc(oasm_ctx *c, const void *dev_text, size_t n, vo
     if (oasm_levcalc_size(c, n, &need) != OASM_OK) return fail(c, OASM_E_INVAL, "output size overflows size_t");
     if (out_bytes < need) return fail(c, OASM_E_INVAL, "output buffer too small for n * sum(2K + 1) bytes");
     if (n == 0) return OASM_OK;
+    TraceRange range("oasm_levcalc");
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     try {
         ck(hipSetDevice(c->device), "hipSetDevice");

@@ -19,5 +19,5 @@ done
 "$HIPCC" "${FLAGS[@]}" -c "$ROOT/tests/native/runtime_asan_driver.cpp" -o "$TMP/driver.o" 2> "$TMP/driver.err" & pids+=($!)
 for p in "${pids[@]}"; do wait "$p"; done
 "$HIPCC" --offload-arch=gfx950 -Xarch_host -fsanitize=address -Xarch_host -fsanitize=undefined \
-    "$TMP"/*.o -o "$OUT"
+    "$TMP"/*.o -L/opt/rocm/lib -lrocprofiler-sdk-roctx -Wl,-rpath,/opt/rocm/lib -o "$OUT"
 echo "$OUT"
