@@ -275,6 +275,42 @@ oasm_status oasm_close_stream(oasm_ctx *ctx, uint64_t stream_id);
 oasm_status oasm_sync(oasm_ctx *ctx);
 
 /*
+ * Checkpoint and resume of one stream.  A stream's whole matching state
+ * between feeds is small: the scan restarts exactly from the m_max + K_max
+ * - 1 symbols before the matched frontier (the bit-parallel column of
+ * Section 5.1 depends on no earlier symbol once that many have been read),
+ * and Alg. 1's state is empty between segments (Section 4), so the only
+ * filter state is the hit ends of the segments still open at the frontier.
+ *
+ * oasm_stream_export first matches every byte fed so far, as oasm_sync does
+ * (queueing the results it completes), then writes the stream's state into
+ * `buf`: a self-describing little-endian record of OASM_CKPT_MAGIC,
+ * OASM_CKPT_VERSION, a fingerprint of the dictionary, thresholds, rules and
+ * symbol classes, the absolute number of bytes matched, the look-back
+ * symbols (as the context's symbol classes) and the carried hit ends (end,
+ * pattern, least distance and hit-set bytes each).  *size always receives
+ * the record's size; with buf NULL nothing else is written (a size query).
+ * The stream stays live in `ctx`.  Errors: OASM_E_INVAL (ctx or size NULL,
+ * an unknown stream, a stream with a close pending, cap below the size),
+ * OASM_E_CLOSED (a closed stream), and those of oasm_sync.
+ *
+ * oasm_stream_import makes `stream_id` a live stream of `ctx` that holds the
+ * exported state: the next bytes fed to it continue the exported stream at
+ * the exported position, and its results (positions absolute, from the
+ * exported stream's first byte) are those the exported stream would have
+ * reported for the same bytes; what the export's context had reported stays
+ * reported there.  `ctx` must be built from the same dictionary, thresholds
+ * and rules.  The caller owns `buf` (read only during the call).  Errors:
+ * OASM_E_INVAL (NULL arguments, a record that is truncated, of another
+ * version or of another dictionary, inconsistent fields, a stream id live or
+ * closed in `ctx`), OASM_E_NOMEM, OASM_E_DEVICE.
+ */
+#define OASM_CKPT_MAGIC 0x4D53414Fu /* "OASM" */
+#define OASM_CKPT_VERSION 1u
+oasm_status oasm_stream_export(oasm_ctx *ctx, uint64_t stream_id, void *buf, size_t cap, size_t *size);
+oasm_status oasm_stream_import(oasm_ctx *ctx, uint64_t stream_id, const void *buf, size_t size);
+
+/*
  * Copy up to `cap` queued records of `kind` into `out` (an array of
  * oasm_hit for OASM_RAW, of oasm_occ otherwise) and remove them from the
  * queue.  *n_out receives the number copied; *more (may be NULL) is set to 1

@@ -782,8 +782,11 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
 // The records a block of k_filter can read: its 64 hit ends and the
 // kShortSeg after them (a short segment that starts in the block ends
 // within them, and its end test reads one record past its last).
-constexpr uint32_t kFilterRecs = 16;  // hit ends owned by one k_filter wavefront
-constexpr uint32_t kFilterWin = kFilterRecs + kShortSeg;
+// hit ends owned by one k_filter wavefront: few while the step's records
+// fill the chip with room to spare, more when there are millions of them
+// (each block stages its own and the kShortSeg after them)
+constexpr uint32_t kFilterRecsFew = 16, kFilterRecsMany = 64;
+constexpr uint32_t kFilterManyCap = 1u << 19;  // record capacities above this use kFilterRecsMany
 
 // The same records through the block's window in LDS.
 struct RecsWin {
@@ -924,14 +927,15 @@ __device__ uint32_t wave_walk(const RecsWin &R, uint32_t i, uint32_t j1, uint32_
     return cnt;
 }
 
-size_t filter_lds_bytes(uint32_t nlevels, uint32_t hks) {
-    return (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t)) + kFilterWin * (8 + 4 + 4) +
-           (((size_t)kFilterWin * hks + 7) & ~size_t(7)) + (size_t)nlevels * (sizeof(uint64_t) + sizeof(uint32_t));
+size_t filter_lds_bytes(uint32_t nlevels, uint32_t hks, uint32_t recs) {
+    const size_t win = recs + kShortSeg;
+    return (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t)) + win * (8 + 4 + 4) +
+           ((win * hks + 7) & ~size_t(7)) + (size_t)nlevels * (sizeof(uint64_t) + sizeof(uint32_t));
 }
 
-// A block of one wavefront owns kFilterRecs hit ends, a thread each (few,
-// so that the segments one wavefront walks in turn are few and the blocks
-// many); the thread that owns the first end of a segment finds its end and
+// A block of one wavefront owns RECS hit ends, a thread each (few, so that
+// the segments one wavefront walks in turn are few and the blocks many,
+// unless the step has millions of records); the thread that owns the first end of a segment finds its end and
 // carry flags, and hands a segment of more than kShortSeg ends to
 // k_filter_long (appended to `long_list`).  The block first copies its
 // window of records (its own and the kShortSeg after them: pattern, stream,
@@ -941,6 +945,7 @@ size_t filter_lds_bytes(uint32_t nlevels, uint32_t hks) {
 // wavefront (wave_walk; a segment with 2K + 1 > 64 by its own thread).
 // Dynamic LDS: the threads' mem rows ([level][thread]), the window, the
 // wave's mem rows.
+template <uint32_t RECS>
 __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pat, const uint32_t *__restrict__ r_sl,
                                                const uint64_t *__restrict__ r_end, const uint8_t *__restrict__ r_hk,
                                                DevN dn, uint32_t hks, const PatDesc *__restrict__ pats,
@@ -952,7 +957,8 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     extern __shared__ uint64_t lds_lv[];
     const bool do_filter = (rules & kRulePaper) != 0;
     const uint32_t n = dev_n(dn);
-    const uint32_t base = blockIdx.x * kFilterRecs;
+    constexpr uint32_t kFilterWin = RECS + kShortSeg;
+    const uint32_t base = blockIdx.x * RECS;
     if (base >= n) return;  // whole block
     uint64_t *tend = lds_lv + (size_t)nlevels * 64 + ((size_t)nlevels * 64 * sizeof(uint32_t) + 7) / 8;
     uint32_t *tpat = reinterpret_cast<uint32_t *>(tend + kFilterWin);
@@ -972,7 +978,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
     bool walk = false;
     uint32_t j1 = i + 1, p = 0, sl = 0;
     int m = 1, K = 0;
-    if (w < kFilterRecs && i < n) {
+    if (w < RECS && i < n) {
         p = tpat[w];
         sl = tsl[w];
         const uint64_t e0 = tend[w];
@@ -1002,7 +1008,7 @@ __global__ void __launch_bounds__(64) k_filter(const uint32_t *__restrict__ r_pa
         }
     }
     RecsWin R{tend, thk, hks, base};
-    // the wavefront walks its short segments (at most kFilterRecs) one after
+    // the wavefront walks its short segments (at most RECS) one after
     // another, the lanes taking a start's candidates
     for (uint64_t wm = __ballot(walk && 2 * K + 1 <= 64); wm; wm &= wm - 1) {
         const int L = __builtin_ctzll(wm);
@@ -1316,8 +1322,15 @@ hipError_t launch_filter(const uint32_t *r_pat, const uint32_t *r_sl, const uint
     const uint32_t nlevels = out_stride;  // K_max + 1 levels
     if (nlevels > (uint32_t)kMaxLevels) return hipErrorInvalidValue;
     const size_t sh = (size_t)nlevels * 64 * (sizeof(uint64_t) + sizeof(uint32_t));
-    hipLaunchKernelGGL(k_filter, dim3((n.cap + kFilterRecs - 1) / kFilterRecs), dim3(64), filter_lds_bytes(nlevels, hks), st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
-                       streams, rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
+    if (n.cap > kFilterManyCap) {
+        hipLaunchKernelGGL(k_filter<kFilterRecsMany>, dim3((n.cap + kFilterRecsMany - 1) / kFilterRecsMany), dim3(64),
+                           filter_lds_bytes(nlevels, hks, kFilterRecsMany), st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
+                           streams, rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
+    } else {
+        hipLaunchKernelGGL(k_filter<kFilterRecsFew>, dim3((n.cap + kFilterRecsFew - 1) / kFilterRecsFew), dim3(64),
+                           filter_lds_bytes(nlevels, hks, kFilterRecsFew), st, r_pat, r_sl, r_end, r_hk, n, hks, pats,
+                           streams, rules, out_stride, seg_out, seg_cnt, carry_flag, long_list, long_cnt, nlevels);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // at most one long segment per kShortSeg + 1 hit ends; a fixed grid that

@@ -73,7 +73,7 @@ struct DevBuf {
         cap = want;
     }
     void release() {
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
         p = nullptr;
         cap = 0;
     }
@@ -99,7 +99,7 @@ struct PinBuf {
         cap = want;
     }
     void release() {
-        if (p) hipHostFree(p);
+        if (p) (void)hipHostFree(p);
         p = nullptr;
         cap = 0;
     }
@@ -144,6 +144,7 @@ struct oasm_ctx {
     std::vector<uint16_t> m, k;
     uint32_t mmax = 0, kmax = 0, hks = 1, lookback = 0, nclass = 1;
     uint8_t class_of[256];
+    uint64_t dict_fp = 0;  // dictionary, thresholds, rules and classes (checkpoints)
     uint64_t msum = 0;   // sum of pattern lengths (cells per byte)
     uint64_t wsum = 0;   // sum of 32-bit words (word-steps per byte)
     std::vector<ClassInfo> classes;
@@ -1413,6 +1414,26 @@ const char *oasm_status_str(oasm_status s) {
 
 static thread_local std::string g_create_error;
 
+// FNV-1a over everything a stream's matching state depends on besides its
+// own bytes: rules, pattern count, each pattern's length, threshold and
+// bytes, and the symbol classes.
+static uint64_t dictionary_fingerprint(const oasm_ctx *c, const std::vector<uint8_t> &bytes) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&h](const void *p, size_t n) {
+        const uint8_t *b = static_cast<const uint8_t *>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
+    };
+    mix(&c->rules, sizeof c->rules);
+    mix(&c->npat, sizeof c->npat);
+    for (uint32_t i = 0; i < c->npat; ++i) {
+        mix(&c->m[i], sizeof c->m[i]);
+        mix(&c->k[i], sizeof c->k[i]);
+    }
+    mix(bytes.data(), bytes.size());
+    mix(c->class_of, sizeof c->class_of);
+    return h;
+}
+
 oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k, uint16_t k_all, uint32_t rules,
                         const oasm_config *cfg, oasm_ctx **out) {
     if (!out) return OASM_E_INVAL;
@@ -1505,6 +1526,7 @@ oasm_status oasm_create(const oasm_pattern *dict, uint32_t n, const uint16_t *k,
         }
         c->hks = 2 * c->kmax + 1;
         c->lookback = c->mmax + c->kmax - 1;
+        c->dict_fp = dictionary_fingerprint(c, bytes);
 
         c->h_patbytes = bytes;
         c->h_pd = pd;
@@ -1709,6 +1731,174 @@ oasm_status oasm_close_stream(oasm_ctx *c, uint64_t stream_id) {
     StreamState &s = c->streams[it->second];
     if (s.closed || s.close_pending) return fail(c, OASM_E_INVAL, "stream already closed");
     s.close_pending = true;
+    return OASM_OK;
+}
+
+// ------------------------------------------------------------------ checkpoint
+// Record layout (little-endian): CkptHeader, nsym look-back symbols (symbol
+// classes), ncarry CkptCarry, then ncarry * hks hit-set bytes.
+namespace {
+struct CkptHeader {
+    uint32_t magic, version;
+    uint64_t dict_fp;
+    uint64_t position;  // absolute symbols matched
+    uint32_t nsym;      // look-back symbols that follow
+    uint32_t ncarry;    // carried hit ends that follow
+    uint32_t hks;       // hit-set bytes per carried hit end
+    uint32_t reserved;
+};
+struct CkptCarry {
+    uint64_t end_abs;
+    uint32_t pattern;
+    uint32_t dist;
+};
+static_assert(sizeof(CkptHeader) == 40 && sizeof(CkptCarry) == 16, "checkpoint layout");
+
+size_t ckpt_size(uint64_t nsym, uint64_t ncarry, uint64_t hks) {
+    return sizeof(CkptHeader) + nsym + ncarry * (sizeof(CkptCarry) + hks);
+}
+
+// The context's carried hit ends (records and hit-set bytes) on the host;
+// the caller has no step in flight.
+void carry_to_host(oasm_ctx *c, std::vector<CarryRec> &rec, std::vector<uint8_t> &hk) {
+    rec.resize(c->ncarry);
+    hk.resize((size_t)c->ncarry * c->hks);
+    if (!c->ncarry) return;
+    ck(hipMemcpyAsync(rec.data(), c->carry_buf[c->carry_cur].p, rec.size() * sizeof(CarryRec),
+                      hipMemcpyDeviceToHost, c->st),
+       "carry download");
+    ck(hipMemcpyAsync(hk.data(), c->carry_hk_buf[c->carry_cur].p, hk.size(), hipMemcpyDeviceToHost, c->st),
+       "carry download");
+    ck(hipStreamSynchronize(c->st), "carry download");
+}
+}  // namespace
+
+oasm_status oasm_stream_export(oasm_ctx *c, uint64_t stream_id, void *buf, size_t cap, size_t *size) {
+    if (!c || !size) return OASM_E_INVAL;
+    *size = 0;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
+    if (is_finished(c, stream_id)) return fail(c, OASM_E_CLOSED, "export of a closed stream");
+    auto it = c->slot_of.find(stream_id);
+    if (it == c->slot_of.end()) return fail(c, OASM_E_INVAL, "export of an unknown stream");
+    if (c->streams[it->second].close_pending) return fail(c, OASM_E_INVAL, "export of a stream with a close pending");
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        sync_all(c);  // every byte fed is matched (the stream stays live: no close was pending)
+        const StreamState &s = c->streams[c->slot_of.at(stream_id)];
+        const uint32_t nsym = (uint32_t)std::min<uint64_t>(s.scanned, c->lookback + 4);
+        const uint32_t n = s.ncarry;
+        const size_t need = ckpt_size(nsym, n, c->hks);
+        *size = need;
+        if (!buf) return OASM_OK;
+        if (cap < need) return fail(c, OASM_E_INVAL, "buffer smaller than the checkpoint");
+        std::vector<CarryRec> rec;
+        std::vector<uint8_t> hk;
+        if (n) carry_to_host(c, rec, hk);
+        uint8_t *o = static_cast<uint8_t *>(buf);
+        const CkptHeader h{OASM_CKPT_MAGIC, OASM_CKPT_VERSION, c->dict_fp, s.base_abs + s.scanned, nsym, n, c->hks, 0};
+        std::memcpy(o, &h, sizeof h);
+        if (nsym) {
+            ck(hipMemcpyAsync(o + sizeof h, s.sym + (s.scanned - nsym), nsym, hipMemcpyDeviceToHost, c->st),
+               "look-back download");
+            ck(hipStreamSynchronize(c->st), "look-back download");
+        }
+        uint8_t *oc = o + sizeof h + nsym, *ohk = oc + (size_t)n * sizeof(CkptCarry);
+        uint32_t w = 0;
+        for (uint32_t i = 0; i < c->ncarry && w < n; ++i) {
+            if (rec[i].stream_slot != s.slot) continue;
+            const CkptCarry cr{rec[i].end_abs, rec[i].pattern, rec[i].dist};
+            std::memcpy(oc + (size_t)w * sizeof cr, &cr, sizeof cr);
+            std::memcpy(ohk + (size_t)w * c->hks, hk.data() + (size_t)i * c->hks, c->hks);
+            ++w;
+        }
+        if (w != n) throw HipFail{hipErrorUnknown, "internal: the stream's carried hit ends are not in the carry"};
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
+    } catch (const std::bad_alloc &) {
+        return step_alloc_fail(c);
+    }
+    return OASM_OK;
+}
+
+oasm_status oasm_stream_import(oasm_ctx *c, uint64_t stream_id, const void *buf, size_t size) {
+    if (!c) return OASM_E_INVAL;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (c->poisoned) return fail(c, OASM_E_DEVICE, "context is poisoned by an earlier error");
+    if (!buf) return fail(c, OASM_E_INVAL, "NULL checkpoint");
+    if (size < sizeof(CkptHeader)) return fail(c, OASM_E_INVAL, "checkpoint truncated");
+    CkptHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    if (h.magic != OASM_CKPT_MAGIC || h.version != OASM_CKPT_VERSION)
+        return fail(c, OASM_E_INVAL, "not a stream checkpoint of this version");
+    if (h.dict_fp != c->dict_fp || h.hks != c->hks)
+        return fail(c, OASM_E_INVAL, "checkpoint of another dictionary, thresholds or rules");
+    if (h.reserved || h.nsym > c->lookback + 4 || h.nsym > h.position)
+        return fail(c, OASM_E_INVAL, "inconsistent checkpoint header");
+    if (size != ckpt_size(h.nsym, h.ncarry, h.hks)) return fail(c, OASM_E_INVAL, "checkpoint size does not match");
+    const uint8_t *sym = static_cast<const uint8_t *>(buf) + sizeof h;
+    const uint8_t *cb = sym + h.nsym, *hkb = cb + (size_t)h.ncarry * sizeof(CkptCarry);
+    for (uint32_t i = 0; i < h.nsym; ++i)
+        if (sym[i] >= c->nclass) return fail(c, OASM_E_INVAL, "checkpoint symbol outside the classes");
+    std::vector<CkptCarry> cr(h.ncarry);
+    if (h.ncarry) std::memcpy(cr.data(), cb, cr.size() * sizeof(CkptCarry));
+    {
+        // within a pattern the ends increase (the order the filter walks them)
+        std::vector<uint64_t> next_min(h.ncarry ? c->npat : 0, 0);
+        for (uint32_t i = 0; i < h.ncarry; ++i) {
+            if (cr[i].pattern >= c->npat || cr[i].end_abs >= h.position || cr[i].dist > c->k[cr[i].pattern])
+                return fail(c, OASM_E_INVAL, "checkpoint hit end out of range");
+            if (cr[i].end_abs < next_min[cr[i].pattern])
+                return fail(c, OASM_E_INVAL, "checkpoint hit ends out of order");
+            next_min[cr[i].pattern] = cr[i].end_abs + 1;
+        }
+    }
+    if (is_finished(c, stream_id) || c->slot_of.count(stream_id))
+        return fail(c, OASM_E_INVAL, "stream id already live or closed in this context");
+    StreamState *sp = nullptr;
+    try {
+        ck(hipSetDevice(c->device), "hipSetDevice");
+        ck(hipStreamSynchronize(c->st), "import sync");  // nothing reads the carry or a staging buffer now
+        std::vector<CarryRec> rec;
+        std::vector<uint8_t> hk;
+        if (h.ncarry) carry_to_host(c, rec, hk);
+        sp = &get_stream(c, stream_id, true);
+        StreamState &s = *sp;
+        if (h.nsym) {
+            const oasm_status r = reserve_stream(c, s, h.nsym);
+            if (r != OASM_OK) throw std::bad_alloc();
+            ck(hipMemcpyAsync(s.sym, sym, h.nsym, hipMemcpyHostToDevice, c->st), "look-back upload");
+        }
+        s.base_abs = h.position - h.nsym;
+        s.valid = s.scanned = h.nsym;
+        if (h.ncarry) {
+            for (uint32_t i = 0; i < h.ncarry; ++i)
+                rec.push_back(CarryRec{cr[i].end_abs, cr[i].pattern, s.slot, cr[i].dist, 0});
+            hk.insert(hk.end(), hkb, hkb + (size_t)h.ncarry * c->hks);
+            const int cur = c->carry_cur;
+            c->carry_buf[cur].ensure(rec.size() * sizeof(CarryRec), c->st);
+            c->carry_hk_buf[cur].ensure(hk.size(), c->st);
+            ck(hipMemcpyAsync(c->carry_buf[cur].p, rec.data(), rec.size() * sizeof(CarryRec), hipMemcpyHostToDevice,
+                              c->st),
+               "carry upload");
+            ck(hipMemcpyAsync(c->carry_hk_buf[cur].p, hk.data(), hk.size(), hipMemcpyHostToDevice, c->st),
+               "carry upload");
+            c->ncarry = (uint32_t)rec.size();
+            s.ncarry = h.ncarry;
+        }
+        ck(hipStreamSynchronize(c->st), "import sync");
+    } catch (const HipFail &f) {
+        return device_fail(c, f);
+    } catch (const std::bad_alloc &) {
+        if (sp && sp->ncarry == 0) {  // nothing of the stream reached the carry: take it back out
+            c->staged_bytes -= sp->cap;
+            release_staging(c, sp->sym, sp->cap);
+            c->slot_of.erase(stream_id);
+            c->free_slots.push_back(sp->slot);
+            *sp = StreamState{};
+        }
+        return fail(c, OASM_E_NOMEM, "allocation failed during import");
+    }
     return OASM_OK;
 }
 

@@ -48,6 +48,9 @@ OASM_MAX_CHUNK_BYTES = 1 << 24
 OASM_NOALLOC_MAX_PATTERNS = 65536
 
 # every symbol the header declares (checked by the ABI test)
+OASM_CKPT_MAGIC = 0x4D53414F  # a stream checkpoint's first word ("OASM")
+OASM_CKPT_VERSION = 1
+
 EXPORTED = [
     "oasm_config_init",
     "oasm_create",
@@ -67,6 +70,8 @@ EXPORTED = [
     "oasm_levcalc",
     "oasm_levcalc_size",
     "oasm_levcalc_noalloc",
+    "oasm_stream_export",
+    "oasm_stream_import",
 ]
 
 
@@ -158,6 +163,10 @@ def _load():
     lib.oasm_levcalc_size.restype = i32
     lib.oasm_status_str.argtypes = [i32]
     lib.oasm_status_str.restype = ctypes.c_char_p
+    lib.oasm_stream_export.argtypes = [P, u64, P, sz, ctypes.POINTER(sz)]
+    lib.oasm_stream_export.restype = i32
+    lib.oasm_stream_import.argtypes = [P, u64, P, sz]
+    lib.oasm_stream_import.restype = i32
     return lib
 
 
@@ -258,6 +267,21 @@ def oasm_serve(ctx, segs: np.ndarray, pool_ptr: int, pool_bytes: int, want_laten
                                lat.ctypes.data_as(ctypes.c_void_p) if lat is not None and lat.size else None,
                                ctypes.byref(rep)))
     return {name: getattr(rep, name) for name, _ in oasm_serve_report._fields_}, lat
+
+
+def oasm_stream_export(ctx, stream_id: int) -> bytes:
+    """A stream's checkpoint (after matching every byte fed so far)."""
+    size = ctypes.c_size_t(0)
+    _check(ctx, lib.oasm_stream_export(ctx, stream_id, None, 0, ctypes.byref(size)))
+    buf = ctypes.create_string_buffer(max(size.value, 1))
+    _check(ctx, lib.oasm_stream_export(ctx, stream_id, buf, size.value, ctypes.byref(size)))
+    return buf.raw[: size.value]
+
+
+def oasm_stream_import(ctx, stream_id: int, blob: bytes):
+    """Make `stream_id` a live stream of `ctx` holding a checkpoint's state."""
+    blob = bytes(blob)
+    _check(ctx, lib.oasm_stream_import(ctx, stream_id, blob, len(blob)))
 
 
 def oasm_levcalc_size(ctx, n: int) -> int:
@@ -405,6 +429,14 @@ class Matcher:
         hs = torch.cuda.current_stream(text.device).cuda_stream
         oasm_levcalc(self.ctx, text.data_ptr() if n else None, n, out.data_ptr(), out.numel(), hs)
         return out[:need]
+
+    def export_stream(self, stream_id: int) -> bytes:
+        """Checkpoint of a live stream (matches every byte fed so far first)."""
+        return oasm_stream_export(self.ctx, stream_id)
+
+    def import_stream(self, stream_id: int, blob: bytes):
+        """Resume a checkpointed stream under `stream_id` (same dictionary)."""
+        oasm_stream_import(self.ctx, stream_id, blob)
 
     def stats(self) -> dict:
         return oasm_get_stats(self.ctx)

@@ -153,3 +153,24 @@ def test_serve_writes_the_report_on_errors(lib):
                                ctypes.c_void_p, ctypes.POINTER(oasm.oasm_serve_report)]
     assert lib.oasm_serve(None, None, 0, None, 0, None, ctypes.byref(rep)) == oasm.OASM_E_INVAL
     assert (rep.segments, rep.bytes, rep.steps) == (0, 0, 0)
+
+
+def test_checkpoint_calls_reject_null_context(lib):
+    """The checkpoint entry points refuse a NULL context without touching a
+    device (OASM_E_INVAL = -1)."""
+    size = ctypes.c_size_t(7)
+    lib.oasm_stream_export.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_size_t)]
+    lib.oasm_stream_import.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t]
+    assert lib.oasm_stream_export(None, 1, None, 0, ctypes.byref(size)) == -1
+    assert lib.oasm_stream_import(None, 1, None, 0) == -1
+
+
+def test_checkpoint_constants_match_the_header():
+    from paper_1712_03560_amd import oasm
+
+    text = open(HEADER).read()
+    magic = int(re.search(r"#define OASM_CKPT_MAGIC (0x[0-9A-Fa-f]+)u", text).group(1), 16)
+    version = int(re.search(r"#define OASM_CKPT_VERSION (\d+)u", text).group(1))
+    assert (magic, version) == (oasm.OASM_CKPT_MAGIC, oasm.OASM_CKPT_VERSION)
+    assert magic.to_bytes(4, "little") == b"OASM"
