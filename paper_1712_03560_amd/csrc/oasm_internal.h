@@ -148,11 +148,20 @@ bool scan_variant_exists(int W, int P, bool cut);
 // stable radix sort on the key, then a gather into the per-record arrays.
 hipError_t launch_place_carry(const CarryRec *carry, uint32_t ncarry, const uint32_t *slot_to_local, uint32_t npat,
                               uint32_t *key, uint32_t *val, uint64_t *end, hipStream_t st);
-hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
-                              uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
-                              const uint32_t *item_cnt, const uint32_t *item_off, uint32_t item_base, uint32_t cap,
-                              uint32_t base, uint32_t cap_n, uint32_t npat, uint32_t *key, uint32_t *val,
-                              uint64_t *end, hipStream_t st);
+// The scan items of every word-count class (items chunk-major inside a
+// class, the classes one after another), for one compaction launch.
+constexpr int kMaxClasses = 8;
+static_assert(kMaxClasses >= kMaxW32, "one class per word count");
+struct ClassItems {
+    uint32_t n;                        // classes
+    uint32_t tile_first[kMaxClasses];  // the class's first tile
+    uint32_t ntiles[kMaxClasses];
+    uint32_t item_base[kMaxClasses];   // the class's first item
+};
+hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, const ClassItems &cls,
+                              const uint32_t *slot_pat, const uint32_t *item_rec, const uint32_t *item_cnt,
+                              const uint32_t *item_off, uint32_t cap, uint32_t base, uint32_t cap_n, uint32_t npat,
+                              uint32_t *key, uint32_t *val, uint64_t *end, hipStream_t st);
 size_t sort_tmp_words(uint32_t cap);
 hipError_t launch_radix_sort(uint32_t *key, uint32_t *val, uint32_t *key2, uint32_t *val2, DevN n,
                              uint32_t key_bits, uint32_t *tmp, hipStream_t st, bool &result_in_second);

@@ -219,25 +219,28 @@ __global__ void k_place_carry(const CarryRec *__restrict__ carry, uint32_t n, co
 
 // One wavefront per scan item: its records go to base + item_off[item].
 __global__ void __launch_bounds__(256) k_compact_raw(const ChunkDesc *__restrict__ chunks, uint32_t nchunks,
-                                                     const TileDesc *__restrict__ tiles, uint32_t tile_first,
-                                                     uint32_t ntiles, const uint32_t *__restrict__ slot_pat,
+                                                     const TileDesc *__restrict__ tiles, ClassItems cls,
+                                                     const uint32_t *__restrict__ slot_pat,
                                                      const uint32_t *__restrict__ item_rec,
                                                      const uint32_t *__restrict__ item_cnt,
-                                                     const uint32_t *__restrict__ item_off, uint32_t item_base,
+                                                     const uint32_t *__restrict__ item_off, uint32_t nitems,
                                                      uint32_t cap, uint32_t base, uint32_t cap_n, uint32_t npat,
                                                      uint32_t *__restrict__ key, uint32_t *__restrict__ val,
                                                      uint64_t *__restrict__ end) {
     const uint32_t lane = lane_id();
     const uint32_t wave = uniform(threadIdx.x >> 6);
-    const uint32_t local = uniform(blockIdx.x * 4 + wave);
-    if (local >= nchunks * ntiles) return;
+    const uint32_t item = uniform(blockIdx.x * 4 + wave);
+    if (item >= nitems) return;
+    uint32_t c = 0;  // the item's class (wave-uniform)
+    for (uint32_t k = 1; k < cls.n; ++k)
+        if (item >= cls.item_base[k]) c = k;
+    const uint32_t ntiles = cls.ntiles[c], local = item - cls.item_base[c];
     const uint32_t chunk = local / ntiles, tile_local = local % ntiles;
-    const uint32_t item = item_base + local;
     uint32_t n = item_cnt[item];
     if (n > cap) n = cap;
-    if (n == 0) return;
+    if (n == 0 || chunk >= nchunks) return;
     const ChunkDesc cd = chunks[chunk];
-    const TileDesc td = tiles[tile_first + tile_local];
+    const TileDesc td = tiles[cls.tile_first[c] + tile_local];
     const uint32_t *rec = item_rec + (size_t)item * cap;
     const uint32_t dst0 = base + item_off[item];
     const uint32_t kbase = cd.stream_local * npat;
@@ -259,16 +262,16 @@ hipError_t launch_place_carry(const CarryRec *carry, uint32_t ncarry, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, uint32_t tile_first,
-                              uint32_t ntiles, const uint32_t *slot_pat, const uint32_t *item_rec,
-                              const uint32_t *item_cnt, const uint32_t *item_off, uint32_t item_base, uint32_t cap,
-                              uint32_t base, uint32_t cap_n, uint32_t npat, uint32_t *key, uint32_t *val,
-                              uint64_t *end, hipStream_t st) {
-    const uint64_t items = (uint64_t)nchunks * ntiles;
+hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const TileDesc *tiles, const ClassItems &cls,
+                              const uint32_t *slot_pat, const uint32_t *item_rec, const uint32_t *item_cnt,
+                              const uint32_t *item_off, uint32_t cap, uint32_t base, uint32_t cap_n, uint32_t npat,
+                              uint32_t *key, uint32_t *val, uint64_t *end, hipStream_t st) {
+    if (cls.n == 0 || cls.n > (uint32_t)kMaxClasses) return cls.n == 0 ? hipSuccess : hipErrorInvalidValue;
+    const uint64_t items = cls.item_base[cls.n - 1] + (uint64_t)nchunks * cls.ntiles[cls.n - 1];
     if (items == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_compact_raw, dim3((uint32_t)((items + 3) / 4)), dim3(256), 0, st, chunks, nchunks, tiles,
-                       tile_first, ntiles, slot_pat, item_rec, item_cnt, item_off, item_base, cap, base, cap_n, npat,
-                       key, val, end);
+    if (items > UINT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_compact_raw, dim3((uint32_t)((items + 3) / 4)), dim3(256), 0, st, chunks, nchunks, tiles, cls,
+                       slot_pat, item_rec, item_cnt, item_off, (uint32_t)items, cap, base, cap_n, npat, key, val, end);
     return hipGetLastError();
 }
 
@@ -785,7 +788,7 @@ __device__ uint32_t filter_walk(Recs &R, uint32_t i, uint32_t j1, uint32_t p, ui
 // hit ends owned by one k_filter wavefront: few while the step's records
 // fill the chip with room to spare, more when there are millions of them
 // (each block stages its own and the kShortSeg after them)
-constexpr uint32_t kFilterRecsFew = 16, kFilterRecsMany = 64;
+constexpr uint32_t kFilterRecsFew = 8, kFilterRecsMany = 64;
 constexpr uint32_t kFilterManyCap = 1u << 19;  // record capacities above this use kFilterRecsMany
 
 // The same records through the block's window in LDS.
@@ -1570,7 +1573,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_apply(const uint32_t *__r
 // the values' prefixes written back through LDS (coalesced), and the round's
 // total carried into the next.
 constexpr uint32_t kSmallThreads = 1024, kSmallPer = 8, kSmallRound = kSmallThreads * kSmallPer;
-constexpr uint32_t kSmallMax = 4 * kSmallRound;  // larger arrays take the three-pass scan
+constexpr uint32_t kSmallMax = 16 * kSmallRound;  // larger arrays take the three-pass scan
 
 // LDS index of value i of a round, padded so that the threads' runs of
 // kSmallPer values start in different banks.

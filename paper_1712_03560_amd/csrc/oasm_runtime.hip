@@ -534,15 +534,18 @@ void step_enqueue(oasm_ctx *c, StepRun &r) {
         ck(launch_place_carry(d_carry, std::min(ncarry, cap_n), d_s2l, c->npat, key0, val0, c->sort_end.as<uint64_t>(),
                               st),
            "place carry");
-        uint32_t item_base = 0;
+        ClassItems cls{};
         for (const ClassInfo &ci : c->classes) {
-            ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), ci.tile_first, ci.ntiles,
-                                  c->d_slot_pat.as<uint32_t>(), c->item_rec.as<uint32_t>(), c->item_cnt.as<uint32_t>(),
-                                  c->offsets.as<uint32_t>(), item_base, c->cap, ncarry, cap_n, c->npat, key0, val0,
-                                  c->sort_end.as<uint64_t>(), st),
-               "compact hit ends");
-            item_base += nchunks * ci.ntiles;
+            if (cls.n == (uint32_t)kMaxClasses) throw HipFail{hipErrorInvalidValue, "more word-count classes than 8"};
+            cls.tile_first[cls.n] = ci.tile_first;
+            cls.ntiles[cls.n] = ci.ntiles;
+            cls.item_base[cls.n] = cls.n ? cls.item_base[cls.n - 1] + nchunks * cls.ntiles[cls.n - 1] : 0u;
+            ++cls.n;
         }
+        ck(launch_compact_raw(d_chunks, nchunks, c->d_tiles.as<TileDesc>(), cls, c->d_slot_pat.as<uint32_t>(),
+                              c->item_rec.as<uint32_t>(), c->item_cnt.as<uint32_t>(), c->offsets.as<uint32_t>(),
+                              c->cap, ncarry, cap_n, c->npat, key0, val0, c->sort_end.as<uint64_t>(), st),
+           "compact hit ends");
         bool second = false;
         ck(launch_radix_sort(key0, val0, key1, val1, dn, key_bits, c->sort_tmp.as<uint32_t>(), st, second),
            "radix sort");
