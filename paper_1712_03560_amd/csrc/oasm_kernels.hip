@@ -278,11 +278,15 @@ hipError_t launch_compact_raw(const ChunkDesc *chunks, uint32_t nchunks, const T
 // Stable LSD radix sort of (key, val) pairs, 8 bits per pass.  Pass =
 // per-block digit histograms (digit-major, so one exclusive scan yields every
 // block's output base per digit) and a stable scatter: each block walks its
-// tile in rounds of 256 elements; inside a wavefront the rank among equal
-// digits comes from eight ballots, across the block's four wavefronts from
-// per-wave digit counts in LDS.
-constexpr uint32_t kSortThreads = 256;
-constexpr uint32_t kSortRounds = 8;
+// tile in rounds of 1024 elements; inside a wavefront the rank among equal
+// digits comes from eight ballots, across the block's sixteen wavefronts
+// from per-wave digit counts in LDS, turned into per-wave offsets once per
+// round.  (Blocks of 1024 threads take a 2048-element tile in two rounds:
+// with steps of a few thousand records a pass is one round trip of a few
+// blocks, so fewer, wider rounds shorten it.)
+constexpr uint32_t kSortThreads = 1024;
+constexpr uint32_t kSortWaves = kSortThreads / kWave;
+constexpr uint32_t kSortRounds = 2;
 constexpr uint32_t kSortTile = kSortThreads * kSortRounds;
 
 __global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t *__restrict__ key, DevN dn,
@@ -290,15 +294,16 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_hist(const uint32_t *__re
                                                             uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[256];
     const uint32_t n = dev_n(dn);
-    h[threadIdx.x] = 0;
+    const uint32_t t = threadIdx.x;
+    if (t < 256) h[t] = 0;
     __syncthreads();
     const uint32_t b0 = blockIdx.x * kSortTile;
     for (uint32_t r = 0; r < kSortRounds; ++r) {
-        const uint32_t i = b0 + r * kSortThreads + threadIdx.x;
+        const uint32_t i = b0 + r * kSortThreads + t;
         if (i < n) atomicAdd(&h[(key[i] >> shift) & 0xFFu], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    if (t < 256) hist[t * nblocks + blockIdx.x] = h[t];
 }
 
 __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t *__restrict__ kin,
@@ -308,14 +313,15 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t *_
                                                                uint32_t *__restrict__ kout,
                                                                uint32_t *__restrict__ vout) {
     __shared__ uint32_t base[256];
+    __shared__ uint32_t tot[256];
+    __shared__ uint32_t wc[kSortWaves][256];  // per-wave digit counts, then per-wave offsets
     const uint32_t n = dev_n(dn);
-    __shared__ uint32_t wc[4][256];
     const uint32_t t = threadIdx.x, wave = t >> 6;
-    base[t] = offs[t * nblocks + blockIdx.x];
-    wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
-    __syncthreads();
+    if (t < 256) base[t] = offs[t * nblocks + blockIdx.x];
     const uint32_t b0 = blockIdx.x * kSortTile;
     for (uint32_t r = 0; r < kSortRounds; ++r) {
+        for (uint32_t x = t; x < kSortWaves * 256; x += kSortThreads) (&wc[0][0])[x] = 0;
+        __syncthreads();
         const uint32_t i = b0 + r * kSortThreads + t;
         const bool valid = i < n;
         const uint32_t k = valid ? kin[i] : 0u;
@@ -332,16 +338,23 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_scatter(const uint32_t *_
         const uint32_t group = (uint32_t)__popcll(same);
         if (valid && rank == group - 1) wc[wave][d] = group;
         __syncthreads();
+        if (t < 256) {  // digit t: the offset of each wavefront's run, and the round's total
+            uint32_t run = 0;
+            for (uint32_t w = 0; w < kSortWaves; ++w) {
+                const uint32_t c = wc[w][t];
+                wc[w][t] = run;
+                run += c;
+            }
+            tot[t] = run;
+        }
+        __syncthreads();
         if (valid) {
-            uint32_t o = base[d] + rank;
-            for (uint32_t w = 0; w < wave; ++w) o += wc[w][d];
+            const uint32_t o = base[d] + wc[wave][d] + rank;
             kout[o] = k;
             vout[o] = v;
         }
         __syncthreads();
-        base[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
-        wc[0][t] = wc[1][t] = wc[2][t] = wc[3][t] = 0;
-        __syncthreads();
+        if (t < 256) base[t] += tot[t];
     }
 }
 
