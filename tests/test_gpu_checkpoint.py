@@ -183,3 +183,49 @@ def test_invalid_checkpoints_are_refused():
     finally:
         m.destroy()
         other.destroy()
+
+
+def test_resume_at_full_size_equals_one_context():
+    """The 64 MiB stream of 256 patterns (10,000 planted copies, so that
+    open segments cross the cut) matched by two contexts, the second
+    resuming the first's checkpoint, reports what one context reports for
+    the whole stream (which the full-size parity tests compare with the
+    oracle)."""
+    w = W.long_stream()
+    text = w.streams[0]
+    # the cut falls one byte before the end of a planted copy near the middle,
+    # so that the copy's hit ends straddle it and its segment is carried
+    mid = min(w.plants, key=lambda pl: abs(pl.site - text.size // 2))
+    cut = mid.site + mid.length - 1
+    say(f"64 MiB stream, 256 patterns, cut at {cut}")
+    dt = torch.from_numpy(text).cuda()
+
+    def feed(m, sid, lo, hi, last):
+        m.feed(sid, dt[lo:hi], last=last)
+
+    whole = oasm.Matcher(w.patterns, w.ks)
+    try:
+        feed(whole, 3, 0, text.size, True)
+        whole.sync()
+        one = whole.results()
+    finally:
+        whole.destroy()
+    a = oasm.Matcher(w.patterns, w.ks)
+    b = oasm.Matcher(w.patterns, w.ks)
+    try:
+        feed(a, 3, 0, cut, False)
+        blob = a.export_stream(3)
+        first = a.results()
+        b.import_stream(3, blob)
+        feed(b, 3, cut, text.size, True)
+        b.sync()
+        second = b.results()
+    finally:
+        a.destroy()
+        b.destroy()
+    assert header(blob)[5] > 0  # hit ends were carried across the cut
+    both = concat([first, second])
+    for f in ("raw", "occ"):
+        x = np.sort(getattr(both, f), order=["pattern", "stream"], kind="stable")
+        y = np.sort(getattr(one, f), order=["pattern", "stream"], kind="stable")
+        assert x.size == y.size and np.array_equal(x, y), f
